@@ -1,0 +1,101 @@
+"""Pins the oracle's Panther++ steps (Sec. 3.3, Algorithm 2): the feature
+vectors theta(v) and the exact Euclidean k-nearest-neighbour search."""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+
+def test_features_vs_sorted_counts(oracle, ba1k, ba1k_paths):
+    paths, inv_ptr, inv_pid = ba1k_paths
+    R = paths.shape[0]
+    D = 50
+    theta = oracle.features(ba1k.n, paths, inv_ptr, inv_pid, D)
+    for v in range(0, ba1k.n, 29):
+        c = oracle.counts_dense(ba1k.n, paths, inv_ptr, inv_pid, v).astype(np.int64)
+        c[v] = 0
+        top = np.sort(c)[::-1][:D]
+        want = (top.astype(np.float32) / np.float32(R)).astype(np.float32)
+        assert (theta[v] == want).all()
+        assert (np.diff(theta[v]) <= 0).all()
+
+
+def test_features_zero_rows_for_unvisited(oracle, inputs):
+    g = inputs.graph_from_edges(6, [(0, 1), (1, 2), (2, 0)], [1, 2, 3])
+    paths = oracle.walk(g, 5, 1000, seed=1)
+    inv_ptr, inv_pid = oracle.index(g.n, paths)
+    th = oracle.features(g.n, paths, inv_ptr, inv_pid, 4)
+    assert (th[3:] == 0).all()
+    assert (th[0, :2] > 0).all() and (th[0, 2:] == 0).all()  # two others only
+
+
+def _exact_knn(theta, q, k):
+    n, D = theta.shape
+    rows = [[Fraction(float(x)) for x in theta[v]] for v in range(n)]
+    d2 = []
+    for v in range(n):
+        if v == q:
+            continue
+        d2.append((sum((a - b) ** 2 for a, b in zip(rows[q], rows[v])), v))
+    d2.sort()
+    return d2[:k]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_knn_vs_exact_rationals(oracle, seed):
+    rng = np.random.default_rng(seed)
+    n, D, k = 60, 7, 9
+    theta = (rng.integers(0, 40, (n, D)) / 1000.0).astype(np.float32)
+    theta = -np.sort(-theta, axis=1)
+    theta[5] = theta[9]  # identical rows -> exact ties broken by id
+    theta[11] = theta[9]
+    theta[20:23] = 0.0
+    qs = np.array([0, 9, 20, 33], np.int32)
+    ids, dist = oracle.knn(theta, qs, k)
+    for i, q in enumerate(qs):
+        want = _exact_knn(theta, int(q), k)
+        wd = np.array([math.sqrt(float(d)) for d, _ in want])
+        assert np.allclose(dist[i], wd, rtol=1e-12, atol=0)
+        # ids agree wherever the exact distance separates neighbours
+        for j, (d, v) in enumerate(want):
+            others = [dd for dd, _ in want if dd != d]
+            assert ids[i, j] == v or any(abs(float(d - dd)) < 1e-12 for dd in others)
+    # identical rows: query 9 sees 5 and 11 at distance 0, in id order
+    assert ids[1, 0] == 5 and ids[1, 1] == 11 and dist[1, 0] == 0.0
+    # zero rows: query 20 sees 21, 22 first
+    assert ids[2, 0] == 21 and ids[2, 1] == 22
+
+
+def test_knn_padding(oracle):
+    theta = np.ones((3, 4), np.float32)
+    ids, dist = oracle.knn(theta, np.array([1], np.int32), 5)
+    assert ids[0].tolist() == [0, 2, -1, -1, -1]
+    assert np.isinf(dist[0, 2:]).all() and (dist[0, :2] == 0).all()
+
+
+def test_dist2_is_fma_chain(oracle):
+    """Squared distance of float32 rows in double, one fma per coordinate:
+    exact for values whose differences square without rounding."""
+    a = np.array([0.5, 0.25, 3.0], np.float32)
+    b = np.array([0.0, 0.75, 1.0], np.float32)
+    assert oracle.dist2(a, b) == 0.25 + 0.25 + 4.0
+
+
+def test_sample_size_closed_forms(oracle):
+    """Theorem 1 with Lemma 1: R = c/eps^2 (log2 C(T,2) + 1 + ln 1/delta)."""
+    e = math.exp(1.0)
+    # T = 2: C(2,2) = 1 -> log term vanishes; delta = 1/e -> ln term is 1
+    assert oracle.sample_size(0.01, 1.0, 1 / e, 2) in (20000, 20001)
+    # T = 3: C(3,2) = 3; c = 0.5, delta = 0.1, eps = 0.1
+    want = 0.5 / 0.01 * (math.log2(3) + 1 + math.log(10))
+    assert oracle.sample_size(0.1, 0.5, 0.1, 3) == math.ceil(want)
+    # the paper's setting (c=0.5, delta=0.1, T=5, eps=sqrt(1/|E|)) gives
+    # R ~= 3.3123 |E| (Section 3.4 parameters)
+    for E in (10_000, 1_000_000):
+        assert abs(oracle.sample_size(math.sqrt(1 / E), 0.5, 0.1, 5) / E - 3.3123) < 1e-3
+    # quartering eps^2 quadruples R
+    a = oracle.sample_size(0.02, 0.5, 0.1, 5)
+    b = oracle.sample_size(0.01, 0.5, 0.1, 5)
+    assert abs(b - 4 * a) <= 4
+    assert oracle.sample_size(0.1, 0.5, 0.1, 1) < 0  # C(1,2) = 0: undefined
