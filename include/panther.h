@@ -1,0 +1,185 @@
+/*
+ * panther.h -- C ABI of the MI355X (gfx950) Panther library.
+ *
+ * Panther (Zhang, Tang, Ma, Tong, Jing, Li; KDD 2015, arXiv:1504.02577)
+ * estimates the similarity of two vertices of an undirected weighted graph
+ * as the fraction of R sampled random T-paths that contain both (Sec. 3.1,
+ * Eq. 4), and answers top-k similarity queries (Problem 1) from a
+ * vertex-to-path inverted index (Algorithm 1).  Panther++ (Sec. 3.3,
+ * Algorithm 2) describes each vertex by its D largest similarities and
+ * answers queries by Euclidean nearest neighbours of those vectors.
+ *
+ * Conventions for every call:
+ *   - Return value: PANTHER_OK (0) or a negative PANTHER_E* code; the
+ *     message of the last failure is panther_last_error(ctx).
+ *   - Validation happens before anything is written: a failed call leaves
+ *     every output buffer untouched and the context usable.
+ *   - Inputs are copied; the caller keeps ownership of all its buffers.
+ *     Outputs are caller-allocated.  `mem` says whether caller pointers
+ *     are host (PANTHER_MEM_HOST) or device (PANTHER_MEM_DEVICE) memory
+ *     on the context's GPU.
+ *   - `stream` is a hipStream_t (NULL = the context's own stream).  With
+ *     device outputs the call returns once the work is queued on `stream`;
+ *     with host outputs it returns when the results are in place.
+ *   - A context serves one host thread at a time.  Calls on different
+ *     streams are ordered: each waits (on the device) for the previous
+ *     call's work, since they share the context's scratch memory.
+ *
+ * Random bits: Philox4x32-10 (Salmon et al., SC 2011) with key
+ * (seed mod 2^32, seed >> 32) and counter (step, 0, pid mod 2^32, pid >> 32);
+ * the 64-bit word of a draw is x0 | x1 << 32.  Step 0 picks the start
+ * vertex, step t >= 1 the t-th transition.
+ */
+#ifndef PANTHER_H_
+#define PANTHER_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct panther_ctx panther_ctx;
+
+enum {
+  PANTHER_OK = 0,
+  PANTHER_EINVAL = -1,  /* malformed argument or graph */
+  PANTHER_ESTATE = -2,  /* call made before its prerequisite */
+  PANTHER_ENOMEM = -3,  /* device allocation failed (context still usable) */
+  PANTHER_ERANGE = -4,  /* a query id outside [0, n) */
+  PANTHER_EDEVICE = -5  /* a HIP runtime error */
+};
+
+enum { PANTHER_MEM_HOST = 0, PANTHER_MEM_DEVICE = 1 };
+
+/* load_graph flags */
+#define PANTHER_START_ALL_VERTICES 1u /* start uniformly over all of V */
+
+/* values of the "topk.form" option */
+#define PANTHER_FORM_PLAIN 0   /* one query per kernel launch */
+#define PANTHER_FORM_BATCHED 1 /* all queries in one persistent launch */
+/* values of the "pp.form" option */
+#define PANTHER_PP_FP64 0      /* brute-force FP64 distances */
+#define PANTHER_PP_BF16 1      /* BF16 MFMA candidate pool, FP64 rerank */
+
+/* Creates a context on GPU `device_ordinal`.  *out receives the handle.
+ * Errors: EINVAL (bad ordinal / NULL out), EDEVICE. */
+int panther_create(int device_ordinal, panther_ctx **out);
+
+/* Frees every device buffer of the context.  NULL is ignored. */
+void panther_destroy(panther_ctx *ctx);
+
+/* Message of the last failed call; owned by the context, valid until the
+ * next call on it.  Never NULL. */
+const char *panther_last_error(const panther_ctx *ctx);
+
+/* Loads G = (V, E, W) (Sec. 2, Definition 1) as CSR with n vertices and m
+ * stored entries: row_ptr int32[n+1] (row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = m), col int32[m] (in [0, n)), w uint32[m] (edge weights;
+ * zero allowed, never sampled).  An undirected edge is stored in both
+ * rows.  Prepares the transition step of Eq. 3: per-row inclusive weight
+ * prefixes and the start set {v : sum of row weights > 0} (or all of V
+ * with PANTHER_START_ALL_VERTICES, where a walk on a weightless vertex
+ * stays put).  Replaces any previous graph and drops paths, index and
+ * features.
+ * Errors: EINVAL (n < 1, m < 0, m >= 2^31, malformed CSR, empty start
+ * set, row weight sum >= 2^63), ENOMEM, EDEVICE. */
+int panther_load_graph(panther_ctx *ctx, int32_t n, int64_t m,
+                       const int32_t *row_ptr, const int32_t *col,
+                       const uint32_t *w, int mem, uint32_t flags);
+
+/* GenerateRandomPath (Algorithm 3): samples R paths of T transitions
+ * (T+1 vertices each) and builds the vertex-to-path inverted index
+ * P_v = ascending ids of the paths that contain v (each path once).
+ * Path pid starts at start_set[floor(r0 * |start_set| / 2^64)]; step t
+ * moves from v along the first CSR entry e of v's row whose inclusive
+ * weight prefix exceeds floor(r_t * W_v / 2^64), W_v the row's weight sum.
+ * Drops features.
+ * Errors: ESTATE (no graph), EINVAL (T < 1 or T > 63, R < 1 or R >= 2^32),
+ * ENOMEM, EDEVICE. */
+int panther_sample_paths(panther_ctx *ctx, int32_t T, int64_t R,
+                         uint64_t seed);
+
+/* Panther top-k query (Algorithm 1, Eq. 4).  For each queries[i] = q:
+ * c(q, v) = number of sampled paths containing both q and v; returns the
+ * min(k, #{v != q : c > 0}) vertices of largest c, ordered by (c
+ * descending, id ascending).  S_RP(q, v) = c / R.
+ * Layout: out_ids int32[nq][k] (padded with -1), out_counts uint32[nq][k]
+ * (padded with 0), out_len int32[nq].  The form (plain or batched) is the
+ * "topk.form" option; both give identical results.
+ * Errors: ESTATE (no paths), EINVAL (k < 1 or k > 1024, nq < 0, NULL
+ * buffers), ERANGE (a query outside [0, n)), ENOMEM, EDEVICE. */
+int panther_topk_similar(panther_ctx *ctx, const int32_t *queries, int64_t nq,
+                         int32_t k, int32_t *out_ids, uint32_t *out_counts,
+                         int32_t *out_len, int mem, void *stream);
+
+/* Panther++ query (Sec. 3.3, Algorithm 2).  theta(v) = the D largest
+ * similarities c(v, u) / R over u != v, in single precision, descending,
+ * zero-padded (computed once per (paths, D) and kept).  For each query q
+ * returns the k vertices v != q nearest to q in Euclidean distance of
+ * theta (S_RP++ = 1 / distance), ordered by (squared distance ascending,
+ * id ascending); the squared distance is accumulated in double precision
+ * with one fused multiply-add per coordinate in coordinate order.
+ * Layout: out_ids int32[nq][k] (padded with -1), out_dist fp64[nq][k]
+ * Euclidean distances (padded with +inf).  The "pp.form" option selects
+ * FP64 brute force or the BF16 candidate pool + FP64 rerank.
+ * Errors: ESTATE (no paths), EINVAL (D < 1 or D > 256, k < 1 or k > 256,
+ * nq < 0), ERANGE, ENOMEM, EDEVICE. */
+int panther_pp_topk(panther_ctx *ctx, const int32_t *queries, int64_t nq,
+                    int32_t D, int32_t k, int32_t *out_ids, double *out_dist,
+                    int mem, void *stream);
+
+/* Sample size of Sec. 3.2 (Theorem 1 with Lemma 1's VC bound):
+ * R = ceil(c / eps^2 * (log2 C(T,2) + 1 + ln(1/delta))).
+ * Returns PANTHER_EINVAL unless 0 < eps < 1, 0 < delta < 1, c > 0, T >= 2. */
+int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
+
+/* Integer options: "topk.form" (PANTHER_FORM_*; default BATCHED),
+ * "pp.form" (PANTHER_PP_*; default BF16), "pp.pool" (candidate pool per
+ * query of the BF16 form, 32..1024, default 256), "autotune" (0/1,
+ * default 1), "timing" (0/1, default 0; see panther_stage_times),
+ * "test.fail_alloc_after" (the next n device allocations
+ * succeed, the one after fails with ENOMEM; -1 disables).
+ * Errors: EINVAL (unknown key or value out of range). */
+int panther_set_option(panther_ctx *ctx, const char *key, int64_t value);
+
+/* Copies the sampled paths, row-major int32[R][T+1]. ESTATE without paths. */
+int panther_get_paths(panther_ctx *ctx, int32_t *out, int mem);
+
+/* Number of (vertex, path) entries of the inverted index, or ESTATE. */
+int64_t panther_index_nnz(const panther_ctx *ctx);
+
+/* Copies the inverted index: inv_ptr int64[n+1], inv_pid uint32[nnz]
+ * (P_v = inv_pid[inv_ptr[v] .. inv_ptr[v+1]), ascending). */
+int panther_get_index(panther_ctx *ctx, int64_t *inv_ptr, uint32_t *inv_pid,
+                      int mem);
+
+/* Computes (if needed) and copies theta, fp32[n][D]. */
+int panther_get_features(panther_ctx *ctx, int32_t D, float *out, int mem);
+
+/* Statistics of the last BF16-form panther_pp_topk call: for each query,
+ * how many returned ids the pool stage had ranked within the first k
+ * before the rerank (*mean_pre_recall, in [0,1]) and the largest relative
+ * error |d~ - d| / max(d, tiny) of the BF16 squared distance over the
+ * returned neighbours (*max_rel_err).  ESTATE if no such call. */
+int panther_pp_stats(panther_ctx *ctx, double *max_rel_err,
+                     double *mean_pre_recall);
+
+/* Device time of the stages of the most recent calls, in milliseconds,
+ * measured with HIP events on the stream each stage ran on, when the
+ * option "timing" is 1 (default 0): out_ms[0] the walk kernel of the last
+ * panther_sample_paths, [1] its index build, [2] the kernels of the last
+ * panther_topk_similar, [3] the feature kernels of the last theta build,
+ * [4] the distance/selection kernels of the last panther_pp_topk.  Stages
+ * not run since timing was enabled read as -1.  ESTATE when timing is off. */
+int panther_stage_times(panther_ctx *ctx, double out_ms[5]);
+
+/* Blocks until all work queued on the context's stream is done. */
+int panther_synchronize(panther_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PANTHER_H_ */

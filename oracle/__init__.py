@@ -55,6 +55,7 @@ def lib():
         L.or_pick_edge.argtypes = [P, P, P, i32, u64]
         L.or_pick_edge.restype = i64
         L.or_walk.argtypes = [i32, i64, P, P, P, i32, i64, u64, ctypes.c_int, P]
+        L.or_walk_pids.argtypes = [i32, i64, P, P, P, i32, u64, ctypes.c_int, P, i64, P]
         L.or_index_ptr.argtypes = [i32, i32, i64, P, P]
         L.or_index_ptr.restype = i64
         L.or_index_fill.argtypes = [i32, i32, i64, P, P, P]
@@ -138,6 +139,17 @@ def walk(g, T: int, R: int, seed: int, start_all: bool = False) -> np.ndarray:
     _check(lib().or_walk(g.n, g.m, _p(rp), _p(col), _p(w), T, R, seed,
                          int(start_all), _p(paths)), "walk")
     return paths
+
+
+def walk_pids(g, T: int, seed: int, pids, start_all: bool = False) -> np.ndarray:
+    rp = _c(g.row_ptr, np.int32)
+    col = _c(g.col, np.int32)
+    w = _c(g.w, np.uint32)
+    p = _c(pids, np.int64)
+    out = np.zeros((p.shape[0], T + 1), np.int32)
+    _check(lib().or_walk_pids(g.n, g.m, _p(rp), _p(col), _p(w), T, seed, int(start_all),
+                              _p(p), p.shape[0], _p(out)), "walk_pids")
+    return out
 
 
 def index(n: int, paths: np.ndarray):

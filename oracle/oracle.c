@@ -423,3 +423,34 @@ int64_t or_sample_size(double eps, double c, double delta, int32_t T) {
   double r = c / (eps * eps) * (log2(pairs) + 1.0 + log(1.0 / delta));
   return (int64_t)ceil(r);
 }
+
+/* Paths of selected ids only (same draws as or_walk), for spot checks of
+ * runs too large to replay whole. out is int32[npids][T+1]. */
+int or_walk_pids(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                 const uint32_t *w, int32_t T, uint64_t seed, int start_all,
+                 const int64_t *pids, int64_t npids, int32_t *out) {
+  if (T < 1) return OR_EINVAL;
+  uint64_t *W = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+  uint64_t *pfx = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+  int32_t *starts = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!W || !pfx || !starts) {
+    free(W); free(pfx); free(starts);
+    return OR_ENOMEM;
+  }
+  or_row_weights(n, row_ptr, w, W);
+  or_row_prefix(n, row_ptr, w, pfx);
+  int32_t ns = or_start_set(n, W, start_all, starts);
+  for (int64_t i = 0; i < npids && ns > 0; ++i) {
+    uint64_t pid = (uint64_t)pids[i];
+    int32_t *p = out + i * (int64_t)(T + 1);
+    int32_t v = starts[or_scale(or_draw(seed, pid, 0u), (uint64_t)ns)];
+    p[0] = v;
+    for (int32_t t = 1; t <= T; ++t) {
+      int64_t e = or_pick_edge(row_ptr, pfx, W, v, or_draw(seed, pid, (uint32_t)t));
+      if (e >= 0) v = col[e];
+      p[t] = v;
+    }
+  }
+  free(W); free(pfx); free(starts);
+  return ns > 0 ? OR_OK : OR_EINVAL;
+}

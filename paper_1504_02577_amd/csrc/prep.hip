@@ -1,0 +1,248 @@
+// Graph preparation (Eq. 3's transition step): CSR validation, per-row
+// weight sums W_v, the start set {v : W_v > 0}, and per-row inclusive weight
+// prefixes, plus the device-wide exclusive scan used here and by the index.
+#include "common.h"
+#include "kernels.h"
+
+namespace panther {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void __launch_bounds__(kBlock)
+k_validate(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t n,
+           int64_t m, uint32_t* err) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gsz = (int64_t)gridDim.x * kBlock;
+  uint32_t e = 0;
+  for (int64_t v = gid; v < n; v += gsz)
+    if (row_ptr[v + 1] < row_ptr[v]) e |= 1u;
+  for (int64_t i = gid; i < m; i += gsz) {
+    const int32_t c = col[i];
+    if (c < 0 || c >= n) e |= 2u;
+  }
+  if (e) atomicOr(err, e);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_rowsum(const int32_t* __restrict__ row_ptr, const uint32_t* __restrict__ w, int32_t n,
+         VRec* __restrict__ vrec, unsigned long long* max_w, int32_t* big_rows,
+         uint32_t* n_big) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  uint64_t s = 0;
+  if (v < n) {
+    const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+    if (b - a > 256) {
+      big_rows[atomicAdd(n_big, 1u)] = v;
+      vrec[v] = VRec{a, b - a, 0u, 0u};
+    } else {
+      for (int32_t e = a; e < b; ++e) s += w[e];
+      vrec[v] = VRec{a, b - a, (uint32_t)s, (uint32_t)(s >> 32)};
+    }
+  }
+  s = wave_max(s);
+  if ((threadIdx.x & (kWave - 1)) == 0 && s) atomicMax(max_w, (unsigned long long)s);
+}
+
+// one wave per long row
+__global__ void __launch_bounds__(kBlock)
+k_rowsum_big(const int32_t* __restrict__ big_rows, uint32_t n_big, const uint32_t* __restrict__ w,
+             VRec* __restrict__ vrec, unsigned long long* max_w) {
+  const uint32_t r = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (r >= n_big) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t v = big_rows[r];
+  const VRec rec = vrec[v];
+  uint64_t s = 0;
+  for (int32_t e = rec.start + lane; e < rec.start + rec.deg; e += kWave) s += w[e];
+  s = wave_sum(s);
+  if (lane == 0) {
+    vrec[v].w_lo = (uint32_t)s;
+    vrec[v].w_hi = (uint32_t)(s >> 32);
+    atomicMax(max_w, (unsigned long long)s);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_start_flags(const VRec* __restrict__ vrec, int32_t n, int start_all, uint32_t* flags) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  const VRec r = vrec[v];
+  flags[v] = (start_all || (r.w_lo | r.w_hi)) ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_start_scatter(const uint32_t* __restrict__ flags, const uint64_t* __restrict__ pos, int32_t n,
+                int32_t* __restrict__ vstart) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v < n && flags[v]) vstart[pos[v]] = v;
+}
+
+// Short rows: one thread per row.  Long rows: one wave per row with a
+// running carry across 64-entry chunks.
+template <typename P>
+__global__ void __launch_bounds__(kBlock)
+k_prefix_small(const VRec* __restrict__ vrec, const uint32_t* __restrict__ w, int32_t n,
+               P* __restrict__ pfx) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  const VRec r = vrec[v];
+  if (r.deg > 256) return;
+  uint64_t s = 0;
+  for (int32_t e = r.start; e < r.start + r.deg; ++e) {
+    s += w[e];
+    pfx[e] = (P)s;
+  }
+}
+
+template <typename P>
+__global__ void __launch_bounds__(kBlock)
+k_prefix_big(const VRec* __restrict__ vrec, const uint32_t* __restrict__ w,
+             const int32_t* __restrict__ big_rows, uint32_t n_big, P* __restrict__ pfx) {
+  const uint32_t r = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (r >= n_big) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const VRec rec = vrec[big_rows[r]];
+  uint64_t carry = 0;
+  for (int32_t base = rec.start; base < rec.start + rec.deg; base += kWave) {
+    const int32_t e = base + lane;
+    const uint64_t x = e < rec.start + rec.deg ? (uint64_t)w[e] : 0ull;
+    const uint64_t inc = wave_inclusive_sum(x);
+    if (e < rec.start + rec.deg) pfx[e] = (P)(carry + inc);
+    carry += __shfl(inc, kWave - 1, kWave);
+  }
+}
+
+// ---- device-wide exclusive scan (reduce tiles, scan tile sums, apply) ----
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint64_t* __restrict__ tile_sums) {
+  __shared__ uint64_t red[kBlock / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  uint64_t s = 0;
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
+    if (idx < n) s += in[idx];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t t = 0;
+    for (int i = 0; i < kBlock / kWave; ++i) t += red[i];
+    tile_sums[blockIdx.x] = t;
+  }
+}
+
+// single block: exclusive scan of the tile sums in place; total at [ntiles]
+__global__ void __launch_bounds__(1024) k_scan_tiles(uint64_t* tile_sums, int64_t ntiles) {
+  __shared__ uint64_t s[1024 / kWave + 1];
+  uint64_t carry = 0;
+  for (int64_t base = 0; base < ntiles; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    const uint64_t x = i < ntiles ? tile_sums[i] : 0ull;
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_sum<1024>(x, s, &tot);
+    if (i < ntiles) tile_sums[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) tile_sums[ntiles] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint64_t* __restrict__ tile_sums,
+             uint64_t* __restrict__ out) {
+  __shared__ uint64_t s[kBlock / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint64_t x[kScanItems];
+  uint64_t loc = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    x[i] = idx < n ? (uint64_t)in[idx] : 0ull;
+    loc += x[i];
+  }
+  uint64_t tot;
+  uint64_t run = tile_sums[blockIdx.x] + block_exclusive_sum<kBlock>(loc, s, &tot);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const int64_t idx = base + i;
+    if (idx < n) out[idx] = run;
+    run += x[i];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = tile_sums[gridDim.x];
+}
+
+inline unsigned grid_for(int64_t work, int per_block, unsigned cap = 1u << 30) {
+  int64_t g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > (int64_t)cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+void launch_validate(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
+                     uint32_t* err, hipStream_t s) {
+  const int64_t work = m > n ? m : n;
+  k_validate<<<grid_for(work, kBlock * 8, 65536), kBlock, 0, s>>>(row_ptr, col, n, m, err);
+}
+
+void launch_rowsum(const int32_t* row_ptr, const uint32_t* w, int32_t n, VRec* vrec,
+                   uint64_t* max_w, int32_t* big_rows, uint32_t* n_big, hipStream_t s) {
+  k_rowsum<<<grid_for(n, kBlock), kBlock, 0, s>>>(row_ptr, w, n, vrec,
+                                                  (unsigned long long*)max_w, big_rows, n_big);
+}
+
+void launch_rowsum_big(const int32_t* big_rows, uint32_t n_big, const uint32_t* w, VRec* vrec,
+                       uint64_t* max_w, hipStream_t s) {
+  if (!n_big) return;
+  k_rowsum_big<<<grid_for(n_big, kBlock / kWave), kBlock, 0, s>>>(
+      big_rows, n_big, w, vrec, (unsigned long long*)max_w);
+}
+
+void launch_start_flags(const VRec* vrec, int32_t n, int start_all, uint32_t* flags,
+                        hipStream_t s) {
+  k_start_flags<<<grid_for(n, kBlock), kBlock, 0, s>>>(vrec, n, start_all, flags);
+}
+
+void launch_start_scatter(const uint32_t* flags, const uint64_t* pos, int32_t n, int32_t* vstart,
+                          hipStream_t s) {
+  k_start_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(flags, pos, n, vstart);
+}
+
+void launch_prefix32(const VRec* vrec, const uint32_t* w, int32_t n, const int32_t* big_rows,
+                     uint32_t n_big, uint32_t* pfx, hipStream_t s) {
+  k_prefix_small<uint32_t><<<grid_for(n, kBlock), kBlock, 0, s>>>(vrec, w, n, pfx);
+  if (n_big)
+    k_prefix_big<uint32_t><<<grid_for(n_big, kBlock / kWave), kBlock, 0, s>>>(vrec, w, big_rows,
+                                                                            n_big, pfx);
+}
+
+void launch_prefix64(const VRec* vrec, const uint32_t* w, int32_t n, const int32_t* big_rows,
+                     uint32_t n_big, uint64_t* pfx, hipStream_t s) {
+  k_prefix_small<uint64_t><<<grid_for(n, kBlock), kBlock, 0, s>>>(vrec, w, n, pfx);
+  if (n_big)
+    k_prefix_big<uint64_t><<<grid_for(n_big, kBlock / kWave), kBlock, 0, s>>>(vrec, w, big_rows,
+                                                                            n_big, pfx);
+}
+
+size_t scan_temp_bytes(int64_t n) {
+  const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  return sizeof(uint64_t) * (size_t)(tiles + 2);
+}
+
+void launch_scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, void* temp,
+                            hipStream_t s) {
+  int64_t tiles = (n + kScanTile - 1) / kScanTile;
+  if (tiles < 1) tiles = 1;
+  uint64_t* ts = static_cast<uint64_t*>(temp);
+  k_scan_reduce<<<(unsigned)tiles, kBlock, 0, s>>>(in, n, ts);
+  k_scan_tiles<<<1, 1024, 0, s>>>(ts, tiles);
+  k_scan_apply<<<(unsigned)tiles, kBlock, 0, s>>>(in, n, ts, out);
+}
+
+}  // namespace panther

@@ -1,0 +1,89 @@
+// Host runtime state of a Panther context (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+struct BatchState;
+struct PPState;
+
+struct panther_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int num_cus = 256;
+  int lds_per_block = 65536;
+  // options
+  int topk_form = 1;  // PANTHER_FORM_BATCHED
+  int pp_form = 1;    // PANTHER_PP_BF16
+  int pp_pool = 256;
+  int autotune = 1;
+  int64_t fail_alloc_after = -1;
+  // graph
+  bool has_graph = false;
+  int32_t n = 0;
+  int64_t m = 0;
+  int32_t* d_col = nullptr;
+  panther::VRec* d_vrec = nullptr;
+  void* d_pfx = nullptr;
+  bool pfx64 = false;
+  int32_t* d_vstart = nullptr;
+  int32_t nstart = 0;
+  uint64_t max_w = 0;
+  // paths + index
+  bool has_paths = false;
+  int32_t T = 0;
+  int64_t R = 0;
+  uint64_t seed = 0;
+  int stride = 0;
+  int32_t* d_paths = nullptr;
+  uint64_t* d_inv_ptr = nullptr;
+  uint32_t* d_inv_pid = nullptr;
+  int64_t nnz = 0;
+  std::vector<uint64_t> h_inv_ptr;
+  // dense query scratch (plain form, hub queries)
+  uint32_t* d_cnt = nullptr;
+  int32_t* d_touched = nullptr;
+  uint32_t* d_ctl = nullptr;
+  // batched form
+  BatchState* batch = nullptr;
+  // calls on different streams share the scratch above: each call waits
+  // for the previous one's completion event before using it
+  hipEvent_t order_ev = nullptr;
+  bool order_pending = false;
+  // stage timing (option "timing")
+  int timing = 0;
+  hipEvent_t ev[10] = {};
+  bool ev_used[5] = {};
+  // Panther++
+  float* d_theta = nullptr;
+  int32_t theta_D = 0;
+  PPState* pp = nullptr;
+};
+
+int ctx_fail(panther_ctx* c, int code, const char* fmt, ...);
+int ctx_hip(panther_ctx* c, hipError_t e, const char* what);
+int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what);
+void ctx_free(void* p);
+// Stage timing: stage i is bracketed by events 2i and 2i+1.
+void stage_begin(panther_ctx* c, int stage, hipStream_t s);
+void stage_end(panther_ctx* c, int stage, hipStream_t s);
+int order_begin(panther_ctx* c, hipStream_t s);
+int order_end(panther_ctx* c, hipStream_t s);
+int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, hipStream_t s,
+                  std::vector<int32_t>& hq, const int32_t** dq, void** dq_owned);
+
+// batched form (batch.hip)
+int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<int32_t>& hq,
+                     int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
+                     hipStream_t s);
+int set_batch_option(panther_ctx* c, const std::string& key, int64_t value);
+void free_batch_state(panther_ctx* c);
+
+// Panther++ (pp.hip)
+void free_pp_state(panther_ctx* c);

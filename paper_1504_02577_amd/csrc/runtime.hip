@@ -1,0 +1,688 @@
+// C ABI and host runtime of the Panther library: context, device memory,
+// argument validation, and the sequencing of the kernels of each call.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/panther.h"
+#include "common.h"
+#include "kernels.h"
+#include "runtime.h"
+
+using namespace panther;
+
+// ---------------------------------------------------------------------------
+// errors and allocation
+// ---------------------------------------------------------------------------
+int ctx_fail(panther_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+int ctx_hip(panther_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return PANTHER_OK;
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    return ctx_fail(c, PANTHER_ENOMEM, "%s: out of device memory", what);
+  }
+  return ctx_fail(c, PANTHER_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (c->fail_alloc_after >= 0) {
+    if (c->fail_alloc_after == 0)
+      return ctx_fail(c, PANTHER_ENOMEM, "%s: allocation failure injected", what);
+    --c->fail_alloc_after;
+  }
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return ctx_fail(c, PANTHER_ENOMEM, "%s: cannot allocate %zu bytes", what, bytes);
+  }
+  return PANTHER_OK;
+}
+
+void ctx_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+#define TRY(expr)                   \
+  do {                              \
+    int _st = (expr);               \
+    if (_st != PANTHER_OK) return _st; \
+  } while (0)
+#define HIPTRY(expr, what) TRY(ctx_hip(c, (expr), what))
+
+static void free_features(panther_ctx* c) {
+  ctx_free(c->d_theta);
+  c->d_theta = nullptr;
+  c->theta_D = 0;
+  free_pp_state(c);
+}
+
+static void free_paths(panther_ctx* c) {
+  free_features(c);
+  free_batch_state(c);
+  ctx_free(c->d_paths);
+  ctx_free(c->d_inv_ptr);
+  ctx_free(c->d_inv_pid);
+  ctx_free(c->d_cnt);
+  ctx_free(c->d_touched);
+  ctx_free(c->d_ctl);
+  c->d_paths = nullptr;
+  c->d_inv_ptr = nullptr;
+  c->d_inv_pid = nullptr;
+  c->d_cnt = nullptr;
+  c->d_touched = nullptr;
+  c->d_ctl = nullptr;
+  c->h_inv_ptr.clear();
+  c->has_paths = false;
+  c->nnz = 0;
+}
+
+static void free_graph(panther_ctx* c) {
+  free_paths(c);
+  ctx_free(c->d_col);
+  ctx_free(c->d_vrec);
+  ctx_free(c->d_pfx);
+  ctx_free(c->d_vstart);
+  c->d_col = nullptr;
+  c->d_vrec = nullptr;
+  c->d_pfx = nullptr;
+  c->d_vstart = nullptr;
+  c->has_graph = false;
+}
+
+// RAII holder for temporaries of a call
+struct Temp {
+  std::vector<void*> ptrs;
+  ~Temp() {
+    for (void* p : ptrs) ctx_free(p);
+  }
+  void* add(void* p) {
+    ptrs.push_back(p);
+    return p;
+  }
+};
+
+void stage_begin(panther_ctx* c, int stage, hipStream_t s) {
+  if (!c->timing) return;
+  if (!c->ev[0]) {
+    for (int i = 0; i < 10; ++i) (void)hipEventCreate(&c->ev[i]);
+  }
+  (void)hipEventRecord(c->ev[2 * stage], s);
+}
+
+void stage_end(panther_ctx* c, int stage, hipStream_t s) {
+  if (!c->timing) return;
+  (void)hipEventRecord(c->ev[2 * stage + 1], s);
+  c->ev_used[stage] = true;
+}
+
+extern "C" int panther_stage_times(panther_ctx* c, double* out_ms) {
+  if (!c || !out_ms) return PANTHER_EINVAL;
+  if (!c->timing) return ctx_fail(c, PANTHER_ESTATE, "timing option is off");
+  for (int i = 0; i < 5; ++i) {
+    out_ms[i] = -1.0;
+    if (!c->ev_used[i]) continue;
+    float ms = 0.f;
+    if (hipEventSynchronize(c->ev[2 * i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, c->ev[2 * i], c->ev[2 * i + 1]) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    out_ms[i] = ms;
+  }
+  return PANTHER_OK;
+}
+
+int order_begin(panther_ctx* c, hipStream_t s) {
+  if (!c->order_ev) {
+    HIPTRY(hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming), "order event");
+  }
+  if (c->order_pending) HIPTRY(hipStreamWaitEvent(s, c->order_ev, 0), "order wait");
+  return PANTHER_OK;
+}
+
+int order_end(panther_ctx* c, hipStream_t s) {
+  HIPTRY(hipEventRecord(c->order_ev, s), "order record");
+  c->order_pending = true;
+  return PANTHER_OK;
+}
+
+static hipStream_t pick_stream(panther_ctx* c, void* s) {
+  return s ? static_cast<hipStream_t>(s) : c->stream;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy / errors / options
+// ---------------------------------------------------------------------------
+extern "C" int panther_create(int device_ordinal, panther_ctx** out) {
+  if (!out) return PANTHER_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device_ordinal < 0 || device_ordinal >= ndev) {
+    (void)hipGetLastError();
+    return PANTHER_EINVAL;
+  }
+  if (hipSetDevice(device_ordinal) != hipSuccess) return PANTHER_EDEVICE;
+  panther_ctx* c = new panther_ctx();
+  c->device = device_ordinal;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    delete c;
+    return PANTHER_EDEVICE;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device_ordinal) == hipSuccess) {
+    c->num_cus = prop.multiProcessorCount;
+    c->lds_per_block = (int)prop.sharedMemPerBlock;
+  }
+  *out = c;
+  return PANTHER_OK;
+}
+
+extern "C" void panther_destroy(panther_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  free_graph(c);
+  for (int i = 0; i < 10; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->order_ev) (void)hipEventDestroy(c->order_ev);
+  (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" const char* panther_last_error(const panther_ctx* c) {
+  return c ? c->err.c_str() : "null context";
+}
+
+extern "C" int panther_set_option(panther_ctx* c, const char* key, int64_t value) {
+  if (!c || !key) return PANTHER_EINVAL;
+  std::string k(key);
+  if (k == "topk.form") {
+    if (value != PANTHER_FORM_PLAIN && value != PANTHER_FORM_BATCHED)
+      return ctx_fail(c, PANTHER_EINVAL, "topk.form must be 0 (plain) or 1 (batched)");
+    c->topk_form = (int)value;
+  } else if (k == "pp.form") {
+    if (value != PANTHER_PP_FP64 && value != PANTHER_PP_BF16)
+      return ctx_fail(c, PANTHER_EINVAL, "pp.form must be 0 (fp64) or 1 (bf16)");
+    c->pp_form = (int)value;
+  } else if (k == "pp.pool") {
+    if (value < 32 || value > 1024)
+      return ctx_fail(c, PANTHER_EINVAL, "pp.pool must lie in [32, 1024]");
+    c->pp_pool = (int)value;
+  } else if (k == "autotune") {
+    if (value != 0 && value != 1) return ctx_fail(c, PANTHER_EINVAL, "autotune must be 0 or 1");
+    c->autotune = (int)value;
+  } else if (k == "timing") {
+    if (value != 0 && value != 1) return ctx_fail(c, PANTHER_EINVAL, "timing must be 0 or 1");
+    c->timing = (int)value;
+    for (int i = 0; i < 5; ++i) c->ev_used[i] = false;
+  } else if (k == "test.fail_alloc_after") {
+    c->fail_alloc_after = value < 0 ? -1 : value;
+  } else if (k == "batch.tier_a" || k == "batch.tier_b" || k == "batch.block") {
+    return set_batch_option(c, k, value);
+  } else {
+    return ctx_fail(c, PANTHER_EINVAL, "unknown option '%s'", key);
+  }
+  return PANTHER_OK;
+}
+
+extern "C" int64_t panther_sample_size(double eps, double cc, double delta, int32_t T) {
+  if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0) || !(cc > 0.0) || T < 2)
+    return PANTHER_EINVAL;
+  const double pairs = 0.5 * (double)T * (double)(T - 1);
+  const double r = cc / (eps * eps) * (std::log2(pairs) + 1.0 + std::log(1.0 / delta));
+  return (int64_t)std::ceil(r);
+}
+
+extern "C" int panther_synchronize(panther_ctx* c) {
+  if (!c) return PANTHER_EINVAL;
+  return ctx_hip(c, hipStreamSynchronize(c->stream), "synchronize");
+}
+
+// ---------------------------------------------------------------------------
+// load_graph (a1): validate, W_v, start set, per-row prefixes
+// ---------------------------------------------------------------------------
+extern "C" int panther_load_graph(panther_ctx* c, int32_t n, int64_t m, const int32_t* row_ptr,
+                                  const int32_t* col, const uint32_t* w, int mem,
+                                  uint32_t flags) {
+  if (!c) return PANTHER_EINVAL;
+  c->err.clear();
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, PANTHER_EDEVICE, "hipSetDevice");
+  if (n < 1) return ctx_fail(c, PANTHER_EINVAL, "n must be >= 1");
+  if (m < 0 || m >= (int64_t(1) << 31))
+    return ctx_fail(c, PANTHER_EINVAL, "m must lie in [0, 2^31)");
+  if (!row_ptr || (m > 0 && (!col || !w)))
+    return ctx_fail(c, PANTHER_EINVAL, "null CSR pointer");
+  if (mem != PANTHER_MEM_HOST && mem != PANTHER_MEM_DEVICE)
+    return ctx_fail(c, PANTHER_EINVAL, "mem must be PANTHER_MEM_HOST or PANTHER_MEM_DEVICE");
+  if (flags & ~PANTHER_START_ALL_VERTICES) return ctx_fail(c, PANTHER_EINVAL, "unknown flags");
+  hipStream_t s = c->stream;
+  int32_t ends[2];
+  if (mem == PANTHER_MEM_HOST) {
+    ends[0] = row_ptr[0];
+    ends[1] = row_ptr[n];
+  } else {
+    HIPTRY(hipMemcpyAsync(&ends[0], row_ptr, 4, hipMemcpyDeviceToHost, s), "load_graph");
+    HIPTRY(hipMemcpyAsync(&ends[1], row_ptr + n, 4, hipMemcpyDeviceToHost, s), "load_graph");
+    HIPTRY(hipStreamSynchronize(s), "load_graph");
+  }
+  if (ends[0] != 0 || (int64_t)ends[1] != m)
+    return ctx_fail(c, PANTHER_EINVAL, "row_ptr must start at 0 and end at m");
+
+  free_graph(c);
+  Temp tmp;
+  const int32_t* d_rp = row_ptr;
+  const uint32_t* d_w = w;
+  int32_t* d_col = nullptr;
+  void* p;
+  TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)m, "graph columns"));
+  d_col = static_cast<int32_t*>(p);
+  c->d_col = d_col;
+  if (mem == PANTHER_MEM_HOST) {
+    TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)(n + 1), "row_ptr staging"));
+    tmp.add(p);
+    HIPTRY(hipMemcpyAsync(p, row_ptr, sizeof(int32_t) * (size_t)(n + 1), hipMemcpyHostToDevice, s),
+           "row_ptr upload");
+    d_rp = static_cast<const int32_t*>(p);
+    TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)m, "weight staging"));
+    tmp.add(p);
+    if (m)
+      HIPTRY(hipMemcpyAsync(p, w, sizeof(uint32_t) * (size_t)m, hipMemcpyHostToDevice, s),
+             "weight upload");
+    d_w = static_cast<const uint32_t*>(p);
+    if (m)
+      HIPTRY(hipMemcpyAsync(d_col, col, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s),
+             "column upload");
+  } else if (m) {
+    HIPTRY(hipMemcpyAsync(d_col, col, sizeof(int32_t) * (size_t)m, hipMemcpyDeviceToDevice, s),
+           "column copy");
+  }
+  // small control block: [0] error bits, [1] n_big, [2..3] max W (u64)
+  TRY(ctx_alloc(c, &p, 64, "control"));
+  tmp.add(p);
+  uint32_t* ctl = static_cast<uint32_t*>(p);
+  HIPTRY(hipMemsetAsync(ctl, 0, 64, s), "control clear");
+  launch_validate(d_rp, d_col, n, m, ctl, s);
+  HIPTRY(hipGetLastError(), "validate");
+  uint32_t hctl[4];
+  HIPTRY(hipMemcpyAsync(hctl, ctl, 16, hipMemcpyDeviceToHost, s), "validate");
+  HIPTRY(hipStreamSynchronize(s), "validate");
+  if (hctl[0] & 1u) {
+    free_graph(c);
+    return ctx_fail(c, PANTHER_EINVAL, "row_ptr decreases");
+  }
+  if (hctl[0] & 2u) {
+    free_graph(c);
+    return ctx_fail(c, PANTHER_EINVAL, "column id out of range");
+  }
+  TRY(ctx_alloc(c, &p, sizeof(VRec) * (size_t)n, "vertex records"));
+  c->d_vrec = static_cast<VRec*>(p);
+  TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)n, "long-row list"));
+  tmp.add(p);
+  int32_t* big = static_cast<int32_t*>(p);
+  launch_rowsum(d_rp, d_w, n, c->d_vrec, reinterpret_cast<uint64_t*>(ctl + 2), big, ctl + 1, s);
+  HIPTRY(hipGetLastError(), "rowsum");
+  HIPTRY(hipMemcpyAsync(hctl, ctl, 16, hipMemcpyDeviceToHost, s), "rowsum");
+  HIPTRY(hipStreamSynchronize(s), "rowsum");
+  const uint32_t n_big = hctl[1];
+  launch_rowsum_big(big, n_big, d_w, c->d_vrec, reinterpret_cast<uint64_t*>(ctl + 2), s);
+  HIPTRY(hipGetLastError(), "rowsum_big");
+  HIPTRY(hipMemcpyAsync(hctl, ctl, 16, hipMemcpyDeviceToHost, s), "rowsum");
+  HIPTRY(hipStreamSynchronize(s), "rowsum");
+  const uint64_t max_w = (uint64_t)hctl[2] | ((uint64_t)hctl[3] << 32);
+  if (max_w >= (uint64_t(1) << 63)) {
+    free_graph(c);
+    return ctx_fail(c, PANTHER_EINVAL, "row weight sum exceeds 2^63");
+  }
+  // start set
+  const int start_all = (flags & PANTHER_START_ALL_VERTICES) ? 1 : 0;
+  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)n, "start flags"));
+  tmp.add(p);
+  uint32_t* sflags = static_cast<uint32_t*>(p);
+  TRY(ctx_alloc(c, &p, sizeof(uint64_t) * (size_t)(n + 1), "start positions"));
+  tmp.add(p);
+  uint64_t* spos = static_cast<uint64_t*>(p);
+  TRY(ctx_alloc(c, &p, scan_temp_bytes(n), "scan temp"));
+  tmp.add(p);
+  void* stemp = p;
+  launch_start_flags(c->d_vrec, n, start_all, sflags, s);
+  launch_scan_u32_to_u64(sflags, spos, n, stemp, s);
+  HIPTRY(hipGetLastError(), "start set");
+  uint64_t nstart = 0;
+  HIPTRY(hipMemcpyAsync(&nstart, spos + n, 8, hipMemcpyDeviceToHost, s), "start set");
+  HIPTRY(hipStreamSynchronize(s), "start set");
+  if (nstart == 0) {
+    free_graph(c);
+    return ctx_fail(c, PANTHER_EINVAL, "no vertex has an edge of positive weight");
+  }
+  TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)nstart, "start set"));
+  c->d_vstart = static_cast<int32_t*>(p);
+  launch_start_scatter(sflags, spos, n, c->d_vstart, s);
+  // prefixes
+  c->pfx64 = max_w >= (uint64_t(1) << 32);
+  TRY(ctx_alloc(c, &p, (c->pfx64 ? 8 : 4) * (size_t)m, "weight prefixes"));
+  c->d_pfx = p;
+  if (c->pfx64)
+    launch_prefix64(c->d_vrec, d_w, n, big, n_big, static_cast<uint64_t*>(c->d_pfx), s);
+  else
+    launch_prefix32(c->d_vrec, d_w, n, big, n_big, static_cast<uint32_t*>(c->d_pfx), s);
+  HIPTRY(hipGetLastError(), "prefix");
+  HIPTRY(hipStreamSynchronize(s), "load_graph");
+  c->n = n;
+  c->m = m;
+  c->nstart = (int32_t)nstart;
+  c->max_w = max_w;
+  c->has_graph = true;
+  return PANTHER_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sample_paths (a2 walk + a3 index)
+// ---------------------------------------------------------------------------
+static int build_index(panther_ctx* c) {
+  hipStream_t s = c->stream;
+  const int32_t n = c->n;
+  const uint64_t R = (uint64_t)c->R;
+  Temp tmp;
+  void* p;
+  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)n, "index counts"));
+  tmp.add(p);
+  uint32_t* cnt = static_cast<uint32_t*>(p);
+  HIPTRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)n, s), "index");
+  launch_index_count(c->stride, c->d_paths, R, cnt, s);
+  HIPTRY(hipGetLastError(), "index count");
+  TRY(ctx_alloc(c, &p, sizeof(uint64_t) * (size_t)(n + 1), "index offsets"));
+  c->d_inv_ptr = static_cast<uint64_t*>(p);
+  TRY(ctx_alloc(c, &p, scan_temp_bytes(n), "scan temp"));
+  tmp.add(p);
+  launch_scan_u32_to_u64(cnt, c->d_inv_ptr, n, p, s);
+  HIPTRY(hipGetLastError(), "index scan");
+  c->h_inv_ptr.resize((size_t)n + 1);
+  HIPTRY(hipMemcpyAsync(c->h_inv_ptr.data(), c->d_inv_ptr, sizeof(uint64_t) * (size_t)(n + 1),
+                        hipMemcpyDeviceToHost, s),
+         "index offsets");
+  HIPTRY(hipStreamSynchronize(s), "index");
+  c->nnz = (int64_t)c->h_inv_ptr[n];
+  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)c->nnz, "index path ids"));
+  c->d_inv_pid = static_cast<uint32_t*>(p);
+  TRY(ctx_alloc(c, &p, sizeof(unsigned long long) * (size_t)n, "index cursors"));
+  tmp.add(p);
+  HIPTRY(hipMemcpyAsync(p, c->d_inv_ptr, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, s),
+         "index cursors");
+  launch_index_scatter(c->stride, c->d_paths, R, static_cast<unsigned long long*>(p),
+                       c->d_inv_pid, s);
+  HIPTRY(hipGetLastError(), "index scatter");
+  // sort each list
+  TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)n * 2 + 64, "list classes"));
+  tmp.add(p);
+  int32_t* mid = static_cast<int32_t*>(p);
+  int32_t* big = mid + n;
+  uint32_t* nctl = reinterpret_cast<uint32_t*>(big + n);
+  HIPTRY(hipMemsetAsync(nctl, 0, 16, s), "index");
+  launch_seg_sort_small(c->d_inv_ptr, n, c->d_inv_pid, mid, nctl, big, nctl + 1, s);
+  HIPTRY(hipGetLastError(), "index sort");
+  uint32_t hn[2];
+  HIPTRY(hipMemcpyAsync(hn, nctl, 8, hipMemcpyDeviceToHost, s), "index sort");
+  HIPTRY(hipStreamSynchronize(s), "index sort");
+  launch_seg_sort_mid(c->d_inv_ptr, mid, hn[0], c->d_inv_pid, s);
+  HIPTRY(hipGetLastError(), "index sort mid");
+  if (hn[1]) {
+    std::vector<int32_t> hbig(hn[1]);
+    HIPTRY(hipMemcpyAsync(hbig.data(), big, 4 * (size_t)hn[1], hipMemcpyDeviceToHost, s),
+           "index sort big");
+    HIPTRY(hipStreamSynchronize(s), "index sort big");
+    std::sort(hbig.begin(), hbig.end());
+    std::vector<SegBlock> blocks;
+    uint64_t maxlen = 0;
+    for (int32_t v : hbig) {
+      const uint64_t a = c->h_inv_ptr[v], len = c->h_inv_ptr[v + 1] - a;
+      maxlen = std::max(maxlen, len);
+      for (uint64_t off = 0; off < len; off += 4096)
+        blocks.push_back(SegBlock{a, (uint32_t)len, (uint32_t)off});
+    }
+    TRY(ctx_alloc(c, &p, sizeof(SegBlock) * blocks.size(), "sort blocks"));
+    tmp.add(p);
+    SegBlock* dblocks = static_cast<SegBlock*>(p);
+    HIPTRY(hipMemcpyAsync(dblocks, blocks.data(), sizeof(SegBlock) * blocks.size(),
+                          hipMemcpyHostToDevice, s),
+           "sort blocks");
+    const uint32_t nb = (uint32_t)blocks.size();
+    launch_seg_chunk_sort(dblocks, nb, c->d_inv_pid, s);
+    HIPTRY(hipGetLastError(), "index chunk sort");
+    TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)c->nnz, "merge buffer"));
+    tmp.add(p);
+    uint32_t* alt = static_cast<uint32_t*>(p);
+    uint32_t* src = c->d_inv_pid;
+    uint32_t* dst = alt;
+    for (uint64_t width = 4096; width < maxlen; width *= 2) {
+      launch_seg_merge(dblocks, nb, (uint32_t)width, src, dst, s);
+      HIPTRY(hipGetLastError(), "index merge");
+      std::swap(src, dst);
+    }
+    if (src != c->d_inv_pid) {
+      launch_seg_copy(dblocks, nb, src, c->d_inv_pid, s);
+      HIPTRY(hipGetLastError(), "index merge copy");
+    }
+    HIPTRY(hipStreamSynchronize(s), "index sort big");
+  }
+  HIPTRY(hipStreamSynchronize(s), "index");
+  return PANTHER_OK;
+}
+
+extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64_t seed) {
+  if (!c) return PANTHER_EINVAL;
+  c->err.clear();
+  if (!c->has_graph) return ctx_fail(c, PANTHER_ESTATE, "sample_paths before load_graph");
+  if (T < 1 || T > 63) return ctx_fail(c, PANTHER_EINVAL, "T must lie in [1, 63]");
+  if (R < 1 || R >= (int64_t(1) << 32)) return ctx_fail(c, PANTHER_EINVAL, "R must lie in [1, 2^32)");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, PANTHER_EDEVICE, "hipSetDevice");
+  free_paths(c);
+  int stride = 4;
+  while (stride < T + 1) stride <<= 1;
+  c->T = T;
+  c->R = R;
+  c->seed = seed;
+  c->stride = stride;
+  void* p;
+  int st = ctx_alloc(c, &p, sizeof(int32_t) * (size_t)R * (size_t)stride, "paths");
+  if (st) return st;
+  c->d_paths = static_cast<int32_t*>(p);
+  stage_begin(c, 0, c->stream);
+  launch_walk(stride, c->pfx64, c->d_vrec, c->d_pfx, c->d_col, c->d_vstart, c->nstart, T,
+              (uint64_t)R, seed, c->d_paths, c->stream);
+  stage_end(c, 0, c->stream);
+  st = ctx_hip(c, hipGetLastError(), "walk");
+  if (!st) {
+    stage_begin(c, 1, c->stream);
+    st = build_index(c);
+    stage_end(c, 1, c->stream);
+  }
+  if (!st) {
+    // dense per-vertex scratch of the query kernels
+    st = ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)c->n, "query counters");
+    if (!st) {
+      c->d_cnt = static_cast<uint32_t*>(p);
+      st = ctx_alloc(c, &p, sizeof(int32_t) * (size_t)c->n, "query touched list");
+    }
+    if (!st) {
+      c->d_touched = static_cast<int32_t*>(p);
+      st = ctx_alloc(c, &p, 64, "query control");
+    }
+    if (!st) {
+      c->d_ctl = static_cast<uint32_t*>(p);
+      st = ctx_hip(c, hipMemsetAsync(c->d_cnt, 0, sizeof(uint32_t) * (size_t)c->n, c->stream),
+                   "query scratch");
+    }
+    if (!st) st = ctx_hip(c, hipMemsetAsync(c->d_ctl, 0, 64, c->stream), "query scratch");
+    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "sample_paths");
+  }
+  if (st) {
+    free_paths(c);
+    return st;
+  }
+  c->has_paths = true;
+  return PANTHER_OK;
+}
+
+// ---------------------------------------------------------------------------
+// accessors
+// ---------------------------------------------------------------------------
+extern "C" int panther_get_paths(panther_ctx* c, int32_t* out, int mem) {
+  if (!c) return PANTHER_EINVAL;
+  c->err.clear();
+  if (!c->has_paths) return ctx_fail(c, PANTHER_ESTATE, "no paths sampled");
+  if (!out) return ctx_fail(c, PANTHER_EINVAL, "null output");
+  const size_t w = sizeof(int32_t) * (size_t)(c->T + 1);
+  HIPTRY(hipMemcpy2DAsync(out, w, c->d_paths, sizeof(int32_t) * (size_t)c->stride, w,
+                          (size_t)c->R,
+                          mem == PANTHER_MEM_DEVICE ? hipMemcpyDeviceToDevice
+                                                    : hipMemcpyDeviceToHost,
+                          c->stream),
+         "get_paths");
+  HIPTRY(hipStreamSynchronize(c->stream), "get_paths");
+  return PANTHER_OK;
+}
+
+extern "C" int64_t panther_index_nnz(const panther_ctx* c) {
+  if (!c) return PANTHER_EINVAL;
+  if (!c->has_paths) return PANTHER_ESTATE;
+  return c->nnz;
+}
+
+extern "C" int panther_get_index(panther_ctx* c, int64_t* inv_ptr, uint32_t* inv_pid, int mem) {
+  if (!c) return PANTHER_EINVAL;
+  c->err.clear();
+  if (!c->has_paths) return ctx_fail(c, PANTHER_ESTATE, "no paths sampled");
+  if (!inv_ptr || (c->nnz && !inv_pid)) return ctx_fail(c, PANTHER_EINVAL, "null output");
+  const hipMemcpyKind kind =
+      mem == PANTHER_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPTRY(hipMemcpyAsync(inv_ptr, c->d_inv_ptr, sizeof(int64_t) * (size_t)(c->n + 1), kind,
+                        c->stream),
+         "get_index");
+  if (c->nnz)
+    HIPTRY(hipMemcpyAsync(inv_pid, c->d_inv_pid, sizeof(uint32_t) * (size_t)c->nnz, kind,
+                          c->stream),
+           "get_index");
+  HIPTRY(hipStreamSynchronize(c->stream), "get_index");
+  return PANTHER_OK;
+}
+
+// ---------------------------------------------------------------------------
+// query validation shared by topk_similar and pp_topk: returns the queries
+// on the host (for range checks and the plain form's launch sizes) and on
+// the device.
+// ---------------------------------------------------------------------------
+int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, hipStream_t s,
+                  std::vector<int32_t>& hq, const int32_t** dq, void** dq_owned) {
+  *dq_owned = nullptr;
+  hq.resize((size_t)nq);
+  if (mem == PANTHER_MEM_HOST) {
+    std::memcpy(hq.data(), queries, sizeof(int32_t) * (size_t)nq);
+  } else {
+    HIPTRY(hipMemcpyAsync(hq.data(), queries, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost,
+                          s),
+           "queries");
+    HIPTRY(hipStreamSynchronize(s), "queries");
+  }
+  for (int64_t i = 0; i < nq; ++i)
+    if (hq[i] < 0 || hq[i] >= c->n)
+      return ctx_fail(c, PANTHER_ERANGE, "query %lld (= %d) outside [0, %d)", (long long)i, hq[i],
+                      c->n);
+  if (mem == PANTHER_MEM_DEVICE) {
+    *dq = queries;
+  } else {
+    void* p;
+    TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)nq, "queries"));
+    *dq_owned = p;
+    HIPTRY(hipMemcpyAsync(p, hq.data(), sizeof(int32_t) * (size_t)nq, hipMemcpyHostToDevice, s),
+           "queries");
+    *dq = static_cast<const int32_t*>(p);
+  }
+  return PANTHER_OK;
+}
+
+// ---------------------------------------------------------------------------
+// topk_similar (a4 + a5; a8 in the batched form)
+// ---------------------------------------------------------------------------
+extern "C" int panther_topk_similar(panther_ctx* c, const int32_t* queries, int64_t nq, int32_t k,
+                                    int32_t* out_ids, uint32_t* out_counts, int32_t* out_len,
+                                    int mem, void* stream) {
+  if (!c) return PANTHER_EINVAL;
+  c->err.clear();
+  if (!c->has_paths) return ctx_fail(c, PANTHER_ESTATE, "topk_similar before sample_paths");
+  if (k < 1 || k > 1024) return ctx_fail(c, PANTHER_EINVAL, "k must lie in [1, 1024]");
+  if (nq < 0) return ctx_fail(c, PANTHER_EINVAL, "nq must be >= 0");
+  if (mem != PANTHER_MEM_HOST && mem != PANTHER_MEM_DEVICE)
+    return ctx_fail(c, PANTHER_EINVAL, "bad mem");
+  if (nq == 0) return PANTHER_OK;
+  if (!queries || !out_ids || !out_counts || !out_len)
+    return ctx_fail(c, PANTHER_EINVAL, "null buffer");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, PANTHER_EDEVICE, "hipSetDevice");
+  hipStream_t s = pick_stream(c, stream);
+  std::vector<int32_t> hq;
+  const int32_t* dq = nullptr;
+  void* owned = nullptr;
+  Temp tmp;
+  int st = stage_queries(c, queries, nq, mem, s, hq, &dq, &owned);
+  if (owned) tmp.add(owned);
+  if (st) return st;
+  int32_t* d_ids = out_ids;
+  uint32_t* d_cnt = out_counts;
+  int32_t* d_len = out_len;
+  if (mem == PANTHER_MEM_HOST) {
+    void* p;
+    TRY(ctx_alloc(c, &p, (sizeof(int32_t) + sizeof(uint32_t)) * (size_t)nq * (size_t)k +
+                             sizeof(int32_t) * (size_t)nq,
+                  "query outputs"));
+    tmp.add(p);
+    d_ids = static_cast<int32_t*>(p);
+    d_cnt = reinterpret_cast<uint32_t*>(d_ids + (size_t)nq * k);
+    d_len = reinterpret_cast<int32_t*>(d_cnt + (size_t)nq * k);
+  }
+  TRY(order_begin(c, s));
+  stage_begin(c, 2, s);
+  if (c->topk_form == PANTHER_FORM_PLAIN) {
+    TopkScratch sc{c->d_cnt, c->d_touched, c->d_ctl};
+    for (int64_t i = 0; i < nq; ++i) {
+      const int32_t q = hq[i];
+      launch_topk_plain(c->stride, q, c->d_inv_ptr, c->d_inv_pid, c->d_paths,
+                        c->h_inv_ptr[q + 1] - c->h_inv_ptr[q], sc, k, d_ids + i * k,
+                        d_cnt + i * k, d_len + i, s);
+    }
+    HIPTRY(hipGetLastError(), "topk plain");
+  } else {
+    TRY(run_topk_batched(c, dq, hq, nq, k, d_ids, d_cnt, d_len, s));
+  }
+  stage_end(c, 2, s);
+  TRY(order_end(c, s));
+  if (mem == PANTHER_MEM_HOST) {
+    HIPTRY(hipMemcpyAsync(out_ids, d_ids, sizeof(int32_t) * (size_t)nq * k, hipMemcpyDeviceToHost,
+                          s),
+           "topk outputs");
+    HIPTRY(hipMemcpyAsync(out_counts, d_cnt, sizeof(uint32_t) * (size_t)nq * k,
+                          hipMemcpyDeviceToHost, s),
+           "topk outputs");
+    HIPTRY(hipMemcpyAsync(out_len, d_len, sizeof(int32_t) * (size_t)nq, hipMemcpyDeviceToHost, s),
+           "topk outputs");
+    HIPTRY(hipStreamSynchronize(s), "topk");
+  } else if (owned) {
+    // the staged query copy is freed on return; make sure it is consumed
+    HIPTRY(hipStreamSynchronize(s), "topk");
+  }
+  return PANTHER_OK;
+}

@@ -1,0 +1,71 @@
+"""The C-ABI library: it loads, exports every symbol the header declares,
+and its host-only helpers behave; no GPU compute here."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "panther.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(panther_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1504_02577_amd import panther
+
+    if not os.path.exists(panther.LIB_PATH):
+        from paper_1504_02577_amd import build
+
+        build.build()
+    return panther.lib()
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    from paper_1504_02577_amd import panther
+
+    assert sorted(panther.EXPORTS) == names
+
+
+def test_sample_size_matches_oracle(L, oracle):
+    for eps, c, d, T in [(0.01, 0.5, 0.1, 5), (0.003, 0.5, 0.1, 5), (0.1, 1.0, 0.5, 2),
+                         (math.sqrt(1 / 5e6), 0.5, 0.1, 5), (0.05, 2.0, 0.01, 10)]:
+        assert L.panther_sample_size(eps, c, d, T) == oracle.sample_size(eps, c, d, T)
+    assert L.panther_sample_size(0.0, 0.5, 0.1, 5) < 0
+    assert L.panther_sample_size(0.1, 0.5, 0.1, 1) < 0
+
+
+def test_null_context_is_rejected(L):
+    assert L.panther_set_option(None, b"topk.form", 0) < 0
+    assert L.panther_sample_paths(None, 5, 10, 1) < 0
+    assert L.panther_last_error(None) == b"null context"
+
+
+def test_create_without_gpu_fails_cleanly(L):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert L.panther_create(0, ctypes.byref(h)) != 0
+    assert not h.value
+
+
+def test_product_path_does_not_import_oracle():
+    pkg = os.path.join(ROOT, "paper_1504_02577_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text, f
