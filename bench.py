@@ -30,20 +30,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def walk_algorithmic_bytes(g, paths, stride_bytes_pfx=4):
-    """Bytes the walk must move per launch: per step a 16-byte vertex record,
-    ceil(log2 deg) prefix probes, one column read; per path the start-set
-    read and the (T+1) written vertices."""
-    deg = np.diff(g.row_ptr.astype(np.int64))
-    probes = np.zeros_like(deg)
-    nz = deg > 1
-    probes[nz] = np.ceil(np.log2(deg[nz])).astype(np.int64)
-    R, T1 = paths.shape
-    total = R * 4 + R * T1 * 4
-    for t in range(T1 - 1):
-        src = paths[:, t]
-        total += int((16 + 4 + stride_bytes_pfx * probes[src]).sum())
-    return total
+def walk_algorithmic_bytes(R, T):
+    """Bytes the guide-table walk must move per launch: per step a 16-byte
+    vertex record, a 4-byte guide entry, one 8-byte {prefix, column} record
+    and the 4-byte vertex written; per path the 4-byte start-set read and
+    the 4-byte start vertex written."""
+    return R * (T * (16 + 4 + 8 + 4) + 8)
 
 
 def cpu_baseline(g, queries, T, k, seed, R_sample):
@@ -69,7 +61,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=0,
+                    help="paths in the oracle sample (0 = the full R of the workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: multi-GPU sharding is designed, not built "
@@ -88,6 +81,10 @@ def main():
         f"(inputs {time.time() - t0:.1f} s)")
 
     dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(0)
+    log(f"device: {props.name} CUs={props.multi_processor_count} "
+        f"mem={props.total_memory / 2**30:.0f} GiB "
+        f"lds/block={getattr(props, 'shared_memory_per_block', '?')}")
     P = Panther(0)
     P.load_graph(g)
     P.set_option("timing", 1)
@@ -136,10 +133,8 @@ def main():
     P.set_option("topk.form", 1)
 
     walk_ms = float(np.mean(stage["walk"]))
-    paths = P.paths()
-    walk_bytes = walk_algorithmic_bytes(g, paths)
+    walk_bytes = walk_algorithmic_bytes(R, T)
     achieved = walk_bytes / (walk_ms * 1e-3) / 1e9
-    del paths
 
     res = {
         "metric": "path-steps/s",
@@ -170,7 +165,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(g, q, T, k, seed, args.cpu_sample)
+        res["cpu_baseline"] = cpu_baseline(g, q, T, k, seed, args.cpu_sample or R)
     P.close()
     print(json.dumps(res), flush=True)
 

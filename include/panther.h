@@ -139,7 +139,10 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * "pp.form" (PANTHER_PP_*; default BF16), "pp.pool" (candidate pool per
  * query of the BF16 form, 32..1024, default 256), "autotune" (0/1,
  * default 1), "timing" (0/1, default 0; see panther_stage_times),
- * "test.fail_alloc_after" (the next n device allocations
+ * "batch.block" (0 = autotuned, 256, 512), "batch.wgs_per_cu" (0 =
+ * autotuned, 1, 2), "batch.tier_a" / "batch.tier_b" (caps on the path-list
+ * length of the wave and work-group tiers of the batched form; -1 = the
+ * LDS-derived default), "test.fail_alloc_after" (the next n device allocations
  * succeed, the one after fails with ENOMEM; -1 disables).
  * Errors: EINVAL (unknown key or value out of range). */
 int panther_set_option(panther_ctx *ctx, const char *key, int64_t value);

@@ -1,27 +1,692 @@
-// Batched form of the Panther query (placeholder: routes through the plain
-// kernels until the persistent kernel lands).
+// Panther query, batched form: every query of a call in one persistent
+// kernel launch (captured in a HIP graph and replayed), with the tile sizes
+// picked by an autotuner.
+//
+// Queries are split by the length L of their path list P_q (known on the
+// host from the index offsets) into three tiers, placed on a device work
+// queue longest-first:
+//   A  (T*L fits half of a per-wave LDS table): one wavefront per query.
+//      Open-addressing hash (vertex -> count) in LDS, then the occupied
+//      slots are compacted to 64-bit ranking keys and bitonic-sorted by the
+//      wave alone (no work-group barrier).
+//   B  (fits half of a work-group LDS table): one work-group per query, LDS
+//      hash, then block selection of the k largest keys.
+//   C  (hubs): one work-group per query with a dense per-vertex counter
+//      array in global memory owned by that work-group, a touched list, and
+//      the same block selection; counters are cleared after use.
+// Counting is exact integer arithmetic and the ranking key (count desc, id
+// asc) is a total order, so the result equals the plain form bit for bit.
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
 #include "../../include/panther.h"
+#include "common.h"
 #include "runtime.h"
 
 using namespace panther;
 
-int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<int32_t>& hq,
-                     int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
-                     hipStream_t s) {
-  (void)dq;
-  TopkScratch sc{c->d_cnt, c->d_touched, c->d_ctl};
-  for (int64_t i = 0; i < nq; ++i) {
-    const int32_t q = hq[i];
-    launch_topk_plain(c->stride, q, c->d_inv_ptr, c->d_inv_pid, c->d_paths,
-                      c->h_inv_ptr[q + 1] - c->h_inv_ptr[q], sc, k, d_ids + i * k,
-                      d_counts + i * k, d_len + i, s);
+namespace {
+
+constexpr int kQueueCtl = 4;  // [0] C head, [1] AB head
+
+struct BatchArgs {
+  const int32_t* queries;  // [nq]
+  const int32_t* itemsC;   // query indices, hubs, longest first
+  const int32_t* itemsB;
+  const int32_t* itemsA;
+  int32_t nC, nB, nA;
+  int32_t hub_wgs;         // work-groups that own a dense slot
+  const uint64_t* inv_ptr;
+  const uint32_t* inv_pid;
+  const int32_t* paths;
+  uint32_t* slot_cnt;      // [hub_wgs][n]
+  int32_t* slot_touched;   // [hub_wgs][n]
+  uint32_t* queue;         // kQueueCtl words
+  int32_t n;
+  int32_t k;
+  int32_t TA, TB;          // table sizes (powers of two)
+  int32_t* out_ids;
+  uint32_t* out_counts;
+  int32_t* out_len;
+};
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t v, uint32_t mask) {
+  return ((uint32_t)v * 0x9E3779B1u >> 7) & mask;
+}
+
+// LDS hash insert (vertex -> +1).  The tier bounds keep the load at most
+// 1/2, so a free slot always exists; the probe count is capped anyway so
+// that no input can make the loop run forever.
+__device__ __forceinline__ void lds_insert(int32_t* keys, uint32_t* vals, uint32_t mask,
+                                           int32_t v) {
+  uint32_t h = hash_slot(v, mask);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const int32_t cur = *((volatile int32_t*)&keys[h]);
+    if (cur == v) {
+      atomicAdd(&vals[h], 1u);
+      return;
+    }
+    if (cur == -1) {
+      const int32_t prev = atomicCAS(&keys[h], -1, v);
+      if (prev == -1 || prev == v) {
+        atomicAdd(&vals[h], 1u);
+        return;
+      }
+    }
+    h = (h + 1) & mask;
   }
-  return ctx_hip(c, hipGetLastError(), "topk batched");
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t ld_agent_u32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Gathers the rows of P_q [a, a+L) with `nthr` threads (thread id `t`),
+// calling f(v) for every distinct vertex v != q of every row.
+template <int S, typename F>
+__device__ __forceinline__ void for_each_candidate(const BatchArgs& A, int32_t q, uint64_t a,
+                                                   uint64_t L, int t, int nthr, F&& f) {
+  for (uint64_t i = t; i < L; i += nthr) {
+    int32_t v[S];
+    load_row<S>(A.paths, A.inv_pid[a + i], v);
+    dedup_row<S>(v);
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      if (v[j] >= 0 && v[j] != q) f(v[j]);
+  }
+}
+
+__device__ __forceinline__ void write_row(const BatchArgs& A, int32_t qi, const uint64_t* keys,
+                                          int m, int t, int nthr) {
+  const int k = A.k;
+  for (int j = t; j < k; j += nthr) {
+    const bool ok = j < m;
+    A.out_ids[(int64_t)qi * k + j] = ok ? key_vertex(keys[j]) : -1;
+    A.out_counts[(int64_t)qi * k + j] = ok ? key_count(keys[j]) : 0u;
+  }
+  if (t == 0) A.out_len[qi] = m;
+}
+
+// ---- tier A: one wavefront per query ----
+template <int S>
+__device__ void wave_query(const BatchArgs& A, int32_t qi, char* region) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int TA = A.TA;
+  int32_t* keys = reinterpret_cast<int32_t*>(region);
+  uint32_t* vals = reinterpret_cast<uint32_t*>(keys + TA);
+  uint64_t* sorted = reinterpret_cast<uint64_t*>(vals + TA);  // TA/2 entries
+  const int32_t q = A.queries[qi];
+  const uint64_t a = A.inv_ptr[q];
+  const uint64_t L = A.inv_ptr[q + 1] - a;
+  for (int j = lane; j < TA; j += kWave) {
+    keys[j] = -1;
+    vals[j] = 0u;
+  }
+  wave_sync();
+  const uint32_t mask = (uint32_t)TA - 1u;
+  for_each_candidate<S>(A, q, a, L, lane, kWave,
+                        [&](int32_t v) { lds_insert(keys, vals, mask, v); });
+  wave_sync();
+  // compact occupied slots into ranking keys
+  int nc = 0;
+  for (int base = 0; base < TA; base += kWave) {
+    const int j = base + lane;
+    const int32_t key = keys[j];
+    const bool occ = key >= 0;
+    const uint64_t bm = __ballot(occ);
+    if (occ) sorted[nc + __popcll(bm & ((1ull << lane) - 1ull))] = rank_key(vals[j], key);
+    nc += __popcll(bm);
+  }
+  int P = 2;
+  while (P < nc) P <<= 1;
+  for (int j = nc + lane; j < P; j += kWave) sorted[j] = 0ull;
+  wave_sync();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (P >> 1); i += kWave) {
+        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool desc = (lo & size) == 0;
+        const uint64_t x = sorted[lo], y = sorted[hi];
+        if ((x < y) == desc) {
+          sorted[lo] = y;
+          sorted[hi] = x;
+        }
+      }
+      wave_sync();
+    }
+  }
+  write_row(A, qi, sorted, nc < A.k ? nc : A.k, lane, kWave);
+  wave_sync();
+}
+
+// ---- tier B: one work-group per query, LDS table ----
+template <int BLOCK, int S>
+__device__ void block_query_lds(const BatchArgs& A, int32_t qi, char* region, SelectSmem& sm,
+                                uint32_t* s_ctl) {
+  const int TB = A.TB;
+  int32_t* keys = reinterpret_cast<int32_t*>(region);
+  uint32_t* vals = reinterpret_cast<uint32_t*>(keys + TB);
+  uint64_t* comp = reinterpret_cast<uint64_t*>(vals + TB);  // TB/2 entries
+  const int32_t q = A.queries[qi];
+  const uint64_t a = A.inv_ptr[q];
+  const uint64_t L = A.inv_ptr[q + 1] - a;
+  for (int j = threadIdx.x; j < TB; j += BLOCK) {
+    keys[j] = -1;
+    vals[j] = 0u;
+  }
+  if (threadIdx.x == 0) s_ctl[0] = 0u;
+  __syncthreads();
+  const uint32_t mask = (uint32_t)TB - 1u;
+  for_each_candidate<S>(A, q, a, L, threadIdx.x, BLOCK,
+                        [&](int32_t v) { lds_insert(keys, vals, mask, v); });
+  __syncthreads();
+  for (int j = threadIdx.x; j < TB; j += BLOCK) {
+    const int32_t key = keys[j];
+    if (key >= 0) comp[atomicAdd(&s_ctl[0], 1u)] = rank_key(vals[j], key);
+  }
+  __syncthreads();
+  const int nc = (int)s_ctl[0];
+  auto keyfn = [&](int i) { return comp[i]; };
+  const int m = block_select_topk<BLOCK>(keyfn, nc, A.k, sm);
+  write_row(A, qi, sm.out, m, threadIdx.x, BLOCK);
+  __syncthreads();
+}
+
+// ---- tier C: one work-group per hub query, dense global counters ----
+template <int BLOCK, int S>
+__device__ void block_query_dense(const BatchArgs& A, int32_t qi, uint32_t* cnt, int32_t* touched,
+                                  SelectSmem& sm, uint32_t* s_ctl) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int32_t q = A.queries[qi];
+  const uint64_t a = A.inv_ptr[q];
+  const uint64_t L = A.inv_ptr[q + 1] - a;
+  if (threadIdx.x == 0) s_ctl[0] = 0u;
+  __syncthreads();
+  for (uint64_t base = 0; base < L; base += BLOCK) {
+    const uint64_t idx = base + threadIdx.x;
+    int32_t v[S];
+    if (idx < L) {
+      load_row<S>(A.paths, A.inv_pid[a + idx], v);
+      dedup_row<S>(v);
+    } else {
+#pragma unroll
+      for (int j = 0; j < S; ++j) v[j] = -1;
+    }
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+      const bool want = v[j] >= 0 && v[j] != q;
+      const uint32_t old = want ? atomicAdd(&cnt[v[j]], 1u) : 1u;
+      const bool fresh = want && old == 0u;
+      const uint64_t bm = __ballot(fresh);
+      if (bm) {
+        uint32_t wbase = 0;
+        if (lane == 0) wbase = atomicAdd(&s_ctl[0], (uint32_t)__popcll(bm));
+        wbase = __shfl(wbase, 0, kWave);
+        if (fresh) touched[wbase + __popcll(bm & ((1ull << lane) - 1ull))] = v[j];
+      }
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  const int nt = (int)s_ctl[0];
+  auto keyfn = [&](int i) {
+    const int32_t v = __hip_atomic_load(&touched[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return rank_key(ld_agent_u32(&cnt[v]), v);
+  };
+  const int m = block_select_topk<BLOCK>(keyfn, nt, A.k, sm);
+  write_row(A, qi, sm.out, m, threadIdx.x, BLOCK);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nt; i += BLOCK)
+    cnt[__hip_atomic_load(&touched[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)] = 0u;
+  __threadfence();
+  __syncthreads();
+}
+
+template <int BLOCK, int S>
+__global__ void __launch_bounds__(BLOCK) k_topk_batched(BatchArgs A) {
+  extern __shared__ __align__(16) char lds[];
+  SelectSmem& sm = *reinterpret_cast<SelectSmem*>(lds);
+  uint32_t* s_ctl = reinterpret_cast<uint32_t*>(lds + sizeof(SelectSmem));
+  char* region = lds + sizeof(SelectSmem) + 64;
+  constexpr int kWaves = BLOCK / kWave;
+  const bool hub = (int)blockIdx.x < A.hub_wgs;
+  bool c_done = !hub;
+  uint32_t* cnt = hub ? A.slot_cnt + (size_t)blockIdx.x * (size_t)A.n : nullptr;
+  int32_t* touched = hub ? A.slot_touched + (size_t)blockIdx.x * (size_t)A.n : nullptr;
+  const int nAgroups = (A.nA + kWaves - 1) / kWaves;
+  while (true) {
+    if (threadIdx.x == 0) {
+      int item = -1;  // encoded: [0, nC) C, [nC, nC+nB) B, then A groups
+      if (!c_done) {
+        const uint32_t x = atomicAdd(&A.queue[0], 1u);
+        if ((int)x < A.nC)
+          item = (int)x;
+        else
+          c_done = true;
+      }
+      if (item < 0) {
+        const uint32_t x = atomicAdd(&A.queue[1], 1u);
+        if ((int)x < A.nB + nAgroups) item = A.nC + (int)x;
+      }
+      s_ctl[1] = (uint32_t)item;
+      s_ctl[2] = c_done ? 1u : 0u;
+    }
+    __syncthreads();
+    const int item = (int)s_ctl[1];
+    c_done = s_ctl[2] != 0u;
+    __syncthreads();
+    if (item < 0) break;
+    if (item < A.nC) {
+      block_query_dense<BLOCK, S>(A, A.itemsC[item], cnt, touched, sm, s_ctl + 4);
+    } else if (item < A.nC + A.nB) {
+      block_query_lds<BLOCK, S>(A, A.itemsB[item - A.nC], region, sm, s_ctl + 4);
+    } else {
+      const int g = item - A.nC - A.nB;
+      const int w = threadIdx.x / kWave;
+      const int ai = g * kWaves + w;
+      if (ai < A.nA)
+        wave_query<S>(A, A.itemsA[ai], region + (size_t)w * (size_t)A.TA * 12);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_reset_queue(uint32_t* q) {
+  if (threadIdx.x < kQueueCtl) q[threadIdx.x] = 0u;
+}
+
+using KernelFn = void (*)(BatchArgs);
+
+template <int BLOCK>
+KernelFn pick_kernel(int stride) {
+  switch (stride) {
+    case 4: return k_topk_batched<BLOCK, 4>;
+    case 8: return k_topk_batched<BLOCK, 8>;
+    case 16: return k_topk_batched<BLOCK, 16>;
+    case 32: return k_topk_batched<BLOCK, 32>;
+    default: return k_topk_batched<BLOCK, 64>;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct BatchConfig {
+  int block = 512;      // threads per work-group
+  int wgs_per_cu = 1;   // persistent work-groups per CU
+};
+
+struct BatchState {
+  // device plan buffers (grown as needed)
+  int32_t* d_items = nullptr;
+  size_t items_cap = 0;
+  uint32_t* d_queue = nullptr;
+  // dense hub slots
+  uint32_t* d_slot_cnt = nullptr;
+  int32_t* d_slot_touched = nullptr;
+  int slots = 0;
+  // configuration
+  bool tuned = false;
+  BatchConfig cfg;
+  int forced_block = 0;
+  int forced_wgs = 0;
+  int64_t tier_a_override = -1;
+  int64_t tier_b_override = -1;
+  // graph cache
+  hipGraphExec_t exec = nullptr;
+  hipStream_t exec_stream = nullptr;
+  BatchArgs exec_args{};
+  int exec_block = 0, exec_grid = 0;
+  size_t exec_lds = 0;
+  std::string tune_key;
+};
+
+static BatchState* state(panther_ctx* c) {
+  if (!c->batch) c->batch = new BatchState();
+  return c->batch;
+}
+
+void free_batch_state(panther_ctx* c) {
+  if (!c->batch) return;
+  BatchState* b = c->batch;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  ctx_free(b->d_items);
+  ctx_free(b->d_queue);
+  ctx_free(b->d_slot_cnt);
+  ctx_free(b->d_slot_touched);
+  delete b;
+  c->batch = nullptr;
 }
 
 int set_batch_option(panther_ctx* c, const std::string& key, int64_t value) {
-  (void)value;
-  return ctx_fail(c, PANTHER_EINVAL, "unknown option '%s'", key.c_str());
+  BatchState* b = state(c);
+  if (key == "batch.block") {
+    if (value != 0 && value != 256 && value != 512)
+      return ctx_fail(c, PANTHER_EINVAL, "batch.block must be 0 (auto), 256 or 512");
+    b->forced_block = (int)value;
+  } else if (key == "batch.tier_a") {
+    b->tier_a_override = value;
+  } else if (key == "batch.tier_b") {
+    b->tier_b_override = value;
+  } else if (key == "batch.wgs_per_cu") {
+    if (value < 0 || value > 2) return ctx_fail(c, PANTHER_EINVAL, "batch.wgs_per_cu in 0..2");
+    b->forced_wgs = (int)value;
+  }
+  b->tuned = false;
+  return PANTHER_OK;
 }
 
-void free_batch_state(panther_ctx* c) { (void)c; }
+namespace {
+
+struct Layout {
+  size_t lds;
+  int TA, TB;
+};
+
+// LDS carve-up for a configuration: selection buffers, control words, and
+// a region holding either the work-group table (12 * TB bytes: keys, counts,
+// compacted keys) or one table per wave (12 * TA bytes each).
+Layout layout_for(const panther_ctx* c, const BatchConfig& cfg) {
+  size_t limit = (size_t)c->lds_per_block;
+  if (limit > 163840) limit = 163840;
+  if (cfg.wgs_per_cu > 1) limit = std::min(limit, (size_t)163840 / cfg.wgs_per_cu);
+  const size_t fixed = sizeof(SelectSmem) + 64;
+  const size_t avail = limit > fixed ? limit - fixed : 0;
+  const int waves = cfg.block / kWave;
+  int TB = 64, TA = 64;
+  while ((size_t)12 * (TB * 2) <= avail && TB < 16384) TB *= 2;
+  while ((size_t)12 * (TA * 2) * waves <= avail && TA < 2048) TA *= 2;
+  const size_t region = std::max((size_t)12 * TB, (size_t)12 * TA * waves);
+  return Layout{fixed + region, TA, TB};
+}
+
+std::string tune_cache_path() {
+  const char* p = getenv("PANTHER_TUNE_CACHE");
+  if (p && *p) return p;
+  const char* h = getenv("HOME");
+  return std::string(h ? h : "/tmp") + "/.cache/panther_tune.txt";
+}
+
+bool tune_lookup(const std::string& key, BatchConfig* cfg) {
+  std::ifstream f(tune_cache_path());
+  std::string line;
+  bool found = false;
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    std::string k;
+    int blk, wgs;
+    if (is >> k >> blk >> wgs && k == key) {
+      cfg->block = blk;
+      cfg->wgs_per_cu = wgs;
+      found = true;
+    }
+  }
+  return found;
+}
+
+void tune_store(const std::string& key, const BatchConfig& cfg) {
+  const std::string path = tune_cache_path();
+  const size_t slash = path.rfind('/');
+  if (slash != std::string::npos) {
+    std::string dir = path.substr(0, slash);
+    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
+    (void)!system(cmd.c_str());
+  }
+  std::ofstream f(path, std::ios::app);
+  if (f) f << key << " " << cfg.block << " " << cfg.wgs_per_cu << "\n";
+}
+
+}  // namespace
+
+static int ensure_slots(panther_ctx* c, BatchState* b, int want) {
+  if (b->slots >= want) return PANTHER_OK;
+  ctx_free(b->d_slot_cnt);
+  ctx_free(b->d_slot_touched);
+  b->d_slot_cnt = nullptr;
+  b->d_slot_touched = nullptr;
+  b->slots = 0;
+  void* p;
+  const size_t per = sizeof(uint32_t) * (size_t)c->n;
+  int st = ctx_alloc(c, &p, per * (size_t)want, "hub counters");
+  if (st) return st;
+  b->d_slot_cnt = static_cast<uint32_t*>(p);
+  st = ctx_alloc(c, &p, per * (size_t)want, "hub touched lists");
+  if (st) return st;
+  b->d_slot_touched = static_cast<int32_t*>(p);
+  st = ctx_hip(c, hipMemsetAsync(b->d_slot_cnt, 0, per * (size_t)want, c->stream), "hub counters");
+  if (st) return st;
+  st = ctx_hip(c, hipStreamSynchronize(c->stream), "hub counters");
+  if (st) return st;
+  b->slots = want;
+  return PANTHER_OK;
+}
+
+// One launch of the persistent kernel for a prepared plan.
+static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
+                          const BatchArgs& args_in, hipStream_t s, bool use_graph) {
+  const Layout lay = layout_for(c, cfg);
+  BatchArgs args = args_in;
+  const int grid = c->num_cus * cfg.wgs_per_cu;
+  args.hub_wgs = std::min(grid, b->slots);
+  KernelFn fn = cfg.block == 256 ? pick_kernel<256>(c->stride) : pick_kernel<512>(c->stride);
+  int st = ctx_hip(c, hipFuncSetAttribute((const void*)fn,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)lay.lds),
+                   "batched kernel attribute");
+  if (st) return st;
+  const bool same = b->exec && b->exec_stream == s && b->exec_block == cfg.block &&
+                    b->exec_grid == grid && b->exec_lds == lay.lds &&
+                    std::memcmp(&b->exec_args, &args, sizeof(args)) == 0;
+  if (use_graph && same) return ctx_hip(c, hipGraphLaunch(b->exec, s), "batched graph replay");
+  if (use_graph) {
+    if (b->exec) {
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    hipStream_t cs;
+    st = ctx_hip(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream");
+    if (st) return st;
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      k_reset_queue<<<1, 64, 0, cs>>>(args.queue);
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.block), lay.lds, cs, args);
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipStreamDestroy(cs);
+    st = ctx_hip(c, e, "batched graph capture");
+    if (st) return st;
+    b->exec_stream = s;
+    b->exec_block = cfg.block;
+    b->exec_grid = grid;
+    b->exec_lds = lay.lds;
+    b->exec_args = args;
+    return ctx_hip(c, hipGraphLaunch(b->exec, s), "batched graph launch");
+  }
+  k_reset_queue<<<1, 64, 0, s>>>(args.queue);
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.block), lay.lds, s, args);
+  return ctx_hip(c, hipGetLastError(), "batched kernel");
+}
+
+// Builds the plan for one configuration; returns the kernel arguments.
+static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int32_t* dq,
+                const std::vector<int32_t>& hq, int64_t nq, int32_t k, int32_t* d_ids,
+                uint32_t* d_counts, int32_t* d_len, hipStream_t s, BatchArgs* out,
+                std::vector<int32_t>* host_items) {
+  const Layout lay = layout_for(c, cfg);
+  const uint64_t T = (uint64_t)c->T;
+  uint64_t LA = (uint64_t)lay.TA / (2 * T);
+  uint64_t LB = (uint64_t)lay.TB / (2 * T);
+  if (b->tier_a_override >= 0) LA = std::min(LA, (uint64_t)b->tier_a_override);
+  if (b->tier_b_override >= 0) LB = std::min(LB, (uint64_t)b->tier_b_override);
+  // the wave-tier sort buffer holds TA/2 keys and the block selection keeps
+  // at most kCand keys without radix narrowing; both are covered by the
+  // load bound T * L <= table / 2
+  std::vector<std::pair<uint64_t, int32_t>> A, B, C;
+  for (int64_t i = 0; i < nq; ++i) {
+    const int32_t q = hq[i];
+    const uint64_t L = c->h_inv_ptr[q + 1] - c->h_inv_ptr[q];
+    if (L <= LA)
+      A.push_back({L, (int32_t)i});
+    else if (L <= LB)
+      B.push_back({L, (int32_t)i});
+    else
+      C.push_back({L, (int32_t)i});
+  }
+  auto longest_first = [](const std::pair<uint64_t, int32_t>& x,
+                          const std::pair<uint64_t, int32_t>& y) {
+    return x.first != y.first ? x.first > y.first : x.second < y.second;
+  };
+  std::sort(B.begin(), B.end(), longest_first);
+  std::sort(C.begin(), C.end(), longest_first);
+  std::sort(A.begin(), A.end(), longest_first);
+  host_items->clear();
+  for (auto& x : C) host_items->push_back(x.second);
+  for (auto& x : B) host_items->push_back(x.second);
+  for (auto& x : A) host_items->push_back(x.second);
+  if (!C.empty()) {
+    // dense slots: one per hub-capable work-group, within a memory budget
+    const int grid = c->num_cus * cfg.wgs_per_cu;
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    const size_t per = 8 * (size_t)c->n;
+    size_t budget = std::min((size_t)16 << 30, free_b / 4);
+    int want = (int)std::min<size_t>((size_t)grid, std::max<size_t>(1, budget / per));
+    want = std::min<int>(want, (int)C.size());
+    int st = ensure_slots(c, b, want);
+    if (st) return st;
+  }
+  const size_t need = host_items->size();
+  if (b->items_cap < need) {
+    ctx_free(b->d_items);
+    b->d_items = nullptr;
+    b->items_cap = 0;
+    void* p;
+    int st = ctx_alloc(c, &p, sizeof(int32_t) * std::max<size_t>(need, 1024), "batch plan");
+    if (st) return st;
+    b->d_items = static_cast<int32_t*>(p);
+    b->items_cap = std::max<size_t>(need, 1024);
+  }
+  if (!b->d_queue) {
+    void* p;
+    int st = ctx_alloc(c, &p, 64, "batch queue");
+    if (st) return st;
+    b->d_queue = static_cast<uint32_t*>(p);
+  }
+  int st = ctx_hip(c, hipMemcpyAsync(b->d_items, host_items->data(), sizeof(int32_t) * need,
+                                     hipMemcpyHostToDevice, s),
+                   "batch plan upload");
+  if (st) return st;
+  BatchArgs a{};
+  a.queries = dq;
+  a.itemsC = b->d_items;
+  a.itemsB = b->d_items + C.size();
+  a.itemsA = b->d_items + C.size() + B.size();
+  a.nC = (int32_t)C.size();
+  a.nB = (int32_t)B.size();
+  a.nA = (int32_t)A.size();
+  a.inv_ptr = c->d_inv_ptr;
+  a.inv_pid = c->d_inv_pid;
+  a.paths = c->d_paths;
+  a.slot_cnt = b->d_slot_cnt;
+  a.slot_touched = b->d_slot_touched;
+  a.queue = b->d_queue;
+  a.n = c->n;
+  a.k = k;
+  a.TA = lay.TA;
+  a.TB = lay.TB;
+  a.out_ids = d_ids;
+  a.out_counts = d_counts;
+  a.out_len = d_len;
+  *out = a;
+  return PANTHER_OK;
+}
+
+int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<int32_t>& hq,
+                     int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
+                     hipStream_t s) {
+  BatchState* b = state(c);
+  std::vector<int32_t> items;
+  BatchArgs args;
+  // configuration: forced, cached, autotuned, or the default
+  std::vector<BatchConfig> cands;
+  for (int blk : {512, 256})
+    for (int wgs : {1, 2}) cands.push_back(BatchConfig{blk, wgs});
+  if (b->forced_block || b->forced_wgs) {
+    BatchConfig f;
+    if (b->forced_block) f.block = b->forced_block;
+    if (b->forced_wgs) f.wgs_per_cu = b->forced_wgs;
+    b->cfg = f;
+    b->tuned = true;
+  }
+  if (!b->tuned) {
+    char key[256];
+    snprintf(key, sizeof key, "gfx950:n%d:T%d:R%lld:nq%lld:k%d:cu%d", c->n, c->T,
+             (long long)c->R, (long long)nq, k, c->num_cus);
+    b->tune_key = key;
+    BatchConfig cached;
+    if (tune_lookup(b->tune_key, &cached)) {
+      b->cfg = cached;
+      b->tuned = true;
+    } else if (c->autotune && nq >= 256) {
+      // time every candidate on this batch (results are identical by
+      // construction; only speed differs) and keep the fastest
+      hipEvent_t e0, e1;
+      int st = ctx_hip(c, hipEventCreate(&e0), "autotune");
+      if (st) return st;
+      st = ctx_hip(c, hipEventCreate(&e1), "autotune");
+      if (st) return st;
+      float best = 1e30f;
+      BatchConfig best_cfg = cands[0];
+      for (const BatchConfig& cfg : cands) {
+        st = plan(c, b, cfg, dq, hq, nq, k, d_ids, d_counts, d_len, s, &args, &items);
+        if (st) break;
+        st = launch_batched(c, b, cfg, args, s, false);  // warm
+        if (st) break;
+        (void)hipEventRecord(e0, s);
+        st = launch_batched(c, b, cfg, args, s, false);
+        if (st) break;
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          best_cfg = cfg;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (st) return st;
+      b->cfg = best_cfg;
+      b->tuned = true;
+      tune_store(b->tune_key, b->cfg);
+    } else {
+      b->cfg = BatchConfig{};
+      b->tuned = true;
+    }
+  }
+  int st = plan(c, b, b->cfg, dq, hq, nq, k, d_ids, d_counts, d_len, s, &args, &items);
+  if (st) return st;
+  st = launch_batched(c, b, b->cfg, args, s, true);
+  if (st) return st;
+  // the host plan vector must outlive the asynchronous upload
+  return ctx_hip(c, hipStreamSynchronize(s), "batched");
+}

@@ -1,13 +1,10 @@
 // Vertex-to-path inverted index (Sec. 3.1; Algorithm 3 "add p_r into P_v").
 //
-// P_v is a set: a path that visits v several times is listed once.  Build:
-// (1) per-vertex list lengths by atomics over the de-duplicated path rows,
-// (2) exclusive scan -> inv_ptr, (3) scatter of path ids through per-vertex
-// atomic cursors, (4) per-list sort into ascending path id, which makes the
-// result independent of the order in which the atomics landed.  Lists of
-// length 2..64 are sorted by one wave each (rank by comparison), 65..4096
-// by one work-group bitonic sort in LDS, longer ones by 4096-entry chunk
-// sorts followed by merge-path passes.
+// P_v is a set: a path that visits v several times is listed once, and the
+// lists hold path ids in ascending order.  The (vertex, path id) pairs of the
+// de-duplicated path rows are sorted by vertex with a stable radix sort, so
+// equal vertices keep path-id order; list offsets come from the boundaries
+// of the sorted keys.
 #include "common.h"
 #include "kernels.h"
 
@@ -17,195 +14,260 @@ namespace {
 
 constexpr int kBlock = 256;
 
-template <int S>
-__global__ void __launch_bounds__(kBlock)
-k_index_count(const int32_t* __restrict__ paths, uint64_t R, uint32_t* __restrict__ cnt) {
-  const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (pid >= R) return;
-  int32_t v[S];
-  load_row<S>(paths, pid, v);
-  dedup_row<S>(v);
-#pragma unroll
-  for (int i = 0; i < S; ++i)
-    if (v[i] >= 0) atomicAdd(&cnt[v[i]], 1u);
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort of the (vertex, path id) pairs by vertex.
+//
+// Pass 1 reads the path rows directly: a tile is `ppt` consecutive paths;
+// their distinct vertices become pairs in path-id order (compacted in LDS).
+// Later passes read tiles of 4096 consecutive pairs.  Each pass has an
+// up-sweep (per-tile digit histogram), a device-wide exclusive scan of the
+// histograms in digit-major order, and a down-sweep that ranks every item
+// stably inside its tile and scatters it to
+//   offset[digit][tile] + (same-digit items before it in the tile).
+// The in-tile rank comes from 64-item chunks: a wave matches digits across
+// its lanes with one ballot per digit bit, chunk histograms are scanned per
+// digit, and the rank is chunk prefix + lanes below with the same digit.
+// No atomics touch global memory, so the order of equal vertices is the
+// path-id order of the input and the index is deterministic.
+// ---------------------------------------------------------------------------
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kTileItems = 4096;
+constexpr int kChunks = kTileItems / kWave;
+
+struct RadixSmem {
+  uint32_t key[kTileItems];
+  uint32_t val[kTileItems];
+  uint16_t chunk[kChunks][kRadix];  // chunk histograms, then exclusive prefixes
+  uint8_t rank[kTileItems];
+  uint32_t scan[kBlock / kWave + 1];
+  uint32_t n;
+};
+
+__device__ __forceinline__ uint32_t digit_of(uint32_t key, int shift, int bits) {
+  return (key >> shift) & ((1u << bits) - 1u);
 }
 
+// Loads the distinct vertices of the tile's paths into sm.key/sm.val in
+// path-id order; returns the item count.
 template <int S>
-__global__ void __launch_bounds__(kBlock)
-k_index_scatter(const int32_t* __restrict__ paths, uint64_t R,
-                unsigned long long* __restrict__ cursor, uint32_t* __restrict__ inv_pid) {
-  const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (pid >= R) return;
-  int32_t v[S];
-  load_row<S>(paths, pid, v);
-  dedup_row<S>(v);
+__device__ int load_tile_from_paths(const int32_t* __restrict__ paths, uint64_t R, uint64_t p0,
+                                    int ppt, RadixSmem& sm) {
+  int base = 0;
+  for (int r0 = 0; r0 < ppt; r0 += kBlock) {
+    const uint64_t pid = p0 + r0 + threadIdx.x;
+    int32_t v[S];
+    const bool live = (r0 + (int)threadIdx.x < ppt) && pid < R;
+    if (live) {
+      load_row<S>(paths, pid, v);
+      dedup_row<S>(v);
+    } else {
 #pragma unroll
-  for (int i = 0; i < S; ++i)
-    if (v[i] >= 0) inv_pid[atomicAdd(&cursor[v[i]], 1ull)] = (uint32_t)pid;
-}
-
-// One wave per vertex.  Lists of length <= 64 are sorted in registers by
-// rank: each lane's element moves to the number of smaller elements.
-__global__ void __launch_bounds__(kBlock)
-k_seg_sort_small(const uint64_t* __restrict__ inv_ptr, int32_t n, uint32_t* __restrict__ inv_pid,
-                 int32_t* mid, uint32_t* n_mid, int32_t* big, uint32_t* n_big) {
-  const int32_t v = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-  if (v >= n) return;
-  const int lane = threadIdx.x & (kWave - 1);
-  const uint64_t a = inv_ptr[v];
-  const uint64_t len = inv_ptr[v + 1] - a;
-  if (len <= 1) return;
-  if (len > 64) {
-    if (lane == 0) {
-      if (len <= 4096)
-        mid[atomicAdd(n_mid, 1u)] = v;
-      else
-        big[atomicAdd(n_big, 1u)] = v;
+      for (int i = 0; i < S; ++i) v[i] = -1;
     }
-    return;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < S; ++i) cnt += v[i] >= 0 ? 1u : 0u;
+    uint32_t tot;
+    uint32_t off = block_exclusive_sum<kBlock>(cnt, sm.scan, &tot);
+    uint32_t o = (uint32_t)base + off;
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+      if (v[i] >= 0) {
+        sm.key[o] = (uint32_t)v[i];
+        sm.val[o] = (uint32_t)pid;
+        ++o;
+      }
+    base += (int)tot;
   }
-  const uint32_t x = lane < (int)len ? inv_pid[a + lane] : 0xFFFFFFFFu;
-  int rank = 0;
-  for (int j = 0; j < (int)len; ++j) {
-    const uint32_t y = __shfl(x, j, kWave);
-    rank += (y < x) ? 1 : 0;
-  }
-  if (lane < (int)len) inv_pid[a + rank] = x;
-}
-
-constexpr int kMidCap = 4096;
-
-__global__ void __launch_bounds__(kBlock)
-k_seg_sort_mid(const uint64_t* __restrict__ inv_ptr, const int32_t* __restrict__ mid,
-               uint32_t* __restrict__ inv_pid) {
-  __shared__ uint32_t s[kMidCap];
-  const int32_t v = mid[blockIdx.x];
-  const uint64_t a = inv_ptr[v];
-  const int len = (int)(inv_ptr[v + 1] - a);
-  const int P = next_pow2(len);
-  for (int i = threadIdx.x; i < P; i += kBlock) s[i] = i < len ? inv_pid[a + i] : 0xFFFFFFFFu;
   __syncthreads();
-  block_bitonic_asc<kBlock>(s, P);
-  for (int i = threadIdx.x; i < len; i += kBlock) inv_pid[a + i] = s[i];
+  return base;
 }
 
-// Big lists, step 1: sort each 4096-entry chunk in place.
-__global__ void __launch_bounds__(kBlock)
-k_seg_chunk_sort(const SegBlock* __restrict__ blocks, uint32_t* __restrict__ data) {
-  __shared__ uint32_t s[kMidCap];
-  const SegBlock b = blocks[blockIdx.x];
-  const uint64_t base = b.start + b.off;
-  const uint32_t rem = b.len - b.off;
-  const int cnt = (int)(rem < (uint32_t)kMidCap ? rem : (uint32_t)kMidCap);
-  const int P = next_pow2(cnt < 2 ? 2 : cnt);
-  for (int i = threadIdx.x; i < P; i += kBlock) s[i] = i < cnt ? data[base + i] : 0xFFFFFFFFu;
+__device__ void tile_histogram(const RadixSmem& sm, int n, int shift, int bits, uint32_t* hist,
+                               uint32_t* s_hist) {
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
   __syncthreads();
-  block_bitonic_asc<kBlock>(s, P);
-  for (int i = threadIdx.x; i < cnt; i += kBlock) data[base + i] = s[i];
+  for (int i = threadIdx.x; i < n; i += kBlock) atomicAdd(&s_hist[digit_of(sm.key[i], shift, bits)], 1u);
+  __syncthreads();
 }
 
-// Big lists, step 2: merge sorted runs of `width` pairwise.  Each block
-// writes 4096 outputs (16 per thread) of one merged pair; each thread finds
-// its start on the merge path by bisection.
-constexpr int kMergeItems = 16;
-constexpr int kMergeTile = kBlock * kMergeItems;
-
-__global__ void __launch_bounds__(kBlock)
-k_seg_merge(const SegBlock* __restrict__ blocks, uint32_t width, const uint32_t* __restrict__ src,
-            uint32_t* __restrict__ dst) {
-  const SegBlock b = blocks[blockIdx.x];
-  const uint64_t w2 = 2ull * width;
-  const uint64_t pair0 = (b.off / w2) * w2;  // start of the pair within the list
-  const uint64_t alen = (pair0 + width < b.len ? pair0 + width : b.len) - pair0;
-  const uint64_t bend = pair0 + w2 < b.len ? pair0 + w2 : b.len;
-  const uint64_t blen = bend > pair0 + alen ? bend - pair0 - alen : 0;
-  const uint32_t* A = src + b.start + pair0;
-  const uint32_t* B = A + alen;
-  const uint64_t total = alen + blen;
-  uint64_t diag = (b.off - pair0) + (uint64_t)threadIdx.x * kMergeItems;
-  if (diag >= total) return;
-  // merge path: i from A, diag - i from B
-  uint64_t lo = diag > blen ? diag - blen : 0;
-  uint64_t hi = diag < alen ? diag : alen;
-  while (lo < hi) {
-    const uint64_t m = (lo + hi) >> 1;
-    if (A[m] <= B[diag - 1 - m])
-      lo = m + 1;
-    else
-      hi = m;
+// In-tile stable ranks (chunk prefix + in-chunk rank), then the scatter.
+__device__ void rank_and_scatter(RadixSmem& sm, int n, int shift, int bits,
+                                 const uint64_t* __restrict__ offsets, uint64_t ntiles,
+                                 uint64_t tile, uint32_t* __restrict__ key_out,
+                                 uint32_t* __restrict__ val_out) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int nchunks = (n + kWave - 1) / kWave;
+  for (int i = threadIdx.x; i < kChunks * kRadix; i += kBlock)
+    (&sm.chunk[0][0])[i] = 0;
+  __syncthreads();
+  for (int c = wid; c < nchunks; c += kBlock / kWave) {
+    const int i = c * kWave + lane;
+    const bool live = i < n;
+    const uint32_t d = live ? digit_of(sm.key[i], shift, bits) : 0xFFFFu;
+    uint64_t same = __ballot(live);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const uint64_t m = __ballot(live && ((d >> b) & 1u));
+      same &= ((d >> b) & 1u) ? m : ~m;
+    }
+    if (live) {
+      const uint64_t below = same & ((1ull << lane) - 1ull);
+      sm.rank[i] = (uint8_t)__popcll(below);
+      if (below == 0) sm.chunk[c][d] = (uint16_t)__popcll(same);
+    }
   }
-  uint64_t i = lo, j = diag - lo;
-  uint32_t* out = dst + b.start + pair0 + diag;
-  for (int t = 0; t < kMergeItems && diag + t < total; ++t) {
-    bool takeA;
-    if (i >= alen)
-      takeA = false;
-    else if (j >= blen)
-      takeA = true;
-    else
-      takeA = A[i] <= B[j];
-    out[t] = takeA ? A[i++] : B[j++];
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) {
+    uint32_t run = 0;
+    for (int c = 0; c < nchunks; ++c) {
+      const uint32_t x = sm.chunk[c][d];
+      sm.chunk[c][d] = (uint16_t)run;
+      run += x;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const uint32_t key = sm.key[i];
+    const uint32_t d = digit_of(key, shift, bits);
+    const uint64_t pos = offsets[(uint64_t)d * ntiles + tile] + sm.chunk[i / kWave][d] + sm.rank[i];
+    if (key_out) key_out[pos] = key;
+    val_out[pos] = sm.val[i];
   }
 }
 
+template <int S>
 __global__ void __launch_bounds__(kBlock)
-k_seg_copy(const SegBlock* __restrict__ blocks, const uint32_t* __restrict__ src,
-           uint32_t* __restrict__ dst) {
-  const SegBlock b = blocks[blockIdx.x];
-  for (uint32_t i = threadIdx.x; i < (uint32_t)kMergeTile && b.off + i < b.len; i += kBlock)
-    dst[b.start + b.off + i] = src[b.start + b.off + i];
+k_radix_up_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shift, int bits,
+                 uint64_t ntiles, uint32_t* __restrict__ hist) {
+  __shared__ RadixSmem sm;
+  __shared__ uint32_t s_hist[kRadix];
+  const int n = load_tile_from_paths<S>(paths, R, (uint64_t)blockIdx.x * ppt, ppt, sm);
+  tile_histogram(sm, n, shift, bits, hist, s_hist);
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
+}
+
+template <int S>
+__global__ void __launch_bounds__(kBlock)
+k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shift, int bits,
+                   uint64_t ntiles, const uint64_t* __restrict__ offsets,
+                   uint32_t* __restrict__ key_out, uint32_t* __restrict__ val_out) {
+  __shared__ RadixSmem sm;
+  const int n = load_tile_from_paths<S>(paths, R, (uint64_t)blockIdx.x * ppt, ppt, sm);
+  rank_and_scatter(sm, n, shift, bits, offsets, ntiles, blockIdx.x, key_out, val_out);
+}
+
+__device__ int load_tile_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                               uint64_t nnz, uint64_t tile, RadixSmem& sm, bool with_vals) {
+  const uint64_t a = tile * kTileItems;
+  const int n = (int)((nnz - a) < (uint64_t)kTileItems ? (nnz - a) : (uint64_t)kTileItems);
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    sm.key[i] = keys[a + i];
+    if (with_vals) sm.val[i] = vals[a + i];
+  }
+  __syncthreads();
+  return n;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_radix_up_pairs(const uint32_t* __restrict__ keys, uint64_t nnz, int shift, int bits,
+                 uint64_t ntiles, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_hist[kRadix];
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
+  __syncthreads();
+  const uint64_t a = (uint64_t)blockIdx.x * kTileItems;
+  for (uint64_t i = a + threadIdx.x; i < a + kTileItems && i < nnz; i += kBlock)
+    atomicAdd(&s_hist[digit_of(keys[i], shift, bits)], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                   uint64_t nnz, int shift, int bits, uint64_t ntiles,
+                   const uint64_t* __restrict__ offsets, uint32_t* __restrict__ key_out,
+                   uint32_t* __restrict__ val_out) {
+  __shared__ RadixSmem sm;
+  const int n = load_tile_pairs(keys, vals, nnz, blockIdx.x, sm, true);
+  rank_and_scatter(sm, n, shift, bits, offsets, ntiles, blockIdx.x, key_out, val_out);
+}
+
+// inv_ptr from the sorted vertex keys: position i opens the lists of every
+// vertex in (key[i-1], key[i]].
+__global__ void __launch_bounds__(kBlock)
+k_list_bounds(const uint32_t* __restrict__ keys, uint64_t nnz, int32_t n,
+              uint64_t* __restrict__ inv_ptr) {
+  const uint64_t gsz = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i <= nnz; i += gsz) {
+    const int64_t kp = i == 0 ? -1 : (int64_t)keys[i - 1];
+    const int64_t kc = i == nnz ? (int64_t)n : (int64_t)keys[i];
+    for (int64_t v = kp + 1; v <= kc; ++v) inv_ptr[v] = i;
+  }
 }
 
 }  // namespace
 
-void launch_index_count(int stride, const int32_t* paths, uint64_t R, uint32_t* cnt,
+uint64_t radix_tiles_paths(uint64_t R, int T) {
+  const int ppt = kTileItems / (T + 1);
+  return (R + ppt - 1) / ppt;
+}
+
+uint64_t radix_tiles_pairs(uint64_t nnz) { return (nnz + kTileItems - 1) / kTileItems; }
+
+void launch_radix_up_paths(int stride, const int32_t* paths, uint64_t R, int T, int shift,
+                           int bits, uint32_t* hist, hipStream_t s) {
+  const int ppt = kTileItems / (T + 1);
+  const uint64_t nt = radix_tiles_paths(R, T);
+#define PANTHER_UP(SS) \
+  k_radix_up_paths<SS><<<(unsigned)nt, kBlock, 0, s>>>(paths, R, ppt, shift, bits, nt, hist)
+  switch (stride) {
+    case 4: PANTHER_UP(4); break;
+    case 8: PANTHER_UP(8); break;
+    case 16: PANTHER_UP(16); break;
+    case 32: PANTHER_UP(32); break;
+    default: PANTHER_UP(64); break;
+  }
+#undef PANTHER_UP
+}
+
+void launch_radix_down_paths(int stride, const int32_t* paths, uint64_t R, int T, int shift,
+                             int bits, const uint64_t* offsets, uint32_t* key_out,
+                             uint32_t* val_out, hipStream_t s) {
+  const int ppt = kTileItems / (T + 1);
+  const uint64_t nt = radix_tiles_paths(R, T);
+#define PANTHER_DOWN(SS)                                                                   \
+  k_radix_down_paths<SS><<<(unsigned)nt, kBlock, 0, s>>>(paths, R, ppt, shift, bits, nt, \
+                                                         offsets, key_out, val_out)
+  switch (stride) {
+    case 4: PANTHER_DOWN(4); break;
+    case 8: PANTHER_DOWN(8); break;
+    case 16: PANTHER_DOWN(16); break;
+    case 32: PANTHER_DOWN(32); break;
+    default: PANTHER_DOWN(64); break;
+  }
+#undef PANTHER_DOWN
+}
+
+void launch_radix_up_pairs(const uint32_t* keys, uint64_t nnz, int shift, int bits,
+                           uint32_t* hist, hipStream_t s) {
+  const uint64_t nt = radix_tiles_pairs(nnz);
+  k_radix_up_pairs<<<(unsigned)nt, kBlock, 0, s>>>(keys, nnz, shift, bits, nt, hist);
+}
+
+void launch_radix_down_pairs(const uint32_t* keys, const uint32_t* vals, uint64_t nnz, int shift,
+                             int bits, const uint64_t* offsets, uint32_t* key_out,
+                             uint32_t* val_out, hipStream_t s) {
+  const uint64_t nt = radix_tiles_pairs(nnz);
+  k_radix_down_pairs<<<(unsigned)nt, kBlock, 0, s>>>(keys, vals, nnz, shift, bits, nt, offsets,
+                                                      key_out, val_out);
+}
+
+void launch_list_bounds(const uint32_t* keys, uint64_t nnz, int32_t n, uint64_t* inv_ptr,
                         hipStream_t s) {
-  const unsigned grid = (unsigned)((R + kBlock - 1) / kBlock);
-  switch (stride) {
-    case 4: k_index_count<4><<<grid, kBlock, 0, s>>>(paths, R, cnt); break;
-    case 8: k_index_count<8><<<grid, kBlock, 0, s>>>(paths, R, cnt); break;
-    case 16: k_index_count<16><<<grid, kBlock, 0, s>>>(paths, R, cnt); break;
-    case 32: k_index_count<32><<<grid, kBlock, 0, s>>>(paths, R, cnt); break;
-    default: k_index_count<64><<<grid, kBlock, 0, s>>>(paths, R, cnt); break;
-  }
-}
-
-void launch_index_scatter(int stride, const int32_t* paths, uint64_t R,
-                          unsigned long long* cursor, uint32_t* inv_pid, hipStream_t s) {
-  const unsigned grid = (unsigned)((R + kBlock - 1) / kBlock);
-  switch (stride) {
-    case 4: k_index_scatter<4><<<grid, kBlock, 0, s>>>(paths, R, cursor, inv_pid); break;
-    case 8: k_index_scatter<8><<<grid, kBlock, 0, s>>>(paths, R, cursor, inv_pid); break;
-    case 16: k_index_scatter<16><<<grid, kBlock, 0, s>>>(paths, R, cursor, inv_pid); break;
-    case 32: k_index_scatter<32><<<grid, kBlock, 0, s>>>(paths, R, cursor, inv_pid); break;
-    default: k_index_scatter<64><<<grid, kBlock, 0, s>>>(paths, R, cursor, inv_pid); break;
-  }
-}
-
-void launch_seg_sort_small(const uint64_t* inv_ptr, int32_t n, uint32_t* inv_pid, int32_t* mid,
-                           uint32_t* n_mid, int32_t* big, uint32_t* n_big, hipStream_t s) {
-  const unsigned grid = (unsigned)((n + kBlock / kWave - 1) / (kBlock / kWave));
-  k_seg_sort_small<<<grid, kBlock, 0, s>>>(inv_ptr, n, inv_pid, mid, n_mid, big, n_big);
-}
-
-void launch_seg_sort_mid(const uint64_t* inv_ptr, const int32_t* mid, uint32_t n_mid,
-                         uint32_t* inv_pid, hipStream_t s) {
-  if (n_mid) k_seg_sort_mid<<<n_mid, kBlock, 0, s>>>(inv_ptr, mid, inv_pid);
-}
-
-void launch_seg_chunk_sort(const SegBlock* blocks, uint32_t nblocks, uint32_t* data,
-                           hipStream_t s) {
-  if (nblocks) k_seg_chunk_sort<<<nblocks, kBlock, 0, s>>>(blocks, data);
-}
-
-void launch_seg_merge(const SegBlock* blocks, uint32_t nblocks, uint32_t width,
-                      const uint32_t* src, uint32_t* dst, hipStream_t s) {
-  if (nblocks) k_seg_merge<<<nblocks, kBlock, 0, s>>>(blocks, width, src, dst);
-}
-
-void launch_seg_copy(const SegBlock* blocks, uint32_t nblocks, const uint32_t* src,
-                     uint32_t* dst, hipStream_t s) {
-  if (nblocks) k_seg_copy<<<nblocks, kBlock, 0, s>>>(blocks, src, dst);
+  uint64_t g = (nnz + 1 + kBlock - 1) / kBlock;
+  if (g > 65536) g = 65536;
+  k_list_bounds<<<(unsigned)g, kBlock, 0, s>>>(keys, nnz, n, inv_ptr);
 }
 
 }  // namespace panther

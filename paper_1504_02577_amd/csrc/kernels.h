@@ -36,41 +36,45 @@ void launch_prefix32(const VRec* vrec, const uint32_t* w, int32_t n, const int32
 void launch_prefix64(const VRec* vrec, const uint32_t* w, int32_t n, const int32_t* big_rows,
                      uint32_t n_big, uint64_t* pfx, hipStream_t s);
 
+// Walk acceleration for 32-bit prefixes: edge[e] = {prefix, column} and the
+// per-row guide table (entry b = first edge any draw of bucket b can pick).
+void launch_pack_edges(const uint32_t* pfx, const int32_t* col, int64_t m, uint2* edge,
+                       hipStream_t s);
+void launch_guide(const VRec* vrec, const uint32_t* pfx, int32_t n, const int32_t* big_rows,
+                  uint32_t n_big, int32_t* guide, hipStream_t s);
+
 // ---- device-wide exclusive scan: out[i] = sum in[0..i), out[n] = total ----
 size_t scan_temp_bytes(int64_t n);
 void launch_scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, void* temp,
                             hipStream_t s);
 
 // ---- walk ----
-void launch_walk(int stride, bool pfx64, const VRec* vrec, const void* pfx, const int32_t* col,
-                 const int32_t* vstart, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
-                 int32_t* paths, hipStream_t s);
+// 64-bit prefixes: bisection over pfx64 + col.  32-bit prefixes: guide
+// table + packed edge records.
+void launch_walk64(int stride, const VRec* vrec, const uint64_t* pfx, const int32_t* col,
+                   const int32_t* vstart, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
+                   int32_t* paths, hipStream_t s);
+void launch_walk32(int stride, const VRec* vrec, const uint2* edge, const int32_t* guide,
+                   const int32_t* vstart, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
+                   int32_t* paths, hipStream_t s);
 
-// ---- index ----
-void launch_index_count(int stride, const int32_t* paths, uint64_t R, uint32_t* cnt,
+// ---- index by stable LSD radix sort of (vertex, path id) pairs ----
+constexpr int kRadixPassBits = 8;
+uint64_t radix_tiles_paths(uint64_t R, int T);
+uint64_t radix_tiles_pairs(uint64_t nnz);
+// hist: [256][tiles] digit-major histograms of the pass
+void launch_radix_up_paths(int stride, const int32_t* paths, uint64_t R, int T, int shift,
+                           int bits, uint32_t* hist, hipStream_t s);
+void launch_radix_down_paths(int stride, const int32_t* paths, uint64_t R, int T, int shift,
+                             int bits, const uint64_t* offsets, uint32_t* key_out,
+                             uint32_t* val_out, hipStream_t s);
+void launch_radix_up_pairs(const uint32_t* keys, uint64_t nnz, int shift, int bits,
+                           uint32_t* hist, hipStream_t s);
+void launch_radix_down_pairs(const uint32_t* keys, const uint32_t* vals, uint64_t nnz, int shift,
+                             int bits, const uint64_t* offsets, uint32_t* key_out,
+                             uint32_t* val_out, hipStream_t s);
+void launch_list_bounds(const uint32_t* keys, uint64_t nnz, int32_t n, uint64_t* inv_ptr,
                         hipStream_t s);
-void launch_index_scatter(int stride, const int32_t* paths, uint64_t R,
-                          unsigned long long* cursor, uint32_t* inv_pid, hipStream_t s);
-// Classifies lists by length: lengths 2..64 sorted by one wave each (in the
-// classification kernel's sibling), 65..4096 listed in mid, >4096 in big.
-void launch_seg_sort_small(const uint64_t* inv_ptr, int32_t n, uint32_t* inv_pid,
-                           int32_t* mid, uint32_t* n_mid, int32_t* big, uint32_t* n_big,
-                           hipStream_t s);
-void launch_seg_sort_mid(const uint64_t* inv_ptr, const int32_t* mid, uint32_t n_mid,
-                         uint32_t* inv_pid, hipStream_t s);
-// Big lists: chunk sort (4096) then merge passes; descs are per-block
-// (list start, list length, block offset) triples prepared by the host.
-struct SegBlock {
-  uint64_t start;
-  uint32_t len;
-  uint32_t off;  // first element (sort) / output position (merge) of the block
-};
-void launch_seg_chunk_sort(const SegBlock* blocks, uint32_t nblocks, uint32_t* data,
-                           hipStream_t s);
-void launch_seg_merge(const SegBlock* blocks, uint32_t nblocks, uint32_t width,
-                      const uint32_t* src, uint32_t* dst, hipStream_t s);
-void launch_seg_copy(const SegBlock* blocks, uint32_t nblocks, const uint32_t* src,
-                     uint32_t* dst, hipStream_t s);
 
 // ---- count + top-k, plain form: one launch per query ----
 struct TopkScratch {

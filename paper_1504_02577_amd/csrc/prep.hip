@@ -114,6 +114,68 @@ k_prefix_big(const VRec* __restrict__ vrec, const uint32_t* __restrict__ w,
   }
 }
 
+// ---- walk acceleration (32-bit prefixes): packed edges and guide table ----
+// edge[e] = {inclusive weight prefix, column}: one 8-byte load gives both.
+__global__ void __launch_bounds__(kBlock)
+k_pack_edges(const uint32_t* __restrict__ pfx, const int32_t* __restrict__ col, int64_t m,
+             uint2* __restrict__ edge) {
+  const int64_t gsz = (int64_t)gridDim.x * kBlock;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < m; e += gsz)
+    edge[e] = make_uint2(pfx[e], (uint32_t)col[e]);
+}
+
+// Guide entry b of a row of degree d: the draws r with floor(r d / 2^64) = b
+// are r in [ceil(b 2^64 / d), ceil((b+1) 2^64 / d)); the smallest of them
+// gives the smallest u = floor(r W / 2^64), and the first edge with prefix
+// > that u is where the selection for any draw of the bucket can start.
+// ceil(b 2^64 / d) = b Q + ceil(b Rm / d) with Q = floor(2^64 / d) and
+// Rm = 2^64 mod d, all in 64-bit integers.
+__device__ __forceinline__ int32_t guide_entry(const uint32_t* __restrict__ pfx, int32_t start,
+                                               int32_t deg, uint64_t W, uint64_t b) {
+  const uint64_t d = (uint64_t)deg;
+  uint64_t Q = ~0ull / d;
+  uint64_t Rm = ~0ull - Q * d + 1ull;
+  if (Rm == d) {
+    Q += 1ull;
+    Rm = 0ull;
+  }
+  const uint64_t rmin = b * Q + (b * Rm + d - 1ull) / d;
+  const uint64_t u = __umul64hi(rmin, W);
+  int32_t lo = start, hi = start + deg - 1;
+  while (lo < hi) {
+    const int32_t mid = lo + ((hi - lo) >> 1);
+    if ((uint64_t)pfx[mid] > u)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_guide_small(const VRec* __restrict__ vrec, const uint32_t* __restrict__ pfx, int32_t n,
+              int32_t* __restrict__ guide) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  const VRec r = vrec[v];
+  const uint64_t W = (uint64_t)r.w_lo | ((uint64_t)r.w_hi << 32);
+  if (r.deg > 256 || r.deg == 0 || W == 0) return;
+  for (int32_t b = 0; b < r.deg; ++b) guide[r.start + b] = guide_entry(pfx, r.start, r.deg, W, b);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_guide_big(const VRec* __restrict__ vrec, const uint32_t* __restrict__ pfx,
+            const int32_t* __restrict__ big_rows, uint32_t n_big, int32_t* __restrict__ guide) {
+  const uint32_t r = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (r >= n_big) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const VRec rec = vrec[big_rows[r]];
+  const uint64_t W = (uint64_t)rec.w_lo | ((uint64_t)rec.w_hi << 32);
+  if (W == 0) return;
+  for (int32_t b = lane; b < rec.deg; b += kWave)
+    guide[rec.start + b] = guide_entry(pfx, rec.start, rec.deg, W, b);
+}
+
 // ---- device-wide exclusive scan (reduce tiles, scan tile sums, apply) ----
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -228,6 +290,19 @@ void launch_prefix64(const VRec* vrec, const uint32_t* w, int32_t n, const int32
   if (n_big)
     k_prefix_big<uint64_t><<<grid_for(n_big, kBlock / kWave), kBlock, 0, s>>>(vrec, w, big_rows,
                                                                             n_big, pfx);
+}
+
+void launch_pack_edges(const uint32_t* pfx, const int32_t* col, int64_t m, uint2* edge,
+                       hipStream_t s) {
+  if (m) k_pack_edges<<<grid_for(m, kBlock * 8, 65536), kBlock, 0, s>>>(pfx, col, m, edge);
+}
+
+void launch_guide(const VRec* vrec, const uint32_t* pfx, int32_t n, const int32_t* big_rows,
+                  uint32_t n_big, int32_t* guide, hipStream_t s) {
+  k_guide_small<<<grid_for(n, kBlock), kBlock, 0, s>>>(vrec, pfx, n, guide);
+  if (n_big)
+    k_guide_big<<<grid_for(n_big, kBlock / kWave), kBlock, 0, s>>>(vrec, pfx, big_rows, n_big,
+                                                                  guide);
 }
 
 size_t scan_temp_bytes(int64_t n) {

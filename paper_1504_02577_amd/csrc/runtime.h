@@ -32,6 +32,8 @@ struct panther_ctx {
   panther::VRec* d_vrec = nullptr;
   void* d_pfx = nullptr;
   bool pfx64 = false;
+  uint2* d_edge = nullptr;    // {prefix, column} when every W_v < 2^32
+  int32_t* d_guide = nullptr; // guide table, same case
   int32_t* d_vstart = nullptr;
   int32_t nstart = 0;
   uint64_t max_w = 0;

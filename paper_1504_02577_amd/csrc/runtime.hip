@@ -98,6 +98,10 @@ static void free_graph(panther_ctx* c) {
   ctx_free(c->d_vrec);
   ctx_free(c->d_pfx);
   ctx_free(c->d_vstart);
+  ctx_free(c->d_edge);
+  ctx_free(c->d_guide);
+  c->d_edge = nullptr;
+  c->d_guide = nullptr;
   c->d_col = nullptr;
   c->d_vrec = nullptr;
   c->d_pfx = nullptr;
@@ -233,7 +237,8 @@ extern "C" int panther_set_option(panther_ctx* c, const char* key, int64_t value
     for (int i = 0; i < 5; ++i) c->ev_used[i] = false;
   } else if (k == "test.fail_alloc_after") {
     c->fail_alloc_after = value < 0 ? -1 : value;
-  } else if (k == "batch.tier_a" || k == "batch.tier_b" || k == "batch.block") {
+  } else if (k == "batch.tier_a" || k == "batch.tier_b" || k == "batch.block" ||
+             k == "batch.wgs_per_cu") {
     return set_batch_option(c, k, value);
   } else {
     return ctx_fail(c, PANTHER_EINVAL, "unknown option '%s'", key);
@@ -377,10 +382,18 @@ extern "C" int panther_load_graph(panther_ctx* c, int32_t n, int64_t m, const in
   c->pfx64 = max_w >= (uint64_t(1) << 32);
   TRY(ctx_alloc(c, &p, (c->pfx64 ? 8 : 4) * (size_t)m, "weight prefixes"));
   c->d_pfx = p;
-  if (c->pfx64)
+  if (c->pfx64) {
     launch_prefix64(c->d_vrec, d_w, n, big, n_big, static_cast<uint64_t*>(c->d_pfx), s);
-  else
+  } else {
     launch_prefix32(c->d_vrec, d_w, n, big, n_big, static_cast<uint32_t*>(c->d_pfx), s);
+    TRY(ctx_alloc(c, &p, sizeof(uint2) * (size_t)m, "packed edges"));
+    c->d_edge = static_cast<uint2*>(p);
+    TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)m, "guide table"));
+    c->d_guide = static_cast<int32_t*>(p);
+    launch_pack_edges(static_cast<const uint32_t*>(c->d_pfx), d_col, m, c->d_edge, s);
+    launch_guide(c->d_vrec, static_cast<const uint32_t*>(c->d_pfx), n, big, n_big, c->d_guide,
+                 s);
+  }
   HIPTRY(hipGetLastError(), "prefix");
   HIPTRY(hipStreamSynchronize(s), "load_graph");
   c->n = n;
@@ -400,86 +413,71 @@ static int build_index(panther_ctx* c) {
   const uint64_t R = (uint64_t)c->R;
   Temp tmp;
   void* p;
-  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)n, "index counts"));
+  int bits_total = 1;
+  while (bits_total < 31 && (int64_t(1) << bits_total) < (int64_t)n) ++bits_total;
+  const int passes = (bits_total + kRadixPassBits - 1) / kRadixPassBits;
+  const int pass_bits = (bits_total + passes - 1) / passes;
+  const uint64_t tiles1 = radix_tiles_paths(R, c->T);
+  // pass 1: histograms straight from the path rows
+  const uint64_t hist_cap = 256 * std::max<uint64_t>(tiles1, radix_tiles_pairs(R * (c->T + 1)));
+  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * hist_cap, "radix histograms"));
   tmp.add(p);
-  uint32_t* cnt = static_cast<uint32_t*>(p);
-  HIPTRY(hipMemsetAsync(cnt, 0, sizeof(uint32_t) * (size_t)n, s), "index");
-  launch_index_count(c->stride, c->d_paths, R, cnt, s);
-  HIPTRY(hipGetLastError(), "index count");
+  uint32_t* hist = static_cast<uint32_t*>(p);
+  TRY(ctx_alloc(c, &p, sizeof(uint64_t) * (hist_cap + 1), "radix offsets"));
+  tmp.add(p);
+  uint64_t* offs = static_cast<uint64_t*>(p);
+  TRY(ctx_alloc(c, &p, scan_temp_bytes((int64_t)hist_cap), "scan temp"));
+  tmp.add(p);
+  void* stemp = p;
+  int shift = 0;
+  int bits = std::min(pass_bits, bits_total - shift);
+  launch_radix_up_paths(c->stride, c->d_paths, R, c->T, shift, bits, hist, s);
+  launch_scan_u32_to_u64(hist, offs, (int64_t)(256 * tiles1), stemp, s);
+  HIPTRY(hipGetLastError(), "index pass 1");
+  uint64_t nnz = 0;
+  HIPTRY(hipMemcpyAsync(&nnz, offs + 256 * tiles1, 8, hipMemcpyDeviceToHost, s), "index");
+  HIPTRY(hipStreamSynchronize(s), "index");
+  c->nnz = (int64_t)nnz;
+  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * nnz, "index path ids"));
+  c->d_inv_pid = static_cast<uint32_t*>(p);
   TRY(ctx_alloc(c, &p, sizeof(uint64_t) * (size_t)(n + 1), "index offsets"));
   c->d_inv_ptr = static_cast<uint64_t*>(p);
-  TRY(ctx_alloc(c, &p, scan_temp_bytes(n), "scan temp"));
-  tmp.add(p);
-  launch_scan_u32_to_u64(cnt, c->d_inv_ptr, n, p, s);
-  HIPTRY(hipGetLastError(), "index scan");
+  uint32_t* keys[2];
+  for (int i = 0; i < 2; ++i) {
+    TRY(ctx_alloc(c, &p, sizeof(uint32_t) * nnz, "radix keys"));
+    tmp.add(p);
+    keys[i] = static_cast<uint32_t*>(p);
+  }
+  uint32_t* vtmp = nullptr;
+  if (passes > 1) {
+    TRY(ctx_alloc(c, &p, sizeof(uint32_t) * nnz, "radix values"));
+    tmp.add(p);
+    vtmp = static_cast<uint32_t*>(p);
+  }
+  // pass p writes its values to inv_pid when (passes - p) is even, so the
+  // last pass lands in inv_pid
+  auto vals_of = [&](int pass) { return ((passes - pass) % 2 == 0) ? c->d_inv_pid : vtmp; };
+  launch_radix_down_paths(c->stride, c->d_paths, R, c->T, shift, bits, offs, keys[0],
+                          vals_of(1), s);
+  HIPTRY(hipGetLastError(), "index pass 1");
+  const uint64_t tiles = radix_tiles_pairs(nnz);
+  for (int pass = 2; pass <= passes; ++pass) {
+    shift += bits;
+    bits = std::min(pass_bits, bits_total - shift);
+    const uint32_t* kin = keys[(pass - 2) % 2];
+    uint32_t* kout = keys[(pass - 1) % 2];
+    launch_radix_up_pairs(kin, nnz, shift, bits, hist, s);
+    launch_scan_u32_to_u64(hist, offs, (int64_t)(256 * tiles), stemp, s);
+    launch_radix_down_pairs(kin, vals_of(pass - 1), nnz, shift, bits, offs, kout, vals_of(pass),
+                            s);
+    HIPTRY(hipGetLastError(), "index pass");
+  }
+  launch_list_bounds(keys[(passes - 1) % 2], nnz, n, c->d_inv_ptr, s);
+  HIPTRY(hipGetLastError(), "index bounds");
   c->h_inv_ptr.resize((size_t)n + 1);
   HIPTRY(hipMemcpyAsync(c->h_inv_ptr.data(), c->d_inv_ptr, sizeof(uint64_t) * (size_t)(n + 1),
                         hipMemcpyDeviceToHost, s),
          "index offsets");
-  HIPTRY(hipStreamSynchronize(s), "index");
-  c->nnz = (int64_t)c->h_inv_ptr[n];
-  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)c->nnz, "index path ids"));
-  c->d_inv_pid = static_cast<uint32_t*>(p);
-  TRY(ctx_alloc(c, &p, sizeof(unsigned long long) * (size_t)n, "index cursors"));
-  tmp.add(p);
-  HIPTRY(hipMemcpyAsync(p, c->d_inv_ptr, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, s),
-         "index cursors");
-  launch_index_scatter(c->stride, c->d_paths, R, static_cast<unsigned long long*>(p),
-                       c->d_inv_pid, s);
-  HIPTRY(hipGetLastError(), "index scatter");
-  // sort each list
-  TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)n * 2 + 64, "list classes"));
-  tmp.add(p);
-  int32_t* mid = static_cast<int32_t*>(p);
-  int32_t* big = mid + n;
-  uint32_t* nctl = reinterpret_cast<uint32_t*>(big + n);
-  HIPTRY(hipMemsetAsync(nctl, 0, 16, s), "index");
-  launch_seg_sort_small(c->d_inv_ptr, n, c->d_inv_pid, mid, nctl, big, nctl + 1, s);
-  HIPTRY(hipGetLastError(), "index sort");
-  uint32_t hn[2];
-  HIPTRY(hipMemcpyAsync(hn, nctl, 8, hipMemcpyDeviceToHost, s), "index sort");
-  HIPTRY(hipStreamSynchronize(s), "index sort");
-  launch_seg_sort_mid(c->d_inv_ptr, mid, hn[0], c->d_inv_pid, s);
-  HIPTRY(hipGetLastError(), "index sort mid");
-  if (hn[1]) {
-    std::vector<int32_t> hbig(hn[1]);
-    HIPTRY(hipMemcpyAsync(hbig.data(), big, 4 * (size_t)hn[1], hipMemcpyDeviceToHost, s),
-           "index sort big");
-    HIPTRY(hipStreamSynchronize(s), "index sort big");
-    std::sort(hbig.begin(), hbig.end());
-    std::vector<SegBlock> blocks;
-    uint64_t maxlen = 0;
-    for (int32_t v : hbig) {
-      const uint64_t a = c->h_inv_ptr[v], len = c->h_inv_ptr[v + 1] - a;
-      maxlen = std::max(maxlen, len);
-      for (uint64_t off = 0; off < len; off += 4096)
-        blocks.push_back(SegBlock{a, (uint32_t)len, (uint32_t)off});
-    }
-    TRY(ctx_alloc(c, &p, sizeof(SegBlock) * blocks.size(), "sort blocks"));
-    tmp.add(p);
-    SegBlock* dblocks = static_cast<SegBlock*>(p);
-    HIPTRY(hipMemcpyAsync(dblocks, blocks.data(), sizeof(SegBlock) * blocks.size(),
-                          hipMemcpyHostToDevice, s),
-           "sort blocks");
-    const uint32_t nb = (uint32_t)blocks.size();
-    launch_seg_chunk_sort(dblocks, nb, c->d_inv_pid, s);
-    HIPTRY(hipGetLastError(), "index chunk sort");
-    TRY(ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)c->nnz, "merge buffer"));
-    tmp.add(p);
-    uint32_t* alt = static_cast<uint32_t*>(p);
-    uint32_t* src = c->d_inv_pid;
-    uint32_t* dst = alt;
-    for (uint64_t width = 4096; width < maxlen; width *= 2) {
-      launch_seg_merge(dblocks, nb, (uint32_t)width, src, dst, s);
-      HIPTRY(hipGetLastError(), "index merge");
-      std::swap(src, dst);
-    }
-    if (src != c->d_inv_pid) {
-      launch_seg_copy(dblocks, nb, src, c->d_inv_pid, s);
-      HIPTRY(hipGetLastError(), "index merge copy");
-    }
-    HIPTRY(hipStreamSynchronize(s), "index sort big");
-  }
   HIPTRY(hipStreamSynchronize(s), "index");
   return PANTHER_OK;
 }
@@ -503,8 +501,12 @@ extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64
   if (st) return st;
   c->d_paths = static_cast<int32_t*>(p);
   stage_begin(c, 0, c->stream);
-  launch_walk(stride, c->pfx64, c->d_vrec, c->d_pfx, c->d_col, c->d_vstart, c->nstart, T,
-              (uint64_t)R, seed, c->d_paths, c->stream);
+  if (c->pfx64)
+    launch_walk64(stride, c->d_vrec, static_cast<const uint64_t*>(c->d_pfx), c->d_col,
+                  c->d_vstart, c->nstart, T, (uint64_t)R, seed, c->d_paths, c->stream);
+  else
+    launch_walk32(stride, c->d_vrec, c->d_edge, c->d_guide, c->d_vstart, c->nstart, T,
+                  (uint64_t)R, seed, c->d_paths, c->stream);
   stage_end(c, 0, c->stream);
   st = ctx_hip(c, hipGetLastError(), "walk");
   if (!st) {

@@ -206,3 +206,60 @@ def test_errors_leave_context_usable(P, oracle, inputs, ba_state):
     qq = np.array([0, 5], np.int32)
     _check_topk(fresh.topk(qq, 10), oracle.topk(g.n, paths, inv_ptr, inv_pid, qq, 10), "after")
     fresh.close()
+
+
+@pytest.mark.parametrize("block,wgs,ta,tb", [
+    (512, 1, -1, -1), (256, 1, -1, -1), (512, 2, -1, -1), (256, 2, -1, -1),
+    (512, 1, 0, 0),     # every non-empty list goes to the dense hub tier
+    (256, 1, 4, 0),     # wave tier + hub tier
+    (512, 2, 1, 60),    # all three tiers, small tables
+])
+def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb):
+    g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
+    _say(f"case: batched tiers block={block} wgs={wgs} ta={ta} tb={tb}")
+    P.load_graph(g)
+    P.sample_paths(T, R, seed)
+    P.set_option("topk.form", 1)
+    P.set_option("batch.block", block)
+    P.set_option("batch.wgs_per_cu", wgs)
+    P.set_option("batch.tier_a", ta)
+    P.set_option("batch.tier_b", tb)
+    try:
+        qs = np.concatenate([inputs.queries_by_degree(g, 1500, 11),
+                             np.arange(0, g.n, 97, dtype=np.int32)])
+        for k in (1, 50, 300):
+            want = oracle.topk(g.n, paths, inv_ptr, inv_pid, qs, k)
+            _check_topk(P.topk(qs, k), want, f"tiers {block}/{wgs}/{ta}/{tb} k={k}")
+    finally:
+        for key, v in (("batch.block", 0), ("batch.wgs_per_cu", 0), ("batch.tier_a", -1),
+                       ("batch.tier_b", -1)):
+            P.set_option(key, v)
+
+
+def test_batched_graph_replays(P, oracle, inputs, rmat14):
+    """Repeated calls with the same buffers replay the captured graph; each
+    replay, with other device work and synchronisations in between, must
+    equal the oracle."""
+    import torch
+
+    g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
+    _say("case: batched graph replays")
+    P.load_graph(g)
+    P.sample_paths(T, R, seed)
+    P.set_option("topk.form", 1)
+    qs = inputs.queries_by_degree(g, 2000, 12)
+    want = oracle.topk(g.n, paths, inv_ptr, inv_pid, qs, 40)
+    dq = torch.from_numpy(qs).cuda()
+    out = (torch.empty((len(qs), 40), dtype=torch.int32, device="cuda"),
+           torch.empty((len(qs), 40), dtype=torch.uint32, device="cuda"),
+           torch.empty(len(qs), dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream().cuda_stream
+    x = torch.randn(1 << 20, device="cuda")
+    for rep in range(4):
+        for t in out:
+            t.fill_(7)
+        P.topk(dq, 40, out=out, stream=stream)
+        torch.cuda.synchronize()
+        _check_topk(tuple(t.cpu().numpy() for t in out), want, f"replay {rep}")
+        x = (x * 1.0001).sin()  # unrelated eager work between replays
+        torch.cuda.synchronize()
