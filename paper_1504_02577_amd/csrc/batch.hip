@@ -527,7 +527,7 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
 
 // Builds the plan for one configuration; returns the kernel arguments.
 static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int32_t* dq,
-                const std::vector<int32_t>& hq, int64_t nq, int32_t k, int32_t* d_ids,
+                const std::vector<uint64_t>& qlen, int64_t nq, int32_t k, int32_t* d_ids,
                 uint32_t* d_counts, int32_t* d_len, hipStream_t s, BatchArgs* out,
                 std::vector<int32_t>* host_items) {
   const Layout lay = layout_for(c, cfg);
@@ -541,8 +541,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   // load bound T * L <= table / 2
   std::vector<std::pair<uint64_t, int32_t>> A, B, C;
   for (int64_t i = 0; i < nq; ++i) {
-    const int32_t q = hq[i];
-    const uint64_t L = c->h_inv_ptr[q + 1] - c->h_inv_ptr[q];
+    const uint64_t L = qlen[i];
     if (L <= LA)
       A.push_back({L, (int32_t)i});
     else if (L <= LB)
@@ -619,7 +618,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   return PANTHER_OK;
 }
 
-int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<int32_t>& hq,
+int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen,
                      int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
                      hipStream_t s) {
   BatchState* b = state(c);
@@ -656,7 +655,7 @@ int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<int32_
       float best = 1e30f;
       BatchConfig best_cfg = cands[0];
       for (const BatchConfig& cfg : cands) {
-        st = plan(c, b, cfg, dq, hq, nq, k, d_ids, d_counts, d_len, s, &args, &items);
+        st = plan(c, b, cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, s, &args, &items);
         if (st) break;
         st = launch_batched(c, b, cfg, args, s, false);  // warm
         if (st) break;
@@ -683,7 +682,7 @@ int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<int32_
       b->tuned = true;
     }
   }
-  int st = plan(c, b, b->cfg, dq, hq, nq, k, d_ids, d_counts, d_len, s, &args, &items);
+  int st = plan(c, b, b->cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, s, &args, &items);
   if (st) return st;
   st = launch_batched(c, b, b->cfg, args, s, true);
   if (st) return st;

@@ -12,6 +12,12 @@
 struct BatchState;
 struct PPState;
 
+// Device buffer that keeps its allocation across calls and grows on demand.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
 struct panther_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -47,7 +53,9 @@ struct panther_ctx {
   uint64_t* d_inv_ptr = nullptr;
   uint32_t* d_inv_pid = nullptr;
   int64_t nnz = 0;
-  std::vector<uint64_t> h_inv_ptr;
+  // storage reused across sample_paths / query calls
+  DevBuf b_paths, b_inv_pid, b_inv_ptr, b_keys0, b_keys1, b_vtmp, b_hist, b_offs, b_stemp;
+  DevBuf b_qlen, b_queries, b_outs;
   // dense query scratch (plain form, hub queries)
   uint32_t* d_cnt = nullptr;
   int32_t* d_touched = nullptr;
@@ -71,6 +79,12 @@ struct panther_ctx {
 int ctx_fail(panther_ctx* c, int code, const char* fmt, ...);
 int ctx_hip(panther_ctx* c, hipError_t e, const char* what);
 int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what);
+// Makes b hold at least `bytes`; the contents are not preserved on growth.
+int ctx_ensure(panther_ctx* c, DevBuf& b, size_t bytes, const char* what);
+void ctx_release(DevBuf& b);
+// Path-list lengths of the queries, gathered on the device and copied back.
+int query_lengths(panther_ctx* c, const int32_t* dq, int64_t nq, hipStream_t s,
+                  std::vector<uint64_t>& len);
 void ctx_free(void* p);
 // Stage timing: stage i is bracketed by events 2i and 2i+1.
 void stage_begin(panther_ctx* c, int stage, hipStream_t s);
@@ -81,7 +95,7 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
                   std::vector<int32_t>& hq, const int32_t** dq, void** dq_owned);
 
 // batched form (batch.hip)
-int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<int32_t>& hq,
+int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen,
                      int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
                      hipStream_t s);
 int set_batch_option(panther_ctx* c, const std::string& key, int64_t value);

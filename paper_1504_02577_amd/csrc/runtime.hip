@@ -58,6 +58,25 @@ void ctx_free(void* p) {
   if (p) (void)hipFree(p);
 }
 
+int ctx_ensure(panther_ctx* c, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes <= b.cap && b.p) return PANTHER_OK;
+  ctx_free(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  void* p;
+  const int st = ctx_alloc(c, &p, bytes, what);
+  if (st) return st;
+  b.p = p;
+  b.cap = bytes;
+  return PANTHER_OK;
+}
+
+void ctx_release(DevBuf& b) {
+  ctx_free(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
 #define TRY(expr)                   \
   do {                              \
     int _st = (expr);               \
@@ -72,28 +91,33 @@ static void free_features(panther_ctx* c) {
   free_pp_state(c);
 }
 
-static void free_paths(panther_ctx* c) {
+// Drops the paths, index and everything derived from them.  The storage of
+// the paths and index is kept for the next sample_paths call unless
+// `release` is set (a new graph, or destroy).
+static void free_paths(panther_ctx* c, bool release) {
   free_features(c);
-  free_batch_state(c);
-  ctx_free(c->d_paths);
-  ctx_free(c->d_inv_ptr);
-  ctx_free(c->d_inv_pid);
-  ctx_free(c->d_cnt);
-  ctx_free(c->d_touched);
-  ctx_free(c->d_ctl);
   c->d_paths = nullptr;
   c->d_inv_ptr = nullptr;
   c->d_inv_pid = nullptr;
-  c->d_cnt = nullptr;
-  c->d_touched = nullptr;
-  c->d_ctl = nullptr;
-  c->h_inv_ptr.clear();
   c->has_paths = false;
   c->nnz = 0;
+  if (release) {
+    free_batch_state(c);
+    for (DevBuf* b : {&c->b_paths, &c->b_inv_pid, &c->b_inv_ptr, &c->b_keys0, &c->b_keys1,
+                      &c->b_vtmp, &c->b_hist, &c->b_offs, &c->b_stemp, &c->b_qlen,
+                      &c->b_queries, &c->b_outs})
+      ctx_release(*b);
+    ctx_free(c->d_cnt);
+    ctx_free(c->d_touched);
+    ctx_free(c->d_ctl);
+    c->d_cnt = nullptr;
+    c->d_touched = nullptr;
+    c->d_ctl = nullptr;
+  }
 }
 
 static void free_graph(panther_ctx* c) {
-  free_paths(c);
+  free_paths(c, true);
   ctx_free(c->d_col);
   ctx_free(c->d_vrec);
   ctx_free(c->d_pfx);
@@ -411,24 +435,20 @@ static int build_index(panther_ctx* c) {
   hipStream_t s = c->stream;
   const int32_t n = c->n;
   const uint64_t R = (uint64_t)c->R;
-  Temp tmp;
-  void* p;
   int bits_total = 1;
   while (bits_total < 31 && (int64_t(1) << bits_total) < (int64_t)n) ++bits_total;
   const int passes = (bits_total + kRadixPassBits - 1) / kRadixPassBits;
   const int pass_bits = (bits_total + passes - 1) / passes;
   const uint64_t tiles1 = radix_tiles_paths(R, c->T);
+  const uint64_t nnz_cap = R * (uint64_t)(c->T + 1);
+  const uint64_t hist_cap = 256 * std::max<uint64_t>(tiles1, radix_tiles_pairs(nnz_cap));
+  TRY(ctx_ensure(c, c->b_hist, sizeof(uint32_t) * hist_cap, "radix histograms"));
+  TRY(ctx_ensure(c, c->b_offs, sizeof(uint64_t) * (hist_cap + 1), "radix offsets"));
+  TRY(ctx_ensure(c, c->b_stemp, scan_temp_bytes((int64_t)hist_cap), "scan temp"));
+  uint32_t* hist = static_cast<uint32_t*>(c->b_hist.p);
+  uint64_t* offs = static_cast<uint64_t*>(c->b_offs.p);
+  void* stemp = c->b_stemp.p;
   // pass 1: histograms straight from the path rows
-  const uint64_t hist_cap = 256 * std::max<uint64_t>(tiles1, radix_tiles_pairs(R * (c->T + 1)));
-  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * hist_cap, "radix histograms"));
-  tmp.add(p);
-  uint32_t* hist = static_cast<uint32_t*>(p);
-  TRY(ctx_alloc(c, &p, sizeof(uint64_t) * (hist_cap + 1), "radix offsets"));
-  tmp.add(p);
-  uint64_t* offs = static_cast<uint64_t*>(p);
-  TRY(ctx_alloc(c, &p, scan_temp_bytes((int64_t)hist_cap), "scan temp"));
-  tmp.add(p);
-  void* stemp = p;
   int shift = 0;
   int bits = std::min(pass_bits, bits_total - shift);
   launch_radix_up_paths(c->stride, c->d_paths, R, c->T, shift, bits, hist, s);
@@ -438,22 +458,16 @@ static int build_index(panther_ctx* c) {
   HIPTRY(hipMemcpyAsync(&nnz, offs + 256 * tiles1, 8, hipMemcpyDeviceToHost, s), "index");
   HIPTRY(hipStreamSynchronize(s), "index");
   c->nnz = (int64_t)nnz;
-  TRY(ctx_alloc(c, &p, sizeof(uint32_t) * nnz, "index path ids"));
-  c->d_inv_pid = static_cast<uint32_t*>(p);
-  TRY(ctx_alloc(c, &p, sizeof(uint64_t) * (size_t)(n + 1), "index offsets"));
-  c->d_inv_ptr = static_cast<uint64_t*>(p);
-  uint32_t* keys[2];
-  for (int i = 0; i < 2; ++i) {
-    TRY(ctx_alloc(c, &p, sizeof(uint32_t) * nnz, "radix keys"));
-    tmp.add(p);
-    keys[i] = static_cast<uint32_t*>(p);
-  }
-  uint32_t* vtmp = nullptr;
-  if (passes > 1) {
-    TRY(ctx_alloc(c, &p, sizeof(uint32_t) * nnz, "radix values"));
-    tmp.add(p);
-    vtmp = static_cast<uint32_t*>(p);
-  }
+  TRY(ctx_ensure(c, c->b_inv_pid, sizeof(uint32_t) * nnz, "index path ids"));
+  TRY(ctx_ensure(c, c->b_inv_ptr, sizeof(uint64_t) * (size_t)(n + 1), "index offsets"));
+  TRY(ctx_ensure(c, c->b_keys0, sizeof(uint32_t) * nnz, "radix keys"));
+  TRY(ctx_ensure(c, c->b_keys1, sizeof(uint32_t) * nnz, "radix keys"));
+  if (passes > 1) TRY(ctx_ensure(c, c->b_vtmp, sizeof(uint32_t) * nnz, "radix values"));
+  c->d_inv_pid = static_cast<uint32_t*>(c->b_inv_pid.p);
+  c->d_inv_ptr = static_cast<uint64_t*>(c->b_inv_ptr.p);
+  uint32_t* keys[2] = {static_cast<uint32_t*>(c->b_keys0.p),
+                       static_cast<uint32_t*>(c->b_keys1.p)};
+  uint32_t* vtmp = static_cast<uint32_t*>(c->b_vtmp.p);
   // pass p writes its values to inv_pid when (passes - p) is even, so the
   // last pass lands in inv_pid
   auto vals_of = [&](int pass) { return ((passes - pass) % 2 == 0) ? c->d_inv_pid : vtmp; };
@@ -474,11 +488,6 @@ static int build_index(panther_ctx* c) {
   }
   launch_list_bounds(keys[(passes - 1) % 2], nnz, n, c->d_inv_ptr, s);
   HIPTRY(hipGetLastError(), "index bounds");
-  c->h_inv_ptr.resize((size_t)n + 1);
-  HIPTRY(hipMemcpyAsync(c->h_inv_ptr.data(), c->d_inv_ptr, sizeof(uint64_t) * (size_t)(n + 1),
-                        hipMemcpyDeviceToHost, s),
-         "index offsets");
-  HIPTRY(hipStreamSynchronize(s), "index");
   return PANTHER_OK;
 }
 
@@ -489,7 +498,7 @@ extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64
   if (T < 1 || T > 63) return ctx_fail(c, PANTHER_EINVAL, "T must lie in [1, 63]");
   if (R < 1 || R >= (int64_t(1) << 32)) return ctx_fail(c, PANTHER_EINVAL, "R must lie in [1, 2^32)");
   if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, PANTHER_EDEVICE, "hipSetDevice");
-  free_paths(c);
+  free_paths(c, false);
   int stride = 4;
   while (stride < T + 1) stride <<= 1;
   c->T = T;
@@ -497,9 +506,9 @@ extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64
   c->seed = seed;
   c->stride = stride;
   void* p;
-  int st = ctx_alloc(c, &p, sizeof(int32_t) * (size_t)R * (size_t)stride, "paths");
+  int st = ctx_ensure(c, c->b_paths, sizeof(int32_t) * (size_t)R * (size_t)stride, "paths");
   if (st) return st;
-  c->d_paths = static_cast<int32_t*>(p);
+  c->d_paths = static_cast<int32_t*>(c->b_paths.p);
   stage_begin(c, 0, c->stream);
   if (c->pfx64)
     launch_walk64(stride, c->d_vrec, static_cast<const uint64_t*>(c->d_pfx), c->d_col,
@@ -514,7 +523,7 @@ extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64
     st = build_index(c);
     stage_end(c, 1, c->stream);
   }
-  if (!st) {
+  if (!st && !c->d_cnt) {
     // dense per-vertex scratch of the query kernels
     st = ctx_alloc(c, &p, sizeof(uint32_t) * (size_t)c->n, "query counters");
     if (!st) {
@@ -531,10 +540,10 @@ extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64
                    "query scratch");
     }
     if (!st) st = ctx_hip(c, hipMemsetAsync(c->d_ctl, 0, 64, c->stream), "query scratch");
-    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "sample_paths");
   }
+  if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "sample_paths");
   if (st) {
-    free_paths(c);
+    free_paths(c, true);
     return st;
   }
   c->has_paths = true;
@@ -618,6 +627,20 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
   return PANTHER_OK;
 }
 
+int query_lengths(panther_ctx* c, const int32_t* dq, int64_t nq, hipStream_t s,
+                  std::vector<uint64_t>& len) {
+  TRY(ctx_ensure(c, c->b_qlen, sizeof(uint64_t) * (size_t)std::max<int64_t>(nq, 1),
+                 "query lengths"));
+  launch_query_lengths(c->d_inv_ptr, dq, nq, static_cast<uint64_t*>(c->b_qlen.p), s);
+  HIPTRY(hipGetLastError(), "query lengths");
+  len.resize((size_t)nq);
+  HIPTRY(hipMemcpyAsync(len.data(), c->b_qlen.p, sizeof(uint64_t) * (size_t)nq,
+                        hipMemcpyDeviceToHost, s),
+         "query lengths");
+  HIPTRY(hipStreamSynchronize(s), "query lengths");
+  return PANTHER_OK;
+}
+
 // ---------------------------------------------------------------------------
 // topk_similar (a4 + a5; a8 in the batched form)
 // ---------------------------------------------------------------------------
@@ -658,17 +681,17 @@ extern "C" int panther_topk_similar(panther_ctx* c, const int32_t* queries, int6
   }
   TRY(order_begin(c, s));
   stage_begin(c, 2, s);
+  std::vector<uint64_t> qlen;
+  TRY(query_lengths(c, dq, nq, s, qlen));
   if (c->topk_form == PANTHER_FORM_PLAIN) {
     TopkScratch sc{c->d_cnt, c->d_touched, c->d_ctl};
     for (int64_t i = 0; i < nq; ++i) {
-      const int32_t q = hq[i];
-      launch_topk_plain(c->stride, q, c->d_inv_ptr, c->d_inv_pid, c->d_paths,
-                        c->h_inv_ptr[q + 1] - c->h_inv_ptr[q], sc, k, d_ids + i * k,
-                        d_cnt + i * k, d_len + i, s);
+      launch_topk_plain(c->stride, hq[i], c->d_inv_ptr, c->d_inv_pid, c->d_paths, qlen[i], sc, k,
+                        d_ids + i * k, d_cnt + i * k, d_len + i, s);
     }
     HIPTRY(hipGetLastError(), "topk plain");
   } else {
-    TRY(run_topk_batched(c, dq, hq, nq, k, d_ids, d_cnt, d_len, s));
+    TRY(run_topk_batched(c, dq, qlen, nq, k, d_ids, d_cnt, d_len, s));
   }
   stage_end(c, 2, s);
   TRY(order_end(c, s));

@@ -86,7 +86,24 @@ k_topk_plain(int32_t q, const uint64_t* __restrict__ inv_ptr, const uint32_t* __
   }
 }
 
+__global__ void k_query_lengths(const uint64_t* __restrict__ inv_ptr,
+                                const int32_t* __restrict__ queries, int64_t nq,
+                                uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < nq) {
+    const int32_t q = queries[i];
+    out[i] = inv_ptr[q + 1] - inv_ptr[q];
+  }
+}
+
 }  // namespace
+
+void launch_query_lengths(const uint64_t* inv_ptr, const int32_t* queries, int64_t nq,
+                          uint64_t* out, hipStream_t s) {
+  if (nq > 0)
+    k_query_lengths<<<(unsigned)((nq + kBlock - 1) / kBlock), kBlock, 0, s>>>(inv_ptr, queries, nq,
+                                                                            out);
+}
 
 void launch_topk_plain(int stride, int32_t q, const uint64_t* inv_ptr, const uint32_t* inv_pid,
                        const int32_t* paths, uint64_t list_len, TopkScratch sc, int32_t k,
