@@ -55,6 +55,10 @@ struct BatchArgs {
   int32_t* out_ids;
   uint32_t* out_counts;
   int32_t* out_len;
+  // feature mode (Panther++): row qi of theta gets count / R of the k = D
+  // largest counts, zero-padded; out_ids/out_counts/out_len unused
+  float* theta;
+  float fR;
 };
 
 __device__ __forceinline__ uint32_t hash_slot(int32_t v, uint32_t mask) {
@@ -111,6 +115,11 @@ __device__ __forceinline__ void for_each_candidate(const BatchArgs& A, int32_t q
 __device__ __forceinline__ void write_row(const BatchArgs& A, int32_t qi, const uint64_t* keys,
                                           int m, int t, int nthr) {
   const int k = A.k;
+  if (A.theta) {
+    for (int j = t; j < k; j += nthr)
+      A.theta[(int64_t)qi * k + j] = j < m ? (float)key_count(keys[j]) / A.fR : 0.0f;
+    return;
+  }
   for (int j = t; j < k; j += nthr) {
     const bool ok = j < m;
     A.out_ids[(int64_t)qi * k + j] = ok ? key_vertex(keys[j]) : -1;
@@ -528,7 +537,7 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
 // Builds the plan for one configuration; returns the kernel arguments.
 static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int32_t* dq,
                 const std::vector<uint64_t>& qlen, int64_t nq, int32_t k, int32_t* d_ids,
-                uint32_t* d_counts, int32_t* d_len, hipStream_t s, BatchArgs* out,
+                uint32_t* d_counts, int32_t* d_len, float* theta, hipStream_t s, BatchArgs* out,
                 std::vector<int32_t>* host_items) {
   const Layout lay = layout_for(c, cfg);
   const uint64_t T = (uint64_t)c->T;
@@ -614,6 +623,8 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   a.out_ids = d_ids;
   a.out_counts = d_counts;
   a.out_len = d_len;
+  a.theta = theta;
+  a.fR = (float)c->R;
   *out = a;
   return PANTHER_OK;
 }
@@ -621,6 +632,12 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
 int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen,
                      int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
                      hipStream_t s) {
+  return run_batched(c, dq, qlen, nq, k, d_ids, d_counts, d_len, nullptr, s);
+}
+
+int run_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen, int64_t nq,
+                int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
+                hipStream_t s) {
   BatchState* b = state(c);
   std::vector<int32_t> items;
   BatchArgs args;
@@ -635,10 +652,11 @@ int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64
     b->cfg = f;
     b->tuned = true;
   }
+  char key[256];
+  snprintf(key, sizeof key, "gfx950:n%d:T%d:R%lld:nq%lld:k%d:cu%d:f%d", c->n, c->T,
+           (long long)c->R, (long long)nq, k, c->num_cus, theta ? 1 : 0);
+  if (b->tuned && !(b->forced_block || b->forced_wgs) && b->tune_key != key) b->tuned = false;
   if (!b->tuned) {
-    char key[256];
-    snprintf(key, sizeof key, "gfx950:n%d:T%d:R%lld:nq%lld:k%d:cu%d", c->n, c->T,
-             (long long)c->R, (long long)nq, k, c->num_cus);
     b->tune_key = key;
     BatchConfig cached;
     if (tune_lookup(b->tune_key, &cached)) {
@@ -655,7 +673,7 @@ int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64
       float best = 1e30f;
       BatchConfig best_cfg = cands[0];
       for (const BatchConfig& cfg : cands) {
-        st = plan(c, b, cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, s, &args, &items);
+        st = plan(c, b, cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, theta, s, &args, &items);
         if (st) break;
         st = launch_batched(c, b, cfg, args, s, false);  // warm
         if (st) break;
@@ -682,7 +700,7 @@ int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64
       b->tuned = true;
     }
   }
-  int st = plan(c, b, b->cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, s, &args, &items);
+  int st = plan(c, b, b->cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, theta, s, &args, &items);
   if (st) return st;
   st = launch_batched(c, b, b->cfg, args, s, true);
   if (st) return st;

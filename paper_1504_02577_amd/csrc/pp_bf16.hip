@@ -1,0 +1,379 @@
+// Panther++ nearest neighbours, precision form: a BF16 matrix-core pass
+// keeps a candidate pool per query, then an exact FP64 rerank of the pool.
+//
+// 1. Feature rows are scaled by R (so theta * R is the integer count c) and
+//    rounded to bfloat16, zero-padded to 64 columns; counts up to 256 are
+//    exact in bfloat16, and their products and sums stay exact in the FP32
+//    accumulator.  FP32 row norms come from the same bfloat16 values.
+// 2. Pool pass: a work-group owns 128 queries for the whole scan and
+//    streams every database row in chunks of 64.  Each wavefront computes
+//    128 x 16 dot products per chunk with v_mfma_f32_16x16x32_bf16 (query
+//    operands stay in registers for the whole scan), turns them into
+//    d2~ = |b_q|^2 + |b_v|^2 - 2 <b_q, b_v>, and appends (d2~, v) keys below
+//    the query's threshold to that query's pool buffer in global memory.
+//    After each chunk, buffers that could overflow on the next chunk are
+//    sorted by one wavefront and cut back to the pool size P, which sets the
+//    threshold to the P-th best key.  Keys are (float bits of d2~, id), so
+//    ties break by id exactly as in the exact order.
+// 3. Rerank: one wavefront per query recomputes the exact FP64 squared
+//    distance (one fma per coordinate, coordinate order) of every pool
+//    member, sorts by (d2, id) and writes the first k.  It also records how
+//    many of the final ids the pool order already had in its first k, and
+//    the relative error of d2~ / R^2 against d2 on the returned neighbours.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/panther.h"
+#include "common.h"
+#include "runtime.h"
+
+using namespace panther;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kDP = 64;        // padded feature width in bfloat16
+constexpr int kQW = 128;       // queries per work-group
+constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
+constexpr int kTiles = kQW / 16;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void wsync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// bf16 rows (scaled by s) and their FP32 norms
+__global__ void __launch_bounds__(kBlock)
+k_bf16_rows(const float* __restrict__ theta, int32_t n, int32_t D, float s,
+            __bf16* __restrict__ out, float* __restrict__ norm) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  float acc = 0.f;
+  for (int d = 0; d < kDP; ++d) {
+    const __bf16 b = d < D ? (__bf16)(theta[(int64_t)v * D + d] * s) : (__bf16)0.f;
+    out[(int64_t)v * kDP + d] = b;
+    const float f = (float)b;
+    acc = fmaf(f, f, acc);
+  }
+  norm[v] = acc;
+}
+
+__device__ __forceinline__ uint64_t pool_key(float d2, int32_t v) {
+  const float c = d2 > 0.f ? d2 : 0.f;
+  return ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)v;
+}
+
+// ascending bitonic sort of cnt keys (padded with ~0) by one wavefront
+__device__ void wave_sort_keys(uint64_t* a, int cnt) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int P = 2;
+  while (P < cnt) P <<= 1;
+  for (int i = cnt + lane; i < P; i += kWave) a[i] = ~0ull;
+  wsync();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (P >> 1); i += kWave) {
+        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const uint64_t x = a[lo], y = a[hi];
+        if ((x > y) == asc) {
+          a[lo] = y;
+          a[hi] = x;
+        }
+      }
+      wsync();
+    }
+  }
+}
+
+struct PoolArgs {
+  const __bf16* rows;    // [n][64]
+  const float* norm;     // [n]
+  int32_t n;
+  const int32_t* queries;
+  int64_t nq;
+  int32_t P;             // pool size (power of two, <= 1024)
+  int32_t cap;           // buffer entries per query: max(2P, P + 64)
+  uint64_t* buf;         // [nq][cap] pool buffers
+  int32_t* pool_ids;     // [nq][P] result, ascending key order, -1 padded
+  float* pool_d2;        // [nq][P] approximate squared distances
+};
+
+__global__ void __launch_bounds__(kBlock)
+k_pp_pool(PoolArgs A) {
+  __shared__ uint32_t cnt[kQW];
+  __shared__ uint64_t tau[kQW];
+  __shared__ int32_t qid[kQW];
+  __shared__ float qn[kQW];
+  __shared__ uint64_t sortbuf[kBlock / kWave][2048];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t q0 = (int64_t)blockIdx.x * kQW;
+  const int P = A.P, cap = A.cap;
+  for (int i = threadIdx.x; i < kQW; i += kBlock) {
+    const int32_t q = q0 + i < A.nq ? A.queries[q0 + i] : -1;
+    qid[i] = q;
+    qn[i] = q >= 0 ? A.norm[q] : 0.f;
+    cnt[i] = 0u;
+    tau[i] = ~0ull;
+  }
+  __syncthreads();
+  // query operands: tile m, k-step ks -> 8 bf16 of row (m*16 + l%16)
+  bf16x8 a[kTiles][2];
+#pragma unroll
+  for (int m = 0; m < kTiles; ++m) {
+    const int32_t q = qid[m * 16 + (lane & 15)];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      if (q >= 0) {
+        a[m][ks] = *reinterpret_cast<const bf16x8*>(A.rows + (int64_t)q * kDP + ks * 32 +
+                                                    8 * (lane >> 4));
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[m][ks][j] = (__bf16)0.f;
+      }
+    }
+  }
+  for (int64_t cb = 0; cb < A.n; cb += kChunk) {
+    const int64_t v = cb + wid * 16 + (lane & 15);
+    const bool vok = v < A.n;
+    bf16x8 b[2];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      if (vok) {
+        b[ks] = *reinterpret_cast<const bf16x8*>(A.rows + v * kDP + ks * 32 + 8 * (lane >> 4));
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) b[ks][j] = (__bf16)0.f;
+      }
+    }
+    const float nv = vok ? A.norm[v] : 0.f;
+    floatx4 acc[kTiles];
+#pragma unroll
+    for (int m = 0; m < kTiles; ++m) {
+      acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][0], b[0], acc[m], 0, 0, 0);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][1], b[1], acc[m], 0, 0, 0);
+    }
+    if (vok) {
+#pragma unroll
+      for (int m = 0; m < kTiles; ++m) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ql = m * 16 + 4 * (lane >> 4) + r;
+          const float d2 = qn[ql] + nv - 2.f * acc[m][r];
+          const uint64_t key = pool_key(d2, (int32_t)v);
+          if (key < tau[ql] && qid[ql] >= 0 && qid[ql] != (int32_t)v) {
+            const uint32_t pos = atomicAdd(&cnt[ql], 1u);
+            A.buf[(q0 + ql) * cap + pos] = key;
+          }
+        }
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+    // cut back buffers that the next chunk could overflow (it adds at most
+    // kChunk keys per query)
+    for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
+      const int c = (int)cnt[ql];
+      if (c > cap - kChunk && c > P) {
+        uint64_t* g = A.buf + (q0 + ql) * cap;
+        uint64_t* sb = sortbuf[wid];
+        for (int i = lane; i < c; i += kWave)
+          sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wsync();
+        wave_sort_keys(sb, c);
+        for (int i = lane; i < P; i += kWave) g[i] = sb[i];
+        if (lane == 0) {
+          cnt[ql] = (uint32_t)P;
+          tau[ql] = sb[P - 1];
+        }
+        wsync();
+      }
+    }
+    __threadfence_block();
+    __syncthreads();
+  }
+  // final pools
+  for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
+    if (qid[ql] < 0) continue;
+    const int c = (int)cnt[ql];
+    uint64_t* g = A.buf + (q0 + ql) * cap;
+    uint64_t* sb = sortbuf[wid];
+    for (int i = lane; i < c; i += kWave)
+      sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    wsync();
+    wave_sort_keys(sb, c);
+    for (int i = lane; i < P; i += kWave) {
+      const bool ok = i < c;
+      A.pool_ids[(q0 + ql) * P + i] = ok ? (int32_t)(uint32_t)sb[i] : -1;
+      A.pool_d2[(q0 + ql) * P + i] = ok ? __uint_as_float((uint32_t)(sb[i] >> 32)) : INFINITY;
+    }
+    wsync();
+  }
+}
+
+struct RerankArgs {
+  const float* theta;    // [n][D]
+  int32_t D;
+  const int32_t* queries;
+  int64_t nq;
+  int32_t P, k;
+  const int32_t* pool_ids;
+  const float* pool_d2;
+  float inv_s2;          // 1 / s^2: scale of d2~ back to theta units
+  int32_t* out_ids;
+  double* out_dist;
+  unsigned long long* stat_hits;   // sum over queries of pre-rerank hits
+  unsigned long long* stat_err;    // max relative error (bits of a double >= 0)
+  unsigned long long* stat_ret;    // sum over queries of returned neighbours
+};
+
+// one wavefront per query
+__global__ void __launch_bounds__(kBlock)
+k_pp_rerank(RerankArgs A) {
+  __shared__ double sd[kBlock / kWave][1024];
+  __shared__ int32_t sv[kBlock / kWave][1024];
+  __shared__ float sa[kBlock / kWave][1024];
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + wid;
+  if (qi >= A.nq) return;
+  const int32_t q = A.queries[qi];
+  const float* tq = A.theta + (int64_t)q * A.D;
+  const int P = A.P;
+  double* d = sd[wid];
+  int32_t* v = sv[wid];
+  float* ap = sa[wid];
+  for (int i = lane; i < P; i += kWave) {
+    const int32_t c = A.pool_ids[qi * P + i];
+    double s = INFINITY;
+    if (c >= 0) {
+      const float* tv = A.theta + (int64_t)c * A.D;
+      s = 0.0;
+      for (int j = 0; j < A.D; ++j) {
+        const double delta = (double)tq[j] - (double)tv[j];
+        s = fma(delta, delta, s);
+      }
+    }
+    d[i] = s;
+    v[i] = c >= 0 ? c : 0x7FFFFFFF;
+    ap[i] = A.pool_d2[qi * P + i];
+  }
+  wsync();
+  // pre-rerank top-k ids are pool entries 0..k-1 (pool is in key order)
+  // count valid entries
+  int valid = 0;
+  for (int i = lane; i < P; i += kWave) valid += A.pool_ids[qi * P + i] >= 0 ? 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) valid += __shfl_xor(valid, off, kWave);
+  // sort (d, v) ascending; the approximate values ride along
+  int PP = 2;
+  while (PP < P) PP <<= 1;
+  for (int size = 2; size <= PP; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = lane; i < (PP >> 1); i += kWave) {
+        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const double x = d[lo], y = d[hi];
+        const int32_t xv = v[lo], yv = v[hi];
+        const bool gt = x > y || (x == y && xv > yv);
+        if (gt == asc) {
+          d[lo] = y;
+          d[hi] = x;
+          v[lo] = yv;
+          v[hi] = xv;
+          const float t = ap[lo];
+          ap[lo] = ap[hi];
+          ap[hi] = t;
+        }
+      }
+      wsync();
+    }
+  }
+  const int k = A.k;
+  const int m = valid < k ? valid : k;
+  unsigned hits = 0;
+  double err = 0.0;
+  for (int j = lane; j < k; j += kWave) {
+    const bool ok = j < m;
+    A.out_ids[qi * k + j] = ok ? v[j] : -1;
+    A.out_dist[qi * k + j] = ok ? sqrt(d[j]) : INFINITY;
+    if (ok) {
+      // was this id within the first k of the pool order?
+      for (int i = 0; i < m; ++i) hits += (A.pool_ids[qi * P + i] == v[j]) ? 1u : 0u;
+      const double approx = (double)ap[j] * (double)A.inv_s2;
+      const double den = d[j] > (double)A.inv_s2 ? d[j] : (double)A.inv_s2;
+      const double e = fabs(approx - d[j]) / den;
+      err = e > err ? e : err;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    hits += __shfl_xor(hits, off, kWave);
+    const double o = __shfl_xor(err, off, kWave);
+    err = o > err ? o : err;
+  }
+  if (lane == 0) {
+    atomicAdd(A.stat_ret, (unsigned long long)m);
+    atomicAdd(A.stat_hits, (unsigned long long)hits);
+    atomicMax(A.stat_err, (unsigned long long)__double_as_longlong(err));
+  }
+}
+
+}  // namespace
+
+namespace panther {
+
+int run_pp_bf16(panther_ctx* c, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
+                int32_t* d_ids, double* d_dist, hipStream_t s) {
+  PPState* pp = c->pp;
+  if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
+  // pool: at least the option and at least 4k (margin for the bfloat16
+  // rounding at the pool boundary), a power of two, at most 1024
+  int P = 32;
+  while (P < c->pp_pool || P < 4 * k) P <<= 1;
+  if (P > 1024) P = 1024;
+  const int cap = std::max(2 * P, P + kChunk);
+  const float scale = (float)c->R;
+  if (pp->bf16_D != D) {
+    TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)c->n * kDP, "bf16 rows"));
+    TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)c->n, "bf16 norms"));
+    k_bf16_rows<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        c->d_theta, c->n, D, scale, static_cast<__bf16*>(pp->b_bf16.p),
+        static_cast<float*>(pp->b_norm.p));
+    HIPTRY(hipGetLastError(), "bf16 rows");
+    pp->bf16_D = D;
+  }
+  const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * cap;
+  const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
+  TRY(ctx_ensure(c, pp->b_pool, buf_bytes + ids_bytes, "pools"));
+  TRY(ctx_ensure(c, pp->b_stats, 64, "pp stats"));
+  uint64_t* buf = static_cast<uint64_t*>(pp->b_pool.p);
+  int32_t* pool_ids = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(buf) + buf_bytes);
+  float* pool_d2 = reinterpret_cast<float*>(pool_ids + (size_t)nq * P);
+  HIPTRY(hipMemsetAsync(pp->b_stats.p, 0, 64, s), "pp stats");
+  PoolArgs pa{static_cast<const __bf16*>(pp->b_bf16.p), static_cast<const float*>(pp->b_norm.p),
+              c->n, dq, nq, P, cap, buf, pool_ids, pool_d2};
+  k_pp_pool<<<(unsigned)((nq + kQW - 1) / kQW), kBlock, 0, s>>>(pa);
+  HIPTRY(hipGetLastError(), "pp pool");
+  unsigned long long* st = static_cast<unsigned long long*>(pp->b_stats.p);
+  RerankArgs ra{c->d_theta, D, dq, nq, P, k, pool_ids, pool_d2,
+                1.0f / (scale * scale), d_ids, d_dist, st, st + 1, st + 2};
+  k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, 0, s>>>(ra);
+  HIPTRY(hipGetLastError(), "pp rerank");
+  unsigned long long hs[3];
+  HIPTRY(hipMemcpyAsync(hs, st, 24, hipMemcpyDeviceToHost, s), "pp stats");
+  HIPTRY(hipStreamSynchronize(s), "pp stats");
+  pp->have_stats = true;
+  pp->mean_pre_recall = hs[2] ? (double)hs[0] / (double)hs[2] : 1.0;
+  double e;
+  std::memcpy(&e, &hs[1], sizeof e);
+  pp->max_rel_err = e;
+  return PANTHER_OK;
+}
+
+}  // namespace panther

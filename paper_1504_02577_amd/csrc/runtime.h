@@ -10,12 +10,20 @@
 #include "kernels.h"
 
 struct BatchState;
-struct PPState;
 
 // Device buffer that keeps its allocation across calls and grows on demand.
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+};
+
+// Panther++ state: bf16 copy of theta, pools, statistics.
+struct PPState {
+  DevBuf b_ids, b_bf16, b_norm, b_pool, b_iota, b_out, b_stats;
+  int32_t bf16_D = 0;
+  bool have_stats = false;
+  double max_rel_err = 0.0;
+  double mean_pre_recall = 0.0;
 };
 
 struct panther_ctx {
@@ -76,6 +84,13 @@ struct panther_ctx {
   PPState* pp = nullptr;
 };
 
+#define TRY(expr)                      \
+  do {                                 \
+    int _st = (expr);                  \
+    if (_st != PANTHER_OK) return _st; \
+  } while (0)
+#define HIPTRY(expr, what) TRY(ctx_hip(c, (expr), what))
+
 int ctx_fail(panther_ctx* c, int code, const char* fmt, ...);
 int ctx_hip(panther_ctx* c, hipError_t e, const char* what);
 int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what);
@@ -98,8 +113,14 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
 int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen,
                      int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
                      hipStream_t s);
+// Generic batched pass: with theta != nullptr it writes Panther++ feature
+// rows (k = D) instead of ids/counts.
+int run_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen, int64_t nq,
+                int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
+                hipStream_t s);
 int set_batch_option(panther_ctx* c, const std::string& key, int64_t value);
 void free_batch_state(panther_ctx* c);
 
 // Panther++ (pp.hip)
 void free_pp_state(panther_ctx* c);
+int ensure_features(panther_ctx* c, int32_t D, hipStream_t s);

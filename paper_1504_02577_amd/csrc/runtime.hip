@@ -77,12 +77,6 @@ void ctx_release(DevBuf& b) {
   b.cap = 0;
 }
 
-#define TRY(expr)                   \
-  do {                              \
-    int _st = (expr);               \
-    if (_st != PANTHER_OK) return _st; \
-  } while (0)
-#define HIPTRY(expr, what) TRY(ctx_hip(c, (expr), what))
 
 static void free_features(panther_ctx* c) {
   ctx_free(c->d_theta);
