@@ -182,6 +182,60 @@ int panther_stage_times(panther_ctx *ctx, double out_ms[5]);
 /* Blocks until all work queued on the context's stream is done. */
 int panther_synchronize(panther_ctx *ctx);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching over the resident paths, index and features.
+ * Not from the paper, which answers one query at a time; it serves the
+ * queries of Problem 1 (Panther) and of Sec. 3.3 (Panther++) as they arrive.
+ * ------------------------------------------------------------------------ */
+#define PANTHER_SERVER_KMAX 256
+
+typedef struct panther_server panther_server;
+
+typedef struct panther_result {
+  uint64_t tag;          /* the caller's tag from panther_server_submit */
+  int32_t kind;          /* 0 Panther, 1 Panther++ */
+  int32_t query;         /* query vertex */
+  int32_t k;             /* k asked */
+  int32_t len;           /* entries filled (<= k) */
+  int32_t status;        /* PANTHER_OK or the error of the batch */
+  int32_t pad_;
+  double latency_ms;     /* submission to completion */
+  int32_t ids[PANTHER_SERVER_KMAX];     /* -1 padded */
+  double scores[PANTHER_SERVER_KMAX];   /* Panther: count c (S = c / R);
+                                           Panther++: Euclidean distance */
+} panther_result;
+
+/* Starts serving on a context that has paths (and, for Panther++ requests,
+ * computes the D-dimensional features first; D = 0 disables Panther++).
+ * `lanes` (1..8) work streams run batches concurrently; a batch holds at
+ * most max_batch requests; a request is admitted only while the in-flight
+ * estimate (its outputs, plus its candidate pool for Panther++) stays within
+ * mem_budget_bytes.  While the server runs, the context must not be used by
+ * other calls.  Errors: ESTATE (no paths), EINVAL, ENOMEM, EDEVICE. */
+int panther_server_start(panther_ctx *ctx, int64_t mem_budget_bytes,
+                         int32_t max_batch, int32_t lanes, int32_t D,
+                         panther_server **out);
+
+/* Queues a request (thread-safe): kind 0 = Panther top-k of q (k <= 256),
+ * kind 1 = Panther++ top-k of q (k <= 256).  Errors: EINVAL, ERANGE (q
+ * outside [0, n)), ESTATE (stopping, or kind 1 with D = 0), ENOMEM (the
+ * request alone exceeds the budget). */
+int panther_server_submit(panther_server *srv, int32_t kind, int32_t q,
+                          int32_t k, uint64_t tag);
+
+/* Moves up to `max` completed results into `results`, waiting up to
+ * timeout_us for the first one; returns how many (>= 0) or EINVAL. */
+int panther_server_poll(panther_server *srv, panther_result *results,
+                        int32_t max, int32_t timeout_us);
+
+/* Latency percentiles and throughput over all completed requests. */
+int panther_server_stats(panther_server *srv, double *p50_ms, double *p99_ms,
+                         double *qps, int64_t *completed);
+
+/* Finishes every queued request, stops the threads and frees the server;
+ * uncollected results are dropped.  Returns EDEVICE if any batch failed. */
+int panther_server_stop(panther_server *srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -365,25 +365,35 @@ struct BatchState {
   std::string tune_key;
 };
 
-static BatchState* state(panther_ctx* c) {
-  if (!c->batch) c->batch = new BatchState();
-  return c->batch;
+static BatchState* state(Lane* lane) {
+  if (!lane->batch) lane->batch = new BatchState();
+  return lane->batch;
 }
 
-void free_batch_state(panther_ctx* c) {
-  if (!c->batch) return;
-  BatchState* b = c->batch;
+void copy_batch_options(panther_ctx* c, Lane* dst) {
+  BatchState* a = state(&c->lane0);
+  BatchState* b = state(dst);
+  b->forced_block = a->forced_block;
+  b->forced_wgs = a->forced_wgs;
+  b->tier_a_override = a->tier_a_override;
+  b->tier_b_override = a->tier_b_override;
+  b->tuned = false;
+}
+
+void free_batch_state(Lane* lane) {
+  if (!lane->batch) return;
+  BatchState* b = lane->batch;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   ctx_free(b->d_items);
   ctx_free(b->d_queue);
   ctx_free(b->d_slot_cnt);
   ctx_free(b->d_slot_touched);
   delete b;
-  c->batch = nullptr;
+  lane->batch = nullptr;
 }
 
 int set_batch_option(panther_ctx* c, const std::string& key, int64_t value) {
-  BatchState* b = state(c);
+  BatchState* b = state(&c->lane0);
   if (key == "batch.block") {
     if (value != 0 && value != 256 && value != 512)
       return ctx_fail(c, PANTHER_EINVAL, "batch.block must be 0 (auto), 256 or 512");
@@ -629,16 +639,10 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   return PANTHER_OK;
 }
 
-int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen,
-                     int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
-                     hipStream_t s) {
-  return run_batched(c, dq, qlen, nq, k, d_ids, d_counts, d_len, nullptr, s);
-}
-
-int run_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen, int64_t nq,
-                int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
-                hipStream_t s) {
-  BatchState* b = state(c);
+int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector<uint64_t>& qlen,
+                int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
+                float* theta, hipStream_t s) {
+  BatchState* b = state(lane);
   std::vector<int32_t> items;
   BatchArgs args;
   // configuration: forced, cached, autotuned, or the default

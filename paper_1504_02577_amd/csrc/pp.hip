@@ -18,7 +18,7 @@ namespace panther {
 size_t knn_fp64_lds(int D);
 int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const int32_t* queries, int64_t nq,
                     int32_t k, int32_t* out_ids, double* out_dist, hipStream_t s);
-int run_pp_bf16(panther_ctx* c, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
+int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
                 int32_t* d_ids, double* d_dist, hipStream_t s);
 }  // namespace panther
 
@@ -32,10 +32,9 @@ __global__ void k_iota(int32_t* out, int32_t n) {
 }  // namespace
 
 void free_pp_state(panther_ctx* c) {
+  c->lane0.have_stats = false;
   if (!c->pp) return;
-  for (DevBuf* b : {&c->pp->b_ids, &c->pp->b_bf16, &c->pp->b_norm, &c->pp->b_pool,
-                    &c->pp->b_iota, &c->pp->b_out, &c->pp->b_stats})
-    ctx_release(*b);
+  for (DevBuf* b : {&c->pp->b_bf16, &c->pp->b_norm, &c->pp->b_iota}) ctx_release(*b);
   delete c->pp;
   c->pp = nullptr;
 }
@@ -61,9 +60,9 @@ int ensure_features(panther_ctx* c, int32_t D, hipStream_t s) {
   k_iota<<<(unsigned)((c->n + 255) / 256), 256, 0, s>>>(ids, c->n);
   HIPTRY(hipGetLastError(), "features");
   std::vector<uint64_t> qlen;
-  TRY(query_lengths(c, ids, c->n, s, qlen));
+  TRY(query_lengths(c, &c->lane0, ids, c->n, s, qlen));
   stage_begin(c, 3, s);
-  TRY(run_batched(c, ids, qlen, c->n, D, nullptr, nullptr, nullptr, c->d_theta, s));
+  TRY(run_batched(c, &c->lane0, ids, qlen, c->n, D, nullptr, nullptr, nullptr, c->d_theta, s));
   stage_end(c, 3, s);
   c->theta_D = D;
   return PANTHER_OK;
@@ -114,22 +113,18 @@ extern "C" int panther_pp_topk(panther_ctx* c, const int32_t* queries, int64_t n
   if (st) return st;
   TRY(order_begin(c, s));
   TRY(ensure_features(c, D, s));
-  PPState* pp = pp_state(c);
+  if (c->pp_form == PANTHER_PP_BF16) TRY(prepare_bf16(c, D, s));
+  Lane* lane = &c->lane0;
   int32_t* d_ids = out_ids;
   double* d_dist = out_dist;
   if (mem == PANTHER_MEM_HOST) {
-    TRY(ctx_ensure(c, pp->b_out, (sizeof(int32_t) + sizeof(double)) * (size_t)nq * k,
+    TRY(ctx_ensure(c, lane->b_out, (sizeof(int32_t) + sizeof(double)) * (size_t)nq * k,
                    "pp outputs"));
-    d_dist = static_cast<double*>(pp->b_out.p);
+    d_dist = static_cast<double*>(lane->b_out.p);
     d_ids = reinterpret_cast<int32_t*>(d_dist + (size_t)nq * k);
   }
   stage_begin(c, 4, s);
-  if (c->pp_form == PANTHER_PP_FP64) {
-    const int e = launch_knn_fp64(c->d_theta, c->n, D, dq, nq, k, d_ids, d_dist, s);
-    HIPTRY((hipError_t)e, "pp fp64 knn");
-  } else {
-    TRY(run_pp_bf16(c, dq, nq, D, k, d_ids, d_dist, s));
-  }
+  TRY(run_pp(c, lane, dq, nq, D, k, d_ids, d_dist, s));
   stage_end(c, 4, s);
   TRY(order_end(c, s));
   if (mem == PANTHER_MEM_HOST) {
@@ -144,10 +139,20 @@ extern "C" int panther_pp_topk(panther_ctx* c, const int32_t* queries, int64_t n
   return PANTHER_OK;
 }
 
+int run_pp(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
+           int32_t* d_ids, double* d_dist, hipStream_t s) {
+  if (c->pp_form == PANTHER_PP_FP64) {
+    const int e = launch_knn_fp64(c->d_theta, c->n, D, dq, nq, k, d_ids, d_dist, s);
+    HIPTRY((hipError_t)e, "pp fp64 knn");
+    return PANTHER_OK;
+  }
+  return run_pp_bf16(c, lane, dq, nq, D, k, d_ids, d_dist, s);
+}
+
 extern "C" int panther_pp_stats(panther_ctx* c, double* max_rel_err, double* mean_pre_recall) {
   if (!c) return PANTHER_EINVAL;
-  if (!c->pp || !c->pp->have_stats) return ctx_fail(c, PANTHER_ESTATE, "no BF16 Panther++ call");
-  if (max_rel_err) *max_rel_err = c->pp->max_rel_err;
-  if (mean_pre_recall) *mean_pre_recall = c->pp->mean_pre_recall;
+  if (!c->lane0.have_stats) return ctx_fail(c, PANTHER_ESTATE, "no BF16 Panther++ call");
+  if (max_rel_err) *max_rel_err = c->lane0.max_rel_err;
+  if (mean_pre_recall) *mean_pre_recall = c->lane0.mean_pre_recall;
   return PANTHER_OK;
 }

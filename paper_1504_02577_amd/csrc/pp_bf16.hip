@@ -326,12 +326,29 @@ k_pp_rerank(RerankArgs A) {
 
 }  // namespace
 
+int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
+  PPState* pp = c->pp;
+  if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
+  if (!pp || !c->d_theta || c->theta_D != D)
+    return ctx_fail(c, PANTHER_ESTATE, "features for D = %d are not computed", D);
+  if (pp->bf16_D == D) return PANTHER_OK;
+  TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)c->n * kDP, "bf16 rows"));
+  TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)c->n, "bf16 norms"));
+  k_bf16_rows<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+      c->d_theta, c->n, D, (float)c->R, static_cast<__bf16*>(pp->b_bf16.p),
+      static_cast<float*>(pp->b_norm.p));
+  HIPTRY(hipGetLastError(), "bf16 rows");
+  pp->bf16_D = D;
+  return PANTHER_OK;
+}
+
 namespace panther {
 
-int run_pp_bf16(panther_ctx* c, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
+int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
                 int32_t* d_ids, double* d_dist, hipStream_t s) {
   PPState* pp = c->pp;
   if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
+  if (!pp || pp->bf16_D != D) return ctx_fail(c, PANTHER_ESTATE, "bf16 rows not prepared");
   // pool: at least the option and at least 4k (margin for the bfloat16
   // rounding at the pool boundary), a power of two, at most 1024
   int P = 32;
@@ -339,28 +356,19 @@ int run_pp_bf16(panther_ctx* c, const int32_t* dq, int64_t nq, int32_t D, int32_
   if (P > 1024) P = 1024;
   const int cap = std::max(2 * P, P + kChunk);
   const float scale = (float)c->R;
-  if (pp->bf16_D != D) {
-    TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)c->n * kDP, "bf16 rows"));
-    TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)c->n, "bf16 norms"));
-    k_bf16_rows<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        c->d_theta, c->n, D, scale, static_cast<__bf16*>(pp->b_bf16.p),
-        static_cast<float*>(pp->b_norm.p));
-    HIPTRY(hipGetLastError(), "bf16 rows");
-    pp->bf16_D = D;
-  }
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * cap;
   const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
-  TRY(ctx_ensure(c, pp->b_pool, buf_bytes + ids_bytes, "pools"));
-  TRY(ctx_ensure(c, pp->b_stats, 64, "pp stats"));
-  uint64_t* buf = static_cast<uint64_t*>(pp->b_pool.p);
+  TRY(ctx_ensure(c, lane->b_pool, buf_bytes + ids_bytes, "pools"));
+  TRY(ctx_ensure(c, lane->b_stats, 64, "pp stats"));
+  uint64_t* buf = static_cast<uint64_t*>(lane->b_pool.p);
   int32_t* pool_ids = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(buf) + buf_bytes);
   float* pool_d2 = reinterpret_cast<float*>(pool_ids + (size_t)nq * P);
-  HIPTRY(hipMemsetAsync(pp->b_stats.p, 0, 64, s), "pp stats");
+  HIPTRY(hipMemsetAsync(lane->b_stats.p, 0, 64, s), "pp stats");
   PoolArgs pa{static_cast<const __bf16*>(pp->b_bf16.p), static_cast<const float*>(pp->b_norm.p),
               c->n, dq, nq, P, cap, buf, pool_ids, pool_d2};
   k_pp_pool<<<(unsigned)((nq + kQW - 1) / kQW), kBlock, 0, s>>>(pa);
   HIPTRY(hipGetLastError(), "pp pool");
-  unsigned long long* st = static_cast<unsigned long long*>(pp->b_stats.p);
+  unsigned long long* st = static_cast<unsigned long long*>(lane->b_stats.p);
   RerankArgs ra{c->d_theta, D, dq, nq, P, k, pool_ids, pool_d2,
                 1.0f / (scale * scale), d_ids, d_dist, st, st + 1, st + 2};
   k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, 0, s>>>(ra);
@@ -368,11 +376,11 @@ int run_pp_bf16(panther_ctx* c, const int32_t* dq, int64_t nq, int32_t D, int32_
   unsigned long long hs[3];
   HIPTRY(hipMemcpyAsync(hs, st, 24, hipMemcpyDeviceToHost, s), "pp stats");
   HIPTRY(hipStreamSynchronize(s), "pp stats");
-  pp->have_stats = true;
-  pp->mean_pre_recall = hs[2] ? (double)hs[0] / (double)hs[2] : 1.0;
+  lane->have_stats = true;
+  lane->mean_pre_recall = hs[2] ? (double)hs[0] / (double)hs[2] : 1.0;
   double e;
   std::memcpy(&e, &hs[1], sizeof e);
-  pp->max_rel_err = e;
+  lane->max_rel_err = e;
   return PANTHER_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,10 +18,18 @@ struct DevBuf {
   size_t cap = 0;
 };
 
-// Panther++ state: bf16 copy of theta, pools, statistics.
+// Panther++ data shared by every lane: bf16 copy of theta and its norms.
 struct PPState {
-  DevBuf b_ids, b_bf16, b_norm, b_pool, b_iota, b_out, b_stats;
+  DevBuf b_bf16, b_norm, b_iota;
   int32_t bf16_D = 0;
+};
+
+// Scratch of one query stream.  The context's own calls use lane 0; the
+// serving loop runs several lanes concurrently, each on its own stream,
+// over the same read-only graph, paths, index and features.
+struct Lane {
+  BatchState* batch = nullptr;
+  DevBuf b_qlen, b_pool, b_out, b_stats, b_q;
   bool have_stats = false;
   double max_rel_err = 0.0;
   double mean_pre_recall = 0.0;
@@ -30,6 +39,7 @@ struct panther_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   std::string err;
+  std::mutex err_mu;
   int num_cus = 256;
   int lds_per_block = 65536;
   // options
@@ -38,6 +48,7 @@ struct panther_ctx {
   int pp_pool = 256;
   int autotune = 1;
   int64_t fail_alloc_after = -1;
+  std::mutex alloc_mu;
   // graph
   bool has_graph = false;
   int32_t n = 0;
@@ -63,13 +74,13 @@ struct panther_ctx {
   int64_t nnz = 0;
   // storage reused across sample_paths / query calls
   DevBuf b_paths, b_inv_pid, b_inv_ptr, b_keys0, b_keys1, b_vtmp, b_hist, b_offs, b_stemp;
-  DevBuf b_qlen, b_queries, b_outs;
+  DevBuf b_queries, b_outs;
   // dense query scratch (plain form, hub queries)
   uint32_t* d_cnt = nullptr;
   int32_t* d_touched = nullptr;
   uint32_t* d_ctl = nullptr;
-  // batched form
-  BatchState* batch = nullptr;
+  // scratch of the context's own query calls
+  Lane lane0;
   // calls on different streams share the scratch above: each call waits
   // for the previous one's completion event before using it
   hipEvent_t order_ev = nullptr;
@@ -93,12 +104,12 @@ struct panther_ctx {
 
 int ctx_fail(panther_ctx* c, int code, const char* fmt, ...);
 int ctx_hip(panther_ctx* c, hipError_t e, const char* what);
-int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what);
+int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what);  // thread-safe
 // Makes b hold at least `bytes`; the contents are not preserved on growth.
 int ctx_ensure(panther_ctx* c, DevBuf& b, size_t bytes, const char* what);
 void ctx_release(DevBuf& b);
 // Path-list lengths of the queries, gathered on the device and copied back.
-int query_lengths(panther_ctx* c, const int32_t* dq, int64_t nq, hipStream_t s,
+int query_lengths(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, hipStream_t s,
                   std::vector<uint64_t>& len);
 void ctx_free(void* p);
 // Stage timing: stage i is bracketed by events 2i and 2i+1.
@@ -109,18 +120,22 @@ int order_end(panther_ctx* c, hipStream_t s);
 int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, hipStream_t s,
                   std::vector<int32_t>& hq, const int32_t** dq, void** dq_owned);
 
-// batched form (batch.hip)
-int run_topk_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen,
-                     int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
-                     hipStream_t s);
-// Generic batched pass: with theta != nullptr it writes Panther++ feature
-// rows (k = D) instead of ids/counts.
-int run_batched(panther_ctx* c, const int32_t* dq, const std::vector<uint64_t>& qlen, int64_t nq,
-                int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
-                hipStream_t s);
+// batched form (batch.hip).  With theta != nullptr the pass writes Panther++
+// feature rows (k = D) instead of ids/counts.
+int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector<uint64_t>& qlen,
+                int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
+                float* theta, hipStream_t s);
 int set_batch_option(panther_ctx* c, const std::string& key, int64_t value);
-void free_batch_state(panther_ctx* c);
+// copies the forced batch options of lane 0 to another lane
+void copy_batch_options(panther_ctx* c, Lane* dst);
+void free_batch_state(Lane* lane);
+void free_lane(Lane* lane);
 
-// Panther++ (pp.hip)
+// Panther++ (pp.hip, knn.hip, pp_bf16.hip)
 void free_pp_state(panther_ctx* c);
 int ensure_features(panther_ctx* c, int32_t D, hipStream_t s);
+// bf16 rows for the precision form (shared by lanes; call before lanes run)
+int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s);
+// Panther++ top-k for device queries into device outputs on one lane
+int run_pp(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
+           int32_t* d_ids, double* d_dist, hipStream_t s);

@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,7 +25,10 @@ int ctx_fail(panther_ctx* c, int code, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (c) c->err = buf;
+  if (c) {
+    std::lock_guard<std::mutex> g(c->err_mu);
+    c->err = buf;
+  }
   return code;
 }
 
@@ -39,11 +43,15 @@ int ctx_hip(panther_ctx* c, hipError_t e, const char* what) {
 
 int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what) {
   *p = nullptr;
-  if (c->fail_alloc_after >= 0) {
+  bool inject = false;
+  {
+    std::lock_guard<std::mutex> g(c->alloc_mu);
     if (c->fail_alloc_after == 0)
-      return ctx_fail(c, PANTHER_ENOMEM, "%s: allocation failure injected", what);
-    --c->fail_alloc_after;
+      inject = true;
+    else if (c->fail_alloc_after > 0)
+      --c->fail_alloc_after;
   }
+  if (inject) return ctx_fail(c, PANTHER_ENOMEM, "%s: allocation failure injected", what);
   if (bytes == 0) bytes = 16;
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
@@ -96,10 +104,10 @@ static void free_paths(panther_ctx* c, bool release) {
   c->has_paths = false;
   c->nnz = 0;
   if (release) {
-    free_batch_state(c);
+    free_lane(&c->lane0);
     for (DevBuf* b : {&c->b_paths, &c->b_inv_pid, &c->b_inv_ptr, &c->b_keys0, &c->b_keys1,
-                      &c->b_vtmp, &c->b_hist, &c->b_offs, &c->b_stemp, &c->b_qlen,
-                      &c->b_queries, &c->b_outs})
+                      &c->b_vtmp, &c->b_hist, &c->b_offs, &c->b_stemp, &c->b_queries,
+                      &c->b_outs})
       ctx_release(*b);
     ctx_free(c->d_cnt);
     ctx_free(c->d_touched);
@@ -621,14 +629,21 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
   return PANTHER_OK;
 }
 
-int query_lengths(panther_ctx* c, const int32_t* dq, int64_t nq, hipStream_t s,
+void free_lane(Lane* lane) {
+  free_batch_state(lane);
+  for (DevBuf* b : {&lane->b_qlen, &lane->b_pool, &lane->b_out, &lane->b_stats, &lane->b_q})
+    ctx_release(*b);
+  lane->have_stats = false;
+}
+
+int query_lengths(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, hipStream_t s,
                   std::vector<uint64_t>& len) {
-  TRY(ctx_ensure(c, c->b_qlen, sizeof(uint64_t) * (size_t)std::max<int64_t>(nq, 1),
+  TRY(ctx_ensure(c, lane->b_qlen, sizeof(uint64_t) * (size_t)std::max<int64_t>(nq, 1),
                  "query lengths"));
-  launch_query_lengths(c->d_inv_ptr, dq, nq, static_cast<uint64_t*>(c->b_qlen.p), s);
+  launch_query_lengths(c->d_inv_ptr, dq, nq, static_cast<uint64_t*>(lane->b_qlen.p), s);
   HIPTRY(hipGetLastError(), "query lengths");
   len.resize((size_t)nq);
-  HIPTRY(hipMemcpyAsync(len.data(), c->b_qlen.p, sizeof(uint64_t) * (size_t)nq,
+  HIPTRY(hipMemcpyAsync(len.data(), lane->b_qlen.p, sizeof(uint64_t) * (size_t)nq,
                         hipMemcpyDeviceToHost, s),
          "query lengths");
   HIPTRY(hipStreamSynchronize(s), "query lengths");
@@ -676,7 +691,7 @@ extern "C" int panther_topk_similar(panther_ctx* c, const int32_t* queries, int6
   TRY(order_begin(c, s));
   stage_begin(c, 2, s);
   std::vector<uint64_t> qlen;
-  TRY(query_lengths(c, dq, nq, s, qlen));
+  TRY(query_lengths(c, &c->lane0, dq, nq, s, qlen));
   if (c->topk_form == PANTHER_FORM_PLAIN) {
     TopkScratch sc{c->d_cnt, c->d_touched, c->d_ctl};
     for (int64_t i = 0; i < nq; ++i) {
@@ -685,7 +700,7 @@ extern "C" int panther_topk_similar(panther_ctx* c, const int32_t* queries, int6
     }
     HIPTRY(hipGetLastError(), "topk plain");
   } else {
-    TRY(run_topk_batched(c, dq, qlen, nq, k, d_ids, d_cnt, d_len, s));
+    TRY(run_batched(c, &c->lane0, dq, qlen, nq, k, d_ids, d_cnt, d_len, nullptr, s));
   }
   stage_end(c, 2, s);
   TRY(order_end(c, s));

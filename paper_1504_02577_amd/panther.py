@@ -38,8 +38,19 @@ EXPORTS = [
     "panther_sample_paths", "panther_topk_similar", "panther_pp_topk",
     "panther_sample_size", "panther_set_option", "panther_get_paths", "panther_index_nnz",
     "panther_get_index", "panther_get_features", "panther_pp_stats", "panther_synchronize",
-    "panther_stage_times",
+    "panther_stage_times", "panther_server_start", "panther_server_submit",
+    "panther_server_poll", "panther_server_stats", "panther_server_stop",
 ]
+
+PANTHER_SERVER_KMAX = 256
+
+
+class PantherResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("kind", ctypes.c_int32), ("query", ctypes.c_int32),
+                ("k", ctypes.c_int32), ("len", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("latency_ms", ctypes.c_double),
+                ("ids", ctypes.c_int32 * PANTHER_SERVER_KMAX),
+                ("scores", ctypes.c_double * PANTHER_SERVER_KMAX)]
 
 _lib = None
 
@@ -84,6 +95,12 @@ def lib():
         "panther_pp_stats": (ctypes.c_int, [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
         "panther_synchronize": (ctypes.c_int, [P]),
         "panther_stage_times": (ctypes.c_int, [P, ctypes.POINTER(dbl)]),
+        "panther_server_start": (ctypes.c_int, [P, i64, i32, i32, i32, PP]),
+        "panther_server_submit": (ctypes.c_int, [P, i32, i32, i32, u64]),
+        "panther_server_poll": (ctypes.c_int, [P, ctypes.POINTER(PantherResult), i32, i32]),
+        "panther_server_stats": (ctypes.c_int, [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                                ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "panther_server_stop": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -167,6 +184,70 @@ def panther_stage_times(ctx):
     out = (ctypes.c_double * 5)()
     st = lib().panther_stage_times(ctx, out)
     return st, list(out)
+
+
+def panther_server_start(ctx, mem_budget_bytes, max_batch, lanes, D):
+    h = ctypes.c_void_p()
+    st = lib().panther_server_start(ctx, mem_budget_bytes, max_batch, lanes, D, ctypes.byref(h))
+    return st, h
+
+
+def panther_server_submit(srv, kind, q, k, tag):
+    return lib().panther_server_submit(srv, kind, q, k, tag)
+
+
+def panther_server_poll(srv, results, max_results, timeout_us):
+    return lib().panther_server_poll(srv, results, max_results, timeout_us)
+
+
+def panther_server_stats(srv):
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_int64()
+    st = lib().panther_server_stats(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                    ctypes.byref(n))
+    return st, a.value, b.value, c.value, n.value
+
+
+def panther_server_stop(srv):
+    return lib().panther_server_stop(srv)
+
+
+class Server:
+    """Continuous-batching server over a context's resident state."""
+
+    def __init__(self, panther, mem_budget_bytes, max_batch=256, lanes=3, D=50):
+        self.P = panther
+        st, self.h = panther_server_start(panther.h, mem_budget_bytes, max_batch, lanes, D)
+        if st != PANTHER_OK:
+            raise PantherError(st, panther_last_error(panther.h))
+        self._buf = (PantherResult * 1024)()
+
+    def submit(self, kind, q, k, tag):
+        return panther_server_submit(self.h, kind, q, k, tag)
+
+    def poll(self, timeout_us=1000):
+        n = panther_server_poll(self.h, self._buf, 1024, timeout_us)
+        if n < 0:
+            raise PantherError(n, "poll failed")
+        out = []
+        for i in range(n):
+            r = self._buf[i]
+            out.append(dict(tag=r.tag, kind=r.kind, query=r.query, k=r.k, len=r.len,
+                            status=r.status, latency_ms=r.latency_ms,
+                            ids=np.ctypeslib.as_array(r.ids)[:r.k].copy(),
+                            scores=np.ctypeslib.as_array(r.scores)[:r.k].copy()))
+        return out
+
+    def stats(self):
+        st, p50, p99, qps, done = panther_server_stats(self.h)
+        return dict(status=st, p50_ms=p50, p99_ms=p99, qps=qps, completed=done)
+
+    def stop(self):
+        if self.h:
+            st = panther_server_stop(self.h)
+            self.h = None
+            return st
+        return PANTHER_OK
 
 
 # ---------------------------------------------------------------------------
