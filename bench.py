@@ -9,6 +9,14 @@ top-k queries/s (with a bit-exactness check between the two), per-stage
 device times, the walk kernel's roofline figure and the oracle timed on the
 host cores on a bounded sample of the same workload.
 
+Other workloads (one JSON line each, not the headline):
+  --workload rmat24     batched vs plain top-k, 10^5 degree-weighted queries,
+                        R = 10^8 (the heavy-tailed batching case)
+  --workload rmat22_pp  Panther++: features (D=50) and 65,536 kNN queries
+                        (k=20) in the BF16 matrix-core form, FP64 form timed
+                        on a 1,024-query subset
+  --workload serve      continuous-batching server under Poisson arrivals
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
 """
 import argparse
@@ -38,6 +46,21 @@ def walk_algorithmic_bytes(R, T):
     return R * (T * (16 + 4 + 8 + 4) + 8)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+            return None
+        return rec["hbm_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(g, queries, T, k, seed, R_sample):
     import oracle
 
@@ -61,6 +84,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rmat20")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=50_000.0)
+    ap.add_argument("--serve-graph", default="rmat20")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="paths in the oracle sample (0 = the full R of the workload)")
     args = ap.parse_args()
@@ -74,6 +102,17 @@ def main():
     from paper_1504_02577_amd.panther import Panther
 
     os.environ.setdefault("PANTHER_INPUT_CACHE", "/tmp/panther_inputs")
+    if args.calibrate_copy:
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read + 1 GiB written")
+        del x, y
+    if args.workload == "rmat22_pp":
+        return bench_pp(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     t0 = time.time()
     g, q, p = inputs.workload(args.workload)
     T, R, seed, k = p["T"], p["R"], p["seed"], p["k"]
@@ -159,14 +198,126 @@ def main():
         "batched_vs_plain": tp / tb,
         "batched_equals_plain": bool(exact),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_walk", "algorithmic_bytes_per_launch": walk_bytes,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (measured_traffic("k_walk32")
+                                 if args.workload == "rmat20" else None),
+                     "kernel": "k_walk32", "algorithmic_bytes_per_launch": walk_bytes,
                      "kernel_ms": walk_ms},
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(g, q, T, k, seed, args.cpu_sample or R)
     P.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_pp(args):
+    """Panther++ at R-MAT 22: feature pass and BF16-MFMA kNN (+ FP64 rerank)."""
+    import torch
+    from paper_1504_02577_amd import inputs
+    from paper_1504_02577_amd.panther import Panther
+
+    t0 = time.time()
+    g, q, p = inputs.workload("rmat22_pp")
+    T, R, seed, k, D = p["T"], p["R"], p["seed"], p["k"], p["D"]
+    log(f"workload rmat22_pp: n={g.n} m={g.m} R={R} queries={len(q)} D={D} k={k} "
+        f"(inputs {time.time() - t0:.1f} s)")
+    P = Panther(0)
+    P.load_graph(g)
+    P.set_option("timing", 1)
+    P.sample_paths(T, R, seed)
+    P.set_option("pp.form", 1)
+    P.set_option("pp.pool", p["pool"])
+    dq = torch.from_numpy(q).cuda()
+    out = (torch.empty((len(q), k), dtype=torch.int32, device="cuda"),
+           torch.empty((len(q), k), dtype=torch.float64, device="cuda"))
+    stream = torch.cuda.current_stream().cuda_stream
+    P.pp_topk(dq, D, k, out=out, stream=stream)  # builds theta, warms up
+    torch.cuda.synchronize()
+    feat_ms = P.stage_times()["features"]
+    times = []
+    for _ in range(max(1, args.steps)):
+        t = time.perf_counter()
+        P.pp_topk(dq, D, k, out=out, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    pp_ms = P.stage_times()["pp"]
+    err, rec = P.pp_stats()
+    bf16_ids = out[0].cpu().numpy()
+    sub = q[:1024]
+    P.set_option("pp.form", 0)
+    t = time.perf_counter()
+    fids, fdist = P.pp_topk(sub, D, k)
+    fp64_s = time.perf_counter() - t
+    agree = float((fids == bf16_ids[:1024]).mean())
+    n_pad = g.n
+    flops = 2.0 * len(q) * n_pad * 64
+    achieved = flops / (pp_ms * 1e-3) / 1e12
+    res = {
+        "metric": "Panther++ queries/s", "value": len(q) / min(times), "unit": "queries/s",
+        "n_gpus": 1, "steps": len(times), "warmup": 1, "ms_per_step": 1e3 * min(times),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64",
+        "data": "synthetic",
+        "config": {"workload": f"rmat22_pp: R-MAT scale 22, {g.m} CSR entries, T={T}, R={R}, "
+                               f"D={D}, {len(q)} queries, k={k}, pool {p['pool']}"},
+        "features_ms": feat_ms, "pp_kernels_ms": pp_ms,
+        "pre_rerank_recall": rec, "bf16_max_rel_err": err,
+        "fp64_form_queries_per_s": len(sub) / fp64_s,
+        "fp64_vs_bf16_id_agreement_1024": agree,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": achieved / 2500.0, "traffic": None,
+                     "kernel": "k_pp_pool + k_pp_rerank",
+                     "algorithmic_flops_per_launch": flops, "kernel_ms": pp_ms},
+    }
+    P.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_serve(args):
+    """Continuous batching under Poisson arrivals: 80% Panther / 20%
+    Panther++, k uniform over {10, 50, 200}, query vertices proportional to
+    degree."""
+    from paper_1504_02577_amd import inputs
+    from paper_1504_02577_amd.panther import Panther, Server
+
+    g, _, p = inputs.workload(args.serve_graph)
+    T, R, seed = p["T"], p["R"], p["seed"]
+    P = Panther(0)
+    P.load_graph(g)
+    P.sample_paths(T, R, seed)
+    log(f"serve: {args.serve_graph} n={g.n} R={R}; building features ...")
+    srv = Server(P, mem_budget_bytes=1 << 32, max_batch=2048, lanes=3, D=50)
+    rng = np.random.default_rng(5)
+    n_req = int(args.serve_rate * args.serve_seconds)
+    qs = inputs.queries_by_degree(g, n_req, 6)
+    kinds = (rng.random(n_req) < 0.2).astype(np.int32)
+    ks = rng.choice([10, 50, 200], n_req).astype(np.int32)
+    gaps = rng.exponential(1.0 / args.serve_rate, n_req)
+    arrive = np.cumsum(gaps)
+    got = 0
+    t0 = time.perf_counter()
+    i = 0
+    while i < n_req:
+        now = time.perf_counter() - t0
+        while i < n_req and arrive[i] <= now:
+            srv.submit(int(kinds[i]), int(qs[i]), int(ks[i]), i)
+            i += 1
+        got += len(srv.poll(0))
+    while got < n_req and time.perf_counter() - t0 < arrive[-1] + 60:
+        got += len(srv.poll(10000))
+    st = srv.stats()
+    srv.stop()
+    P.close()
+    res = {"metric": "p99 ms", "value": st["p99_ms"], "unit": "ms", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32+bf16+f64",
+           "data": "synthetic",
+           "config": {"workload": f"serve: {args.serve_graph}, R={R}, Poisson "
+                                  f"{args.serve_rate:.0f}/s for {args.serve_seconds:.0f} s, "
+                                  "80% Panther / 20% Panther++ (D=50), k in {10,50,200}, "
+                                  "3 lanes, max batch 2048"},
+           "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "sustained_qps": st["qps"],
+           "offered_qps": args.serve_rate, "completed": st["completed"], "submitted": n_req}
     print(json.dumps(res), flush=True)
 
 
