@@ -362,7 +362,14 @@ struct BatchState {
   BatchArgs exec_args{};
   int exec_block = 0, exec_grid = 0;
   size_t exec_lds = 0;
+  // the previous direct launch (a repeat of it gets captured)
+  bool last_valid = false;
+  hipStream_t last_stream = nullptr;
+  BatchArgs last_args{};
+  int last_block = 0, last_grid = 0;
+  size_t last_lds = 0;
   std::string tune_key;
+  bool no_tune = false;  // serving lanes reuse a stored or default configuration
 };
 
 static BatchState* state(Lane* lane) {
@@ -378,6 +385,7 @@ void copy_batch_options(panther_ctx* c, Lane* dst) {
   b->tier_a_override = a->tier_a_override;
   b->tier_b_override = a->tier_b_override;
   b->tuned = false;
+  b->no_tune = true;
 }
 
 void free_batch_state(Lane* lane) {
@@ -512,7 +520,18 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
                     b->exec_grid == grid && b->exec_lds == lay.lds &&
                     std::memcmp(&b->exec_args, &args, sizeof(args)) == 0;
   if (use_graph && same) return ctx_hip(c, hipGraphLaunch(b->exec, s), "batched graph replay");
-  if (use_graph) {
+  // capture only once the same launch comes back: a graph pays off for
+  // repeated identical batches, not for a stream of different ones
+  const bool repeat = b->last_valid && b->last_stream == s && b->last_block == cfg.block &&
+                      b->last_grid == grid && b->last_lds == lay.lds &&
+                      std::memcmp(&b->last_args, &args, sizeof(args)) == 0;
+  b->last_valid = true;
+  b->last_stream = s;
+  b->last_block = cfg.block;
+  b->last_grid = grid;
+  b->last_lds = lay.lds;
+  b->last_args = args;
+  if (use_graph && repeat) {
     if (b->exec) {
       (void)hipGraphExecDestroy(b->exec);
       b->exec = nullptr;
@@ -572,9 +591,25 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
                           const std::pair<uint64_t, int32_t>& y) {
     return x.first != y.first ? x.first > y.first : x.second < y.second;
   };
-  std::sort(B.begin(), B.end(), longest_first);
+  // hubs exactly longest-first; the LDS tiers by power-of-two length class
+  // (a stable counting sort, O(n)), which is enough for load balance
   std::sort(C.begin(), C.end(), longest_first);
-  std::sort(A.begin(), A.end(), longest_first);
+  auto by_class = [](std::vector<std::pair<uint64_t, int32_t>>& v) {
+    size_t cnt[65] = {0};
+    auto cls = [](uint64_t L) { return L ? 64 - __builtin_clzll(L) : 0; };
+    for (auto& x : v) ++cnt[cls(x.first)];
+    size_t pos[65];
+    size_t run = 0;
+    for (int c2 = 64; c2 >= 0; --c2) {
+      pos[c2] = run;
+      run += cnt[c2];
+    }
+    std::vector<std::pair<uint64_t, int32_t>> out(v.size());
+    for (auto& x : v) out[pos[cls(x.first)]++] = x;
+    v.swap(out);
+  };
+  by_class(B);
+  by_class(A);
   host_items->clear();
   for (auto& x : C) host_items->push_back(x.second);
   for (auto& x : B) host_items->push_back(x.second);
@@ -656,9 +691,15 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector
     b->cfg = f;
     b->tuned = true;
   }
+  // the tuned choice is kept per shape class: graph and path count, and the
+  // batch size and k rounded to powers of two
+  int nq_bucket = 0;
+  while ((int64_t(2) << nq_bucket) <= nq) ++nq_bucket;
+  int k_bucket = 1;
+  while (k_bucket < k) k_bucket <<= 1;
   char key[256];
-  snprintf(key, sizeof key, "gfx950:n%d:T%d:R%lld:nq%lld:k%d:cu%d:f%d", c->n, c->T,
-           (long long)c->R, (long long)nq, k, c->num_cus, theta ? 1 : 0);
+  snprintf(key, sizeof key, "gfx950:n%d:T%d:R%lld:nq2^%d:k%d:cu%d:f%d", c->n, c->T,
+           (long long)c->R, nq_bucket, k_bucket, c->num_cus, theta ? 1 : 0);
   if (b->tuned && !(b->forced_block || b->forced_wgs) && b->tune_key != key) b->tuned = false;
   if (!b->tuned) {
     b->tune_key = key;
@@ -666,9 +707,10 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector
     if (tune_lookup(b->tune_key, &cached)) {
       b->cfg = cached;
       b->tuned = true;
-    } else if (c->autotune && nq >= 256) {
-      // time every candidate on this batch (results are identical by
-      // construction; only speed differs) and keep the fastest
+    } else if (c->autotune && !b->no_tune && nq >= 256) {
+      // time every candidate on (a prefix of) this batch -- results are
+      // identical by construction, only speed differs -- and keep the fastest
+      const int64_t m = std::min<int64_t>(nq, 16384);
       hipEvent_t e0, e1;
       int st = ctx_hip(c, hipEventCreate(&e0), "autotune");
       if (st) return st;
@@ -677,7 +719,7 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector
       float best = 1e30f;
       BatchConfig best_cfg = cands[0];
       for (const BatchConfig& cfg : cands) {
-        st = plan(c, b, cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, theta, s, &args, &items);
+        st = plan(c, b, cfg, dq, qlen, m, k, d_ids, d_counts, d_len, theta, s, &args, &items);
         if (st) break;
         st = launch_batched(c, b, cfg, args, s, false);  // warm
         if (st) break;

@@ -292,15 +292,16 @@ __device__ int block_select_topk(KeyFn key, int n, int k, SelectSmem& sm) {
     uint64_t hi = shift >= 64 ? 0ull : (x >> shift);
     if (hi > prefix) {
       uint32_t p = atomicAdd(&sm.misc[3], 1u);
-      sm.out[p] = x;
+      if (p < (uint32_t)kOutCap) sm.out[p] = x;
     } else if (hi == prefix) {
       uint32_t p = atomicAdd(&sm.misc[4], 1u);
-      sm.cand[p] = x;
+      if (p < (uint32_t)kCand) sm.cand[p] = x;
     }
   }
   __syncthreads();
-  const int ndef = (int)sm.misc[3];
-  const int ncls = (int)sm.misc[4];
+  // keys are distinct, so these stay within the buffers; clamp regardless
+  const int ndef = (int)(sm.misc[3] < (uint32_t)kOutCap ? sm.misc[3] : (uint32_t)kOutCap);
+  const int ncls = (int)(sm.misc[4] < (uint32_t)kCand ? sm.misc[4] : (uint32_t)kCand);
   const int P = next_pow2(ncls < 2 ? 2 : ncls);
   for (int i = ncls + tid; i < P; i += BLOCK) sm.cand[i] = 0ull;
   __syncthreads();

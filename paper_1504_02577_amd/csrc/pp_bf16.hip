@@ -38,6 +38,7 @@ constexpr int kDP = 64;        // padded feature width in bfloat16
 constexpr int kQW = 128;       // queries per work-group
 constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
 constexpr int kTiles = kQW / 16;
+constexpr int kCheckEvery = 4;  // chunks between pool compaction checks
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -99,28 +100,40 @@ struct PoolArgs {
   const int32_t* queries;
   int64_t nq;
   int32_t P;             // pool size (power of two, <= 1024)
-  int32_t cap;           // buffer entries per query: max(2P, P + 64)
-  uint64_t* buf;         // [nq][cap] pool buffers
-  int32_t* pool_ids;     // [nq][P] result, ascending key order, -1 padded
-  float* pool_d2;        // [nq][P] approximate squared distances
+  int32_t cap;           // buffer entries per (query, slice): 2P + kCheckEvery * kChunk
+  int32_t slices;        // database slices (grid.y)
+  int32_t rows_per_slice;// multiple of kChunk
+  int32_t sort_cap;      // per-wave sort buffer entries: next power of two >= cap
+  uint64_t* buf;         // [nq][slices][cap] pool buffers
+  uint64_t* part;        // [nq][slices][P] sorted slice pools (slices > 1)
+  int32_t* part_cnt;     // [nq][slices]
+  int32_t* pool_ids;     // [nq][P] result when slices == 1, ascending key order, -1 padded
+  float* pool_d2;        // [nq][P]
 };
 
+// grid (query tiles, database slices)
 __global__ void __launch_bounds__(kBlock)
 k_pp_pool(PoolArgs A) {
   __shared__ uint32_t cnt[kQW];
   __shared__ uint64_t tau[kQW];
+  __shared__ float tauf_s[kQW];  // float part of tau, for the prefilter
   __shared__ int32_t qid[kQW];
-  __shared__ float qn[kQW];
-  __shared__ uint64_t sortbuf[kBlock / kWave][2048];
+  __shared__ float qn_s[kQW];
+  extern __shared__ __align__(16) uint64_t sortmem[];  // [waves][cap]
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t q0 = (int64_t)blockIdx.x * kQW;
+  const int slice = blockIdx.y;
   const int P = A.P, cap = A.cap;
+  const int check_every = kCheckEvery;
+  const int64_t r0 = (int64_t)slice * A.rows_per_slice;
+  const int64_t r1 = r0 + A.rows_per_slice < A.n ? r0 + A.rows_per_slice : A.n;
   for (int i = threadIdx.x; i < kQW; i += kBlock) {
     const int32_t q = q0 + i < A.nq ? A.queries[q0 + i] : -1;
     qid[i] = q;
-    qn[i] = q >= 0 ? A.norm[q] : 0.f;
+    qn_s[i] = q >= 0 ? A.norm[q] : 0.f;
     cnt[i] = 0u;
     tau[i] = ~0ull;
+    tauf_s[i] = INFINITY;
   }
   __syncthreads();
   // query operands: tile m, k-step ks -> 8 bf16 of row (m*16 + l%16)
@@ -139,20 +152,27 @@ k_pp_pool(PoolArgs A) {
       }
     }
   }
-  for (int64_t cb = 0; cb < A.n; cb += kChunk) {
+  auto load_b = [&](int64_t cb, bf16x8 (&bb)[2], float& nvv) {
     const int64_t v = cb + wid * 16 + (lane & 15);
-    const bool vok = v < A.n;
-    bf16x8 b[2];
+    const bool ok = v < r1;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
-      if (vok) {
-        b[ks] = *reinterpret_cast<const bf16x8*>(A.rows + v * kDP + ks * 32 + 8 * (lane >> 4));
+      if (ok) {
+        bb[ks] = *reinterpret_cast<const bf16x8*>(A.rows + v * kDP + ks * 32 + 8 * (lane >> 4));
       } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) b[ks][j] = (__bf16)0.f;
+        for (int j = 0; j < 8; ++j) bb[ks][j] = (__bf16)0.f;
       }
     }
-    const float nv = vok ? A.norm[v] : 0.f;
+    nvv = ok ? A.norm[v] : 0.f;
+  };
+  bf16x8 b[2], bn[2];
+  float nv = 0.f, nvn = 0.f;
+  if (r0 < r1) load_b(r0, b, nv);
+  int chunk_no = 0;
+  for (int64_t cb = r0; cb < r1; cb += kChunk) {
+    if (cb + kChunk < r1) load_b(cb + kChunk, bn, nvn);  // prefetch the next chunk
+    const int64_t v = cb + wid * 16 + (lane & 15);
     floatx4 acc[kTiles];
 #pragma unroll
     for (int m = 0; m < kTiles; ++m) {
@@ -160,30 +180,36 @@ k_pp_pool(PoolArgs A) {
       acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][0], b[0], acc[m], 0, 0, 0);
       acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][1], b[1], acc[m], 0, 0, 0);
     }
-    if (vok) {
+    if (v < r1) {
 #pragma unroll
       for (int m = 0; m < kTiles; ++m) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int ql = m * 16 + 4 * (lane >> 4) + r;
-          const float d2 = qn[ql] + nv - 2.f * acc[m][r];
-          const uint64_t key = pool_key(d2, (int32_t)v);
-          if (key < tau[ql] && qid[ql] >= 0 && qid[ql] != (int32_t)v) {
-            const uint32_t pos = atomicAdd(&cnt[ql], 1u);
-            A.buf[(q0 + ql) * cap + pos] = key;
+          float d2 = qn_s[ql] + nv - 2.f * acc[m][r];
+          d2 = d2 > 0.f ? d2 : 0.f;
+          if (d2 <= tauf_s[ql]) {  // float prefilter; the exact key test follows
+            const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)v;
+            if (key < tau[ql] && qid[ql] >= 0 && qid[ql] != (int32_t)v) {
+              const uint32_t pos = atomicAdd(&cnt[ql], 1u);
+              A.buf[((q0 + ql) * A.slices + slice) * cap + pos] = key;
+            }
           }
         }
       }
     }
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) b[ks] = bn[ks];
+    nv = nvn;
+    if (++chunk_no % check_every != 0 && cb + kChunk < r1) continue;
     __threadfence_block();
     __syncthreads();
-    // cut back buffers that the next chunk could overflow (it adds at most
-    // kChunk keys per query)
+    // cut back buffers that the next check_every chunks could overflow
     for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
       const int c = (int)cnt[ql];
-      if (c > cap - kChunk && c > P) {
-        uint64_t* g = A.buf + (q0 + ql) * cap;
-        uint64_t* sb = sortbuf[wid];
+      if (c > P && c > cap - check_every * kChunk) {
+        uint64_t* g = A.buf + ((q0 + ql) * A.slices + slice) * cap;
+        uint64_t* sb = sortmem + (size_t)wid * A.sort_cap;
         for (int i = lane; i < c; i += kWave)
           sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wsync();
@@ -192,6 +218,7 @@ k_pp_pool(PoolArgs A) {
         if (lane == 0) {
           cnt[ql] = (uint32_t)P;
           tau[ql] = sb[P - 1];
+          tauf_s[ql] = __uint_as_float((uint32_t)(sb[P - 1] >> 32));
         }
         wsync();
       }
@@ -199,22 +226,67 @@ k_pp_pool(PoolArgs A) {
     __threadfence_block();
     __syncthreads();
   }
-  // final pools
+  // final pools of this slice
   for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
     if (qid[ql] < 0) continue;
     const int c = (int)cnt[ql];
-    uint64_t* g = A.buf + (q0 + ql) * cap;
-    uint64_t* sb = sortbuf[wid];
+    uint64_t* g = A.buf + ((q0 + ql) * A.slices + slice) * cap;
+    uint64_t* sb = sortmem + (size_t)wid * A.sort_cap;
     for (int i = lane; i < c; i += kWave)
       sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     wsync();
     wave_sort_keys(sb, c);
-    for (int i = lane; i < P; i += kWave) {
-      const bool ok = i < c;
-      A.pool_ids[(q0 + ql) * P + i] = ok ? (int32_t)(uint32_t)sb[i] : -1;
-      A.pool_d2[(q0 + ql) * P + i] = ok ? __uint_as_float((uint32_t)(sb[i] >> 32)) : INFINITY;
+    const int m = c < P ? c : P;
+    if (A.slices == 1) {
+      for (int i = lane; i < P; i += kWave) {
+        const bool ok = i < m;
+        A.pool_ids[(q0 + ql) * P + i] = ok ? (int32_t)(uint32_t)sb[i] : -1;
+        A.pool_d2[(q0 + ql) * P + i] = ok ? __uint_as_float((uint32_t)(sb[i] >> 32)) : INFINITY;
+      }
+    } else {
+      uint64_t* o = A.part + ((q0 + ql) * A.slices + slice) * P;
+      for (int i = lane; i < m; i += kWave) o[i] = sb[i];
+      if (lane == 0) A.part_cnt[(q0 + ql) * A.slices + slice] = m;
     }
     wsync();
+  }
+}
+
+// One work-group per query: the P smallest keys over all slice pools.
+__global__ void __launch_bounds__(kBlock)
+k_pp_merge(PoolArgs A) {
+  __shared__ SelectSmem sm;
+  __shared__ int32_t pre[257];
+  const int64_t qi = blockIdx.x;
+  const int S = A.slices, P = A.P;
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int s2 = 0; s2 < S; ++s2) {
+      pre[s2] = run;
+      run += A.part_cnt[qi * S + s2];
+    }
+    pre[S] = run;
+  }
+  __syncthreads();
+  const int total = pre[S];
+  const uint64_t* base = A.part + qi * (int64_t)S * P;
+  auto key = [&](int i) {
+    int lo = 0, hi = S - 1;  // slice s with pre[s] <= i < pre[s+1]
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (pre[mid] <= i)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    return ~base[(int64_t)lo * P + (i - pre[lo])];  // larger = better
+  };
+  const int m = block_select_topk<kBlock>(key, total, P, sm);
+  for (int i = threadIdx.x; i < P; i += kBlock) {
+    const bool ok = i < m;
+    const uint64_t k2 = ok ? ~sm.out[i] : 0ull;
+    A.pool_ids[qi * P + i] = ok ? (int32_t)(uint32_t)k2 : -1;
+    A.pool_d2[qi * P + i] = ok ? __uint_as_float((uint32_t)(k2 >> 32)) : INFINITY;
   }
 }
 
@@ -354,20 +426,45 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   int P = 32;
   while (P < c->pp_pool || P < 4 * k) P <<= 1;
   if (P > 1024) P = 1024;
-  const int cap = std::max(2 * P, P + kChunk);
+  // buffer: P kept keys, at least P more before a compaction is worth its
+  // sort, and room for the kCheckEvery chunks between checks
+  const int cap = 2 * P + kCheckEvery * kChunk;
   const float scale = (float)c->R;
-  const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * cap;
+  // split the database into slices when the batch has few query tiles,
+  // so that about two work-groups per CU scan it
+  const int64_t tiles = (nq + kQW - 1) / kQW;
+  int64_t S = (2 * (int64_t)c->num_cus + tiles - 1) / tiles;
+  S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, c->n / 4096));
+  const int64_t rps = ((c->n + S - 1) / S + kChunk - 1) / kChunk * kChunk;
+  const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
+  const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;
+  const size_t cnt_bytes = S > 1 ? sizeof(int32_t) * (size_t)nq * S : 0;
   const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
-  TRY(ctx_ensure(c, lane->b_pool, buf_bytes + ids_bytes, "pools"));
+  TRY(ctx_ensure(c, lane->b_pool, buf_bytes + part_bytes + cnt_bytes + ids_bytes + 256, "pools"));
   TRY(ctx_ensure(c, lane->b_stats, 64, "pp stats"));
-  uint64_t* buf = static_cast<uint64_t*>(lane->b_pool.p);
-  int32_t* pool_ids = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(buf) + buf_bytes);
+  char* base = static_cast<char*>(lane->b_pool.p);
+  uint64_t* buf = reinterpret_cast<uint64_t*>(base);
+  uint64_t* part = reinterpret_cast<uint64_t*>(base + buf_bytes);
+  int32_t* part_cnt = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes);
+  int32_t* pool_ids = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes + cnt_bytes);
   float* pool_d2 = reinterpret_cast<float*>(pool_ids + (size_t)nq * P);
   HIPTRY(hipMemsetAsync(lane->b_stats.p, 0, 64, s), "pp stats");
+  int sort_cap = 2;
+  while (sort_cap < cap) sort_cap <<= 1;
   PoolArgs pa{static_cast<const __bf16*>(pp->b_bf16.p), static_cast<const float*>(pp->b_norm.p),
-              c->n, dq, nq, P, cap, buf, pool_ids, pool_d2};
-  k_pp_pool<<<(unsigned)((nq + kQW - 1) / kQW), kBlock, 0, s>>>(pa);
+              c->n, dq, nq, P, cap, (int32_t)S, (int32_t)rps, sort_cap, buf, part, part_cnt,
+              pool_ids, pool_d2};
+  const size_t sort_lds = sizeof(uint64_t) * (size_t)sort_cap * (kBlock / kWave);
+  HIPTRY(hipFuncSetAttribute((const void*)k_pp_pool, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sort_lds),
+         "pp pool attribute");
+  k_pp_pool<<<dim3((unsigned)tiles, (unsigned)S), kBlock, sort_lds, s>>>(pa);
   HIPTRY(hipGetLastError(), "pp pool");
+  if (S > 1) {
+    k_pp_merge<<<(unsigned)nq, kBlock, 0, s>>>(pa);
+    HIPTRY(hipGetLastError(), "pp merge");
+  }
   unsigned long long* st = static_cast<unsigned long long*>(lane->b_stats.p);
   RerankArgs ra{c->d_theta, D, dq, nq, P, k, pool_ids, pool_d2,
                 1.0f / (scale * scale), d_ids, d_dist, st, st + 1, st + 2};

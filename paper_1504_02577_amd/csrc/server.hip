@@ -97,7 +97,7 @@ static size_t request_mem(const panther_server* sv, int kind, int32_t k) {
     int P = 32;
     while (P < sv->c->pp_pool || P < 4 * k) P <<= 1;
     if (P > 1024) P = 1024;
-    const size_t cap = std::max(2 * P, P + 64);
+    const size_t cap = 2 * (size_t)P + 256;
     b += cap * 8 + (size_t)P * 8;
   }
   return b;
