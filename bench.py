@@ -39,11 +39,11 @@ def log(*a):
 
 
 def walk_algorithmic_bytes(R, T):
-    """Bytes the guide-table walk must move per launch: per step a 16-byte
-    vertex record, a 4-byte guide entry, one 8-byte {prefix, column} record
-    and the 4-byte vertex written; per path the 4-byte start-set read and
-    the 4-byte start vertex written."""
-    return R * (T * (16 + 4 + 8 + 4) + 8)
+    """Bytes the walk must move per launch: per step one 64-byte guide
+    record (three candidate edges with their targets' records) and the
+    4-byte vertex written; per path the 16-byte start record and the 4-byte
+    start written."""
+    return R * (T * (64 + 4) + 20)
 
 
 def measured_traffic(kernel):

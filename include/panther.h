@@ -138,7 +138,7 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
 /* Integer options: "topk.form" (PANTHER_FORM_*; default BATCHED),
  * "pp.form" (PANTHER_PP_*; default BF16), "pp.pool" (candidate pool per
  * query of the BF16 form, 32..1024, default 256; the pool used is the
- * smallest power of two >= max(pp.pool, 4k), at most 1024), "autotune" (0/1,
+ * smallest power of two >= max(pp.pool, 2k), at most 1024), "autotune" (0/1,
  * default 1), "timing" (0/1, default 0; see panther_stage_times),
  * "batch.block" (0 = autotuned, 256, 512), "batch.wgs_per_cu" (0 =
  * autotuned, 1, 2), "batch.tier_a" / "batch.tier_b" (caps on the path-list

@@ -24,9 +24,11 @@ constexpr int kBlock = 256;
 // histograms in digit-major order, and a down-sweep that ranks every item
 // stably inside its tile and scatters it to
 //   offset[digit][tile] + (same-digit items before it in the tile).
-// The in-tile rank comes from 64-item chunks: a wave matches digits across
-// its lanes with one ballot per digit bit, chunk histograms are scanned per
-// digit, and the rank is chunk prefix + lanes below with the same digit.
+// The tile lives in registers (thread t holds items j * 256 + t, so each
+// wavefront holds whole 64-item chunks).  The in-tile rank comes from those
+// chunks: a wave matches digits across its lanes with one ballot per digit
+// bit, chunk histograms (LDS) are scanned per digit, and the rank is chunk
+// prefix + lanes below with the same digit.
 // No atomics touch global memory, so the order of equal vertices is the
 // path-id order of the input and the index is deterministic.
 // ---------------------------------------------------------------------------
@@ -35,25 +37,104 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kTileItems = 4096;
 constexpr int kChunks = kTileItems / kWave;
 
-struct RadixSmem {
-  uint32_t key[kTileItems];
-  uint32_t val[kTileItems];
-  uint16_t chunk[kChunks][kRadix];  // chunk histograms, then exclusive prefixes
-  uint8_t rank[kTileItems];
-  uint32_t scan[kBlock / kWave + 1];
-  uint32_t n;
-};
-
 __device__ __forceinline__ uint32_t digit_of(uint32_t key, int shift, int bits) {
   return (key >> shift) & ((1u << bits) - 1u);
 }
 
-// Loads the distinct vertices of the tile's paths into sm.key/sm.val in
-// path-id order; returns the item count.
 template <int S>
-__device__ int load_tile_from_paths(const int32_t* __restrict__ paths, uint64_t R, uint64_t p0,
-                                    int ppt, RadixSmem& sm) {
+__global__ void __launch_bounds__(kBlock)
+k_radix_up_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shift, int bits,
+                 uint64_t ntiles, uint32_t* __restrict__ hist) {
+  // a histogram needs no order: digits straight from the de-duplicated rows
+  __shared__ uint32_t s_hist[kRadix];
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
+  __syncthreads();
+  const uint64_t p0 = (uint64_t)blockIdx.x * ppt;
+  for (int r = threadIdx.x; r < ppt; r += kBlock) {
+    const uint64_t pid = p0 + r;
+    if (pid >= R) break;
+    int32_t v[S];
+    load_row<S>(paths, pid, v);
+    dedup_row<S>(v);
+#pragma unroll
+    for (int i = 0; i < S; ++i)
+      if (v[i] >= 0) atomicAdd(&s_hist[digit_of((uint32_t)v[i], shift, bits)], 1u);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
+}
+
+// Ranks and scatters a tile held in registers (thread t holds items
+// j * 256 + t), using `chunk` (64 x 256 uint16 in LDS) for the histograms.
+__device__ __forceinline__ void rank_scatter_regs(const uint32_t (&k)[16], const uint32_t (&v)[16],
+                                                  int n, int shift, int bits,
+                                                  uint16_t (*chunk)[kRadix],
+                                                  const uint64_t* __restrict__ offsets,
+                                                  uint64_t ntiles, uint64_t tile,
+                                                  uint32_t* __restrict__ key_out,
+                                                  uint32_t* __restrict__ val_out) {
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t rk[16];
+  for (int i = threadIdx.x; i < kChunks * kRadix; i += kBlock) (&chunk[0][0])[i] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = j * kBlock + threadIdx.x;
+    const int c = j * (kBlock / kWave) + wid;
+    const bool live = i < n;
+    const uint32_t d = live ? digit_of(k[j], shift, bits) : 0u;
+    uint64_t same = __ballot(live);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const uint64_t m = __ballot(live && ((d >> b) & 1u));
+      same &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const uint64_t below = same & ((1ull << lane) - 1ull);
+    rk[j] = (uint32_t)__popcll(below);
+    if (live && below == 0) chunk[c][d] = (uint16_t)__popcll(same);
+  }
+  __syncthreads();
+  const int nchunks = (n + kWave - 1) / kWave;
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) {
+    uint32_t run = 0;
+    for (int c = 0; c < nchunks; ++c) {
+      const uint32_t x = chunk[c][d];
+      chunk[c][d] = (uint16_t)run;
+      run += x;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = j * kBlock + threadIdx.x;
+    if (i < n) {
+      const uint32_t d = digit_of(k[j], shift, bits);
+      const int c = j * (kBlock / kWave) + wid;
+      const uint64_t pos = offsets[(uint64_t)d * ntiles + tile] + chunk[c][d] + rk[j];
+      if (key_out) key_out[pos] = k[j];
+      val_out[pos] = v[j];
+    }
+  }
+}
+
+struct StageSmem {
+  uint32_t key[kTileItems];
+  uint32_t val[kTileItems];
+  uint32_t scan[kBlock / kWave + 1];
+};
+
+template <int S>
+__global__ void __launch_bounds__(kBlock)
+k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shift, int bits,
+                   uint64_t ntiles, const uint64_t* __restrict__ offsets,
+                   uint32_t* __restrict__ key_out, uint32_t* __restrict__ val_out) {
+  // 32 KB of LDS: first the compacted (vertex, path id) pairs in path-id
+  // order, then -- once they are in registers -- the chunk histograms
+  __shared__ __align__(16) unsigned char raw[sizeof(StageSmem)];
+  StageSmem& st = *reinterpret_cast<StageSmem*>(raw);
+  uint16_t (*chunk)[kRadix] = reinterpret_cast<uint16_t (*)[kRadix]>(raw);
   int base = 0;
+  const uint64_t p0 = (uint64_t)blockIdx.x * ppt;
   for (int r0 = 0; r0 < ppt; r0 += kBlock) {
     const uint64_t pid = p0 + r0 + threadIdx.x;
     int32_t v[S];
@@ -69,105 +150,28 @@ __device__ int load_tile_from_paths(const int32_t* __restrict__ paths, uint64_t 
 #pragma unroll
     for (int i = 0; i < S; ++i) cnt += v[i] >= 0 ? 1u : 0u;
     uint32_t tot;
-    uint32_t off = block_exclusive_sum<kBlock>(cnt, sm.scan, &tot);
+    uint32_t off = block_exclusive_sum<kBlock>(cnt, st.scan, &tot);
     uint32_t o = (uint32_t)base + off;
 #pragma unroll
     for (int i = 0; i < S; ++i)
       if (v[i] >= 0) {
-        sm.key[o] = (uint32_t)v[i];
-        sm.val[o] = (uint32_t)pid;
+        st.key[o] = (uint32_t)v[i];
+        st.val[o] = (uint32_t)pid;
         ++o;
       }
     base += (int)tot;
   }
   __syncthreads();
-  return base;
-}
-
-__device__ void tile_histogram(const RadixSmem& sm, int n, int shift, int bits, uint32_t* hist,
-                               uint32_t* s_hist) {
-  for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kBlock) atomicAdd(&s_hist[digit_of(sm.key[i], shift, bits)], 1u);
-  __syncthreads();
-}
-
-// In-tile stable ranks (chunk prefix + in-chunk rank), then the scatter.
-__device__ void rank_and_scatter(RadixSmem& sm, int n, int shift, int bits,
-                                 const uint64_t* __restrict__ offsets, uint64_t ntiles,
-                                 uint64_t tile, uint32_t* __restrict__ key_out,
-                                 uint32_t* __restrict__ val_out) {
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int nchunks = (n + kWave - 1) / kWave;
-  for (int i = threadIdx.x; i < kChunks * kRadix; i += kBlock)
-    (&sm.chunk[0][0])[i] = 0;
-  __syncthreads();
-  for (int c = wid; c < nchunks; c += kBlock / kWave) {
-    const int i = c * kWave + lane;
-    const bool live = i < n;
-    const uint32_t d = live ? digit_of(sm.key[i], shift, bits) : 0xFFFFu;
-    uint64_t same = __ballot(live);
+  const int n = base;
+  uint32_t k[16], vv[16];
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const uint64_t m = __ballot(live && ((d >> b) & 1u));
-      same &= ((d >> b) & 1u) ? m : ~m;
-    }
-    if (live) {
-      const uint64_t below = same & ((1ull << lane) - 1ull);
-      sm.rank[i] = (uint8_t)__popcll(below);
-      if (below == 0) sm.chunk[c][d] = (uint16_t)__popcll(same);
-    }
+  for (int j = 0; j < 16; ++j) {
+    const int i = j * kBlock + threadIdx.x;
+    k[j] = i < n ? st.key[i] : 0u;
+    vv[j] = i < n ? st.val[i] : 0u;
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += kBlock) {
-    uint32_t run = 0;
-    for (int c = 0; c < nchunks; ++c) {
-      const uint32_t x = sm.chunk[c][d];
-      sm.chunk[c][d] = (uint16_t)run;
-      run += x;
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    const uint32_t key = sm.key[i];
-    const uint32_t d = digit_of(key, shift, bits);
-    const uint64_t pos = offsets[(uint64_t)d * ntiles + tile] + sm.chunk[i / kWave][d] + sm.rank[i];
-    if (key_out) key_out[pos] = key;
-    val_out[pos] = sm.val[i];
-  }
-}
-
-template <int S>
-__global__ void __launch_bounds__(kBlock)
-k_radix_up_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shift, int bits,
-                 uint64_t ntiles, uint32_t* __restrict__ hist) {
-  __shared__ RadixSmem sm;
-  __shared__ uint32_t s_hist[kRadix];
-  const int n = load_tile_from_paths<S>(paths, R, (uint64_t)blockIdx.x * ppt, ppt, sm);
-  tile_histogram(sm, n, shift, bits, hist, s_hist);
-  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
-}
-
-template <int S>
-__global__ void __launch_bounds__(kBlock)
-k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shift, int bits,
-                   uint64_t ntiles, const uint64_t* __restrict__ offsets,
-                   uint32_t* __restrict__ key_out, uint32_t* __restrict__ val_out) {
-  __shared__ RadixSmem sm;
-  const int n = load_tile_from_paths<S>(paths, R, (uint64_t)blockIdx.x * ppt, ppt, sm);
-  rank_and_scatter(sm, n, shift, bits, offsets, ntiles, blockIdx.x, key_out, val_out);
-}
-
-__device__ int load_tile_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                               uint64_t nnz, uint64_t tile, RadixSmem& sm, bool with_vals) {
-  const uint64_t a = tile * kTileItems;
-  const int n = (int)((nnz - a) < (uint64_t)kTileItems ? (nnz - a) : (uint64_t)kTileItems);
-  for (int i = threadIdx.x; i < n; i += kBlock) {
-    sm.key[i] = keys[a + i];
-    if (with_vals) sm.val[i] = vals[a + i];
-  }
-  __syncthreads();
-  return n;
+  rank_scatter_regs(k, vv, n, shift, bits, chunk, offsets, ntiles, blockIdx.x, key_out, val_out);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -183,14 +187,23 @@ k_radix_up_pairs(const uint32_t* __restrict__ keys, uint64_t nnz, int shift, int
   for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
 }
 
+// Passes >= 2: the tile of 4096 consecutive pairs goes straight to registers.
 __global__ void __launch_bounds__(kBlock)
 k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                    uint64_t nnz, int shift, int bits, uint64_t ntiles,
                    const uint64_t* __restrict__ offsets, uint32_t* __restrict__ key_out,
                    uint32_t* __restrict__ val_out) {
-  __shared__ RadixSmem sm;
-  const int n = load_tile_pairs(keys, vals, nnz, blockIdx.x, sm, true);
-  rank_and_scatter(sm, n, shift, bits, offsets, ntiles, blockIdx.x, key_out, val_out);
+  __shared__ uint16_t chunk[kChunks][kRadix];
+  const uint64_t a = (uint64_t)blockIdx.x * kTileItems;
+  const int n = (int)((nnz - a) < (uint64_t)kTileItems ? (nnz - a) : (uint64_t)kTileItems);
+  uint32_t k[16], v[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int i = j * kBlock + threadIdx.x;
+    k[j] = i < n ? keys[a + i] : 0u;
+    v[j] = i < n ? vals[a + i] : 0u;
+  }
+  rank_scatter_regs(k, v, n, shift, bits, chunk, offsets, ntiles, blockIdx.x, key_out, val_out);
 }
 
 // inv_ptr from the sorted vertex keys: position i opens the lists of every

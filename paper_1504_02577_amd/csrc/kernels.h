@@ -43,6 +43,15 @@ void launch_pack_edges(const uint32_t* pfx, const int32_t* col, int64_t m, uint2
 void launch_guide(const VRec* vrec, const uint32_t* pfx, int32_t n, const int32_t* big_rows,
                   uint32_t n_big, int32_t* guide, hipStream_t s);
 
+// 64-byte fat guide records (4 x uint4 per bucket), see prep.hip.
+void launch_fat_guide(const VRec* vrec, const uint32_t* pfx, const int32_t* col,
+                      const int32_t* guide, int32_t n, const int32_t* big_rows, uint32_t n_big,
+                      uint4* fat, hipStream_t s);
+
+// {vertex, row start, degree, W} per start-set entry (32-bit weight sums).
+void launch_start_records(const int32_t* vstart, int32_t nstart, const VRec* vrec, int4* out,
+                          hipStream_t s);
+
 // ---- device-wide exclusive scan: out[i] = sum in[0..i), out[n] = total ----
 size_t scan_temp_bytes(int64_t n);
 void launch_scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, void* temp,
@@ -54,8 +63,8 @@ void launch_scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, void* 
 void launch_walk64(int stride, const VRec* vrec, const uint64_t* pfx, const int32_t* col,
                    const int32_t* vstart, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
                    int32_t* paths, hipStream_t s);
-void launch_walk32(int stride, const VRec* vrec, const uint2* edge, const int32_t* guide,
-                   const int32_t* vstart, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
+void launch_walk32(int stride, const VRec* vrec, const uint2* edge, const uint4* fat,
+                   const int4* start_rec, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
                    int32_t* paths, hipStream_t s);
 
 // ---- index by stable LSD radix sort of (vertex, path id) pairs ----

@@ -421,10 +421,10 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   PPState* pp = c->pp;
   if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
   if (!pp || pp->bf16_D != D) return ctx_fail(c, PANTHER_ESTATE, "bf16 rows not prepared");
-  // pool: at least the option and at least 4k (margin for the bfloat16
+  // pool: at least the option and at least 2k (margin for the bfloat16
   // rounding at the pool boundary), a power of two, at most 1024
   int P = 32;
-  while (P < c->pp_pool || P < 4 * k) P <<= 1;
+  while (P < c->pp_pool || P < 2 * k) P <<= 1;
   if (P > 1024) P = 1024;
   // buffer: P kept keys, at least P more before a compaction is worth its
   // sort, and room for the kCheckEvery chunks between checks
@@ -436,6 +436,7 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   int64_t S = (2 * (int64_t)c->num_cus + tiles - 1) / tiles;
   S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
   S = std::min<int64_t>(S, std::max<int64_t>(1, c->n / 4096));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, 32768 / P));  // bounds the merge work
   const int64_t rps = ((c->n + S - 1) / S + kChunk - 1) / kChunk * kChunk;
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
   const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;

@@ -176,6 +176,70 @@ k_guide_big(const VRec* __restrict__ vrec, const uint32_t* __restrict__ pfx,
     guide[rec.start + b] = guide_entry(pfx, rec.start, rec.deg, W, b);
 }
 
+// Fat guide record of bucket b (64 bytes, 16 words): the first three
+// candidate edges from the guide entry e0 onward, each as {inclusive
+// prefix, column, target's row start, target's degree, target's W}, and e0
+// itself in word 15.  Candidates past the row end repeat the last edge, whose
+// prefix W_v exceeds every draw, so they are never preferred.
+__device__ __forceinline__ void fat_record(const VRec* __restrict__ vrec,
+                                           const uint32_t* __restrict__ pfx,
+                                           const int32_t* __restrict__ col, int32_t start,
+                                           int32_t deg, int32_t e0, uint4* __restrict__ out) {
+  uint32_t w[16];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    int32_t e = e0 + j;
+    if (e > start + deg - 1) e = start + deg - 1;
+    const int32_t t = col[e];
+    const VRec r = vrec[t];
+    w[5 * j + 0] = pfx[e];
+    w[5 * j + 1] = (uint32_t)t;
+    w[5 * j + 2] = (uint32_t)r.start;
+    w[5 * j + 3] = (uint32_t)r.deg;
+    w[5 * j + 4] = r.w_lo;
+  }
+  w[15] = (uint32_t)e0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fat_small(const VRec* __restrict__ vrec, const uint32_t* __restrict__ pfx,
+            const int32_t* __restrict__ col, const int32_t* __restrict__ guide, int32_t n,
+            uint4* __restrict__ fat) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  const VRec r = vrec[v];
+  if (r.deg > 256 || r.deg == 0 || (r.w_lo | r.w_hi) == 0) return;
+  for (int32_t b = 0; b < r.deg; ++b)
+    fat_record(vrec, pfx, col, r.start, r.deg, guide[r.start + b], fat + 4 * (int64_t)(r.start + b));
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_fat_big(const VRec* __restrict__ vrec, const uint32_t* __restrict__ pfx,
+          const int32_t* __restrict__ col, const int32_t* __restrict__ guide,
+          const int32_t* __restrict__ big_rows, uint32_t n_big, uint4* __restrict__ fat) {
+  const uint32_t rr = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+  if (rr >= n_big) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const VRec r = vrec[big_rows[rr]];
+  if ((r.w_lo | r.w_hi) == 0) return;
+  for (int32_t b = lane; b < r.deg; b += kWave)
+    fat_record(vrec, pfx, col, r.start, r.deg, guide[r.start + b], fat + 4 * (int64_t)(r.start + b));
+}
+
+// Start records: {vertex, row start, degree, W} of each start-set entry, so
+// the walk's first step reads one 16-byte record instead of two lines.
+__global__ void __launch_bounds__(kBlock)
+k_start_records(const int32_t* __restrict__ vstart, int32_t nstart, const VRec* __restrict__ vrec,
+                int4* __restrict__ out) {
+  const int32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nstart) return;
+  const int32_t v = vstart[i];
+  const VRec r = vrec[v];
+  out[i] = make_int4(v, r.start, r.deg, (int32_t)r.w_lo);
+}
+
 // ---- device-wide exclusive scan (reduce tiles, scan tile sums, apply) ----
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;
@@ -303,6 +367,20 @@ void launch_guide(const VRec* vrec, const uint32_t* pfx, int32_t n, const int32_
   if (n_big)
     k_guide_big<<<grid_for(n_big, kBlock / kWave), kBlock, 0, s>>>(vrec, pfx, big_rows, n_big,
                                                                   guide);
+}
+
+void launch_fat_guide(const VRec* vrec, const uint32_t* pfx, const int32_t* col,
+                      const int32_t* guide, int32_t n, const int32_t* big_rows, uint32_t n_big,
+                      uint4* fat, hipStream_t s) {
+  k_fat_small<<<grid_for(n, kBlock), kBlock, 0, s>>>(vrec, pfx, col, guide, n, fat);
+  if (n_big)
+    k_fat_big<<<grid_for(n_big, kBlock / kWave), kBlock, 0, s>>>(vrec, pfx, col, guide, big_rows,
+                                                                n_big, fat);
+}
+
+void launch_start_records(const int32_t* vstart, int32_t nstart, const VRec* vrec, int4* out,
+                          hipStream_t s) {
+  k_start_records<<<grid_for(nstart, kBlock), kBlock, 0, s>>>(vstart, nstart, vrec, out);
 }
 
 size_t scan_temp_bytes(int64_t n) {

@@ -58,7 +58,8 @@ struct panther_ctx {
   void* d_pfx = nullptr;
   bool pfx64 = false;
   uint2* d_edge = nullptr;    // {prefix, column} when every W_v < 2^32
-  int32_t* d_guide = nullptr; // guide table, same case
+  uint4* d_fat = nullptr;     // 64-byte guide records, same case
+  int4* d_start_rec = nullptr;  // {v, row start, degree, W} per start entry, same case
   int32_t* d_vstart = nullptr;
   int32_t nstart = 0;
   uint64_t max_w = 0;

@@ -125,9 +125,11 @@ static void free_graph(panther_ctx* c) {
   ctx_free(c->d_pfx);
   ctx_free(c->d_vstart);
   ctx_free(c->d_edge);
-  ctx_free(c->d_guide);
+  ctx_free(c->d_fat);
+  ctx_free(c->d_start_rec);
   c->d_edge = nullptr;
-  c->d_guide = nullptr;
+  c->d_fat = nullptr;
+  c->d_start_rec = nullptr;
   c->d_col = nullptr;
   c->d_vrec = nullptr;
   c->d_pfx = nullptr;
@@ -415,10 +417,17 @@ extern "C" int panther_load_graph(panther_ctx* c, int32_t n, int64_t m, const in
     TRY(ctx_alloc(c, &p, sizeof(uint2) * (size_t)m, "packed edges"));
     c->d_edge = static_cast<uint2*>(p);
     TRY(ctx_alloc(c, &p, sizeof(int32_t) * (size_t)m, "guide table"));
-    c->d_guide = static_cast<int32_t*>(p);
+    tmp.add(p);
+    int32_t* guide = static_cast<int32_t*>(p);
+    TRY(ctx_alloc(c, &p, 4 * sizeof(uint4) * (size_t)m, "guide records"));
+    c->d_fat = static_cast<uint4*>(p);
     launch_pack_edges(static_cast<const uint32_t*>(c->d_pfx), d_col, m, c->d_edge, s);
-    launch_guide(c->d_vrec, static_cast<const uint32_t*>(c->d_pfx), n, big, n_big, c->d_guide,
-                 s);
+    launch_guide(c->d_vrec, static_cast<const uint32_t*>(c->d_pfx), n, big, n_big, guide, s);
+    launch_fat_guide(c->d_vrec, static_cast<const uint32_t*>(c->d_pfx), d_col, guide, n, big,
+                     n_big, c->d_fat, s);
+    TRY(ctx_alloc(c, &p, sizeof(int4) * (size_t)nstart, "start records"));
+    c->d_start_rec = static_cast<int4*>(p);
+    launch_start_records(c->d_vstart, (int32_t)nstart, c->d_vrec, c->d_start_rec, s);
   }
   HIPTRY(hipGetLastError(), "prefix");
   HIPTRY(hipStreamSynchronize(s), "load_graph");
@@ -516,7 +525,7 @@ extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64
     launch_walk64(stride, c->d_vrec, static_cast<const uint64_t*>(c->d_pfx), c->d_col,
                   c->d_vstart, c->nstart, T, (uint64_t)R, seed, c->d_paths, c->stream);
   else
-    launch_walk32(stride, c->d_vrec, c->d_edge, c->d_guide, c->d_vstart, c->nstart, T,
+    launch_walk32(stride, c->d_vrec, c->d_edge, c->d_fat, c->d_start_rec, c->nstart, T,
                   (uint64_t)R, seed, c->d_paths, c->stream);
   stage_end(c, 0, c->stream);
   st = ctx_hip(c, hipGetLastError(), "walk");

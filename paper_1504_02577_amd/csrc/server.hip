@@ -95,7 +95,7 @@ static size_t request_mem(const panther_server* sv, int kind, int32_t k) {
   size_t b = (size_t)k * 16 + 64;
   if (kind == 1) {
     int P = 32;
-    while (P < sv->c->pp_pool || P < 4 * k) P <<= 1;
+    while (P < sv->c->pp_pool || P < 2 * k) P <<= 1;
     if (P > 1024) P = 1024;
     const size_t cap = 2 * (size_t)P + 256;
     b += cap * 8 + (size_t)P * 8;

@@ -7,11 +7,14 @@
 // keeps the walk in place.
 //
 // Rows whose weight sums fit 32 bits use a guide table: bucket
-// b = floor(r_t * deg / 2^64) names the first edge any draw of that bucket
-// can select, and a short forward scan over packed {prefix, column} records
-// (8 bytes, eight to a 64-byte line) finds the edge -- the same edge as a
-// bisection, in about one cache line instead of log2(deg).  Per step: one
-// 16-byte vertex record, one 4-byte guide entry, and the scanned records.
+// b = floor(r_t * deg / 2^64) names the first edge e0 any draw of that bucket
+// can select.  Its 64-byte record (one aligned line) holds the edges e0,
+// e0+1, e0+2 with their inclusive prefixes, targets and the targets' own
+// {row start, degree, W}, so the usual step reads one line and already has
+// the next vertex's record; only when the draw lies beyond e0+2 does the
+// step scan packed {prefix, column} records and load the vertex record.
+// The chosen edge is always the first whose prefix exceeds u, as in a
+// bisection.
 // Rows with 64-bit sums use the bisection over separate prefix and column
 // arrays.  Each path's T+1 vertices are written once as 16-byte stores.
 #include "common.h"
@@ -36,42 +39,58 @@ __device__ __forceinline__ void store_row(int32_t* __restrict__ paths, uint64_t 
 template <int S>
 __global__ void __launch_bounds__(kBlock)
 k_walk32(const VRec* __restrict__ vrec, const uint2* __restrict__ edge,
-         const int32_t* __restrict__ guide, const int32_t* __restrict__ vstart, int32_t nstart,
+         const uint4* __restrict__ fat, const int4* __restrict__ start_rec, int32_t nstart,
          int32_t T, uint64_t R, PhiloxKey key, int32_t* __restrict__ paths) {
   const uint64_t pid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (pid >= R) return;
   int32_t row[S];
-  int32_t v = vstart[scale64(draw(key, pid, 0u), (uint64_t)nstart)];
+  const int4 s0 = start_rec[scale64(draw(key, pid, 0u), (uint64_t)nstart)];
+  int32_t v = s0.x;
   row[0] = v;
+  VRec cur = VRec{s0.y, s0.z, (uint32_t)s0.w, 0u};
 #pragma unroll
   for (int t = 1; t < S; ++t) {
     if (t <= T) {
       const uint64_t r = draw(key, pid, (uint32_t)t);
-      const VRec rec = vrec[v];
-      const uint32_t W = rec.w_lo;  // w_hi == 0 on this path
+      const uint32_t W = cur.w_lo;  // w_hi == 0 on this path
       if (W != 0u) {
         const uint32_t u = (uint32_t)scale64(r, (uint64_t)W);
-        int32_t e = guide[rec.start + (int32_t)scale64(r, (uint64_t)rec.deg)];
-        uint2 x = edge[e];
-        int steps = 0;
-        while (x.x <= u && steps < kScanMax) {
-          ++e;
-          x = edge[e];
-          ++steps;
-        }
-        if (x.x <= u) {
-          // rare: bisection over the rest of the row
-          int32_t lo = e + 1, hi = rec.start + rec.deg - 1;
-          while (lo < hi) {
-            const int32_t mid = lo + ((hi - lo) >> 1);
-            if (edge[mid].x > u)
-              hi = mid;
-            else
-              lo = mid + 1;
+        const uint4* g = fat + 4 * (int64_t)(cur.start + (int32_t)scale64(r, (uint64_t)cur.deg));
+        const uint4 g0 = g[0], g1 = g[1], g2 = g[2], g3 = g[3];
+        // words: [pfx0 col0 st0 dg0] [W0 pfx1 col1 st1] [dg1 W1 pfx2 col2] [st2 dg2 W2 e0]
+        if (u < g0.x) {
+          v = (int32_t)g0.y;
+          cur = VRec{(int32_t)g0.z, (int32_t)g0.w, g1.x, 0u};
+        } else if (u < g1.y) {
+          v = (int32_t)g1.z;
+          cur = VRec{(int32_t)g1.w, (int32_t)g2.x, g2.y, 0u};
+        } else if (u < g2.z) {
+          v = (int32_t)g2.w;
+          cur = VRec{(int32_t)g3.x, (int32_t)g3.y, g3.z, 0u};
+        } else {
+          // rare: scan on from the fourth candidate, bisection after kScanMax
+          int32_t e = (int32_t)g3.w + 3;
+          uint2 x = edge[e];
+          int steps = 0;
+          while (x.x <= u && steps < kScanMax) {
+            ++e;
+            x = edge[e];
+            ++steps;
           }
-          x = edge[lo];
+          if (x.x <= u) {
+            int32_t lo = e + 1, hi = cur.start + cur.deg - 1;
+            while (lo < hi) {
+              const int32_t mid = lo + ((hi - lo) >> 1);
+              if (edge[mid].x > u)
+                hi = mid;
+              else
+                lo = mid + 1;
+            }
+            x = edge[lo];
+          }
+          v = (int32_t)x.y;
+          cur = vrec[v];
         }
-        v = (int32_t)x.y;
       }
       row[t] = v;
     } else {
@@ -139,13 +158,13 @@ void launch_walk64(int stride, const VRec* vrec, const uint64_t* pfx, const int3
 #undef PANTHER_W64
 }
 
-void launch_walk32(int stride, const VRec* vrec, const uint2* edge, const int32_t* guide,
-                   const int32_t* vstart, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
+void launch_walk32(int stride, const VRec* vrec, const uint2* edge, const uint4* fat,
+                   const int4* start_rec, int32_t nstart, int32_t T, uint64_t R, uint64_t seed,
                    int32_t* paths, hipStream_t s) {
   const PhiloxKey key{(uint32_t)seed, (uint32_t)(seed >> 32)};
   const unsigned grid = (unsigned)((R + kBlock - 1) / kBlock);
 #define PANTHER_W32(SS) \
-  k_walk32<SS><<<grid, kBlock, 0, s>>>(vrec, edge, guide, vstart, nstart, T, R, key, paths)
+  k_walk32<SS><<<grid, kBlock, 0, s>>>(vrec, edge, fat, start_rec, nstart, T, R, key, paths)
   PANTHER_STRIDES(PANTHER_W32)
 #undef PANTHER_W32
 }
