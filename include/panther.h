@@ -143,7 +143,10 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * "batch.block" (0 = autotuned, 256, 512), "batch.wgs_per_cu" (0 =
  * autotuned, 1, 2), "batch.tier_a" / "batch.tier_b" (caps on the path-list
  * length of the wave and work-group tiers of the batched form; -1 = the
- * LDS-derived default), "test.fail_alloc_after" (the next n device allocations
+ * LDS-derived default; longer lists go to the split hub pipeline),
+ * "batch.hub_bits" (largest log2 bucket count per hub query, 0..12, -1 =
+ * 12; smaller values make buckets overflow their LDS table and take the
+ * sub-range path, for tests), "test.fail_alloc_after" (the next n device allocations
  * succeed, the one after fails with ENOMEM; -1 disables).
  * Errors: EINVAL (unknown key or value out of range). */
 int panther_set_option(panther_ctx *ctx, const char *key, int64_t value);

@@ -11,9 +11,10 @@
 //      wave alone (no work-group barrier).
 //   B  (fits half of a work-group LDS table): one work-group per query, LDS
 //      hash, then block selection of the k largest keys.
-//   C  (hubs): one work-group per query with a dense per-vertex counter
-//      array in global memory owned by that work-group, a touched list, and
-//      the same block selection; counters are cleared after use.
+//   C  (hubs, the rest): split across many work-groups by the pipeline in
+//      hub.hip (candidates bucketed by a hash of their id, each bucket
+//      counted in LDS by its own work-group, per-bucket winners merged),
+//      enqueued on the same stream ahead of the persistent kernel.
 // Counting is exact integer arithmetic and the ranking key (count desc, id
 // asc) is a total order, so the result equals the plain form bit for bit.
 #include <algorithm>
@@ -29,25 +30,23 @@
 #include "../../include/panther.h"
 #include "common.h"
 #include "runtime.h"
+#include "hub.h"
+#include "kernels.h"
 
 using namespace panther;
 
 namespace {
 
-constexpr int kQueueCtl = 4;  // [0] C head, [1] AB head
+constexpr int kQueueCtl = 4;  // [0] work-queue head
 
 struct BatchArgs {
   const int32_t* queries;  // [nq]
-  const int32_t* itemsC;   // query indices, hubs, longest first
-  const int32_t* itemsB;
+  const int32_t* itemsB;   // query indices, longest class first
   const int32_t* itemsA;
-  int32_t nC, nB, nA;
-  int32_t hub_wgs;         // work-groups that own a dense slot
+  int32_t nB, nA;
   const uint64_t* inv_ptr;
   const uint32_t* inv_pid;
   const int32_t* paths;
-  uint32_t* slot_cnt;      // [hub_wgs][n]
-  int32_t* slot_touched;   // [hub_wgs][n]
   uint32_t* queue;         // kQueueCtl words
   int32_t n;
   int32_t k;
@@ -214,56 +213,6 @@ __device__ void block_query_lds(const BatchArgs& A, int32_t qi, char* region, Se
   __syncthreads();
 }
 
-// ---- tier C: one work-group per hub query, dense global counters ----
-template <int BLOCK, int S>
-__device__ void block_query_dense(const BatchArgs& A, int32_t qi, uint32_t* cnt, int32_t* touched,
-                                  SelectSmem& sm, uint32_t* s_ctl) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int32_t q = A.queries[qi];
-  const uint64_t a = A.inv_ptr[q];
-  const uint64_t L = A.inv_ptr[q + 1] - a;
-  if (threadIdx.x == 0) s_ctl[0] = 0u;
-  __syncthreads();
-  for (uint64_t base = 0; base < L; base += BLOCK) {
-    const uint64_t idx = base + threadIdx.x;
-    int32_t v[S];
-    if (idx < L) {
-      load_row<S>(A.paths, A.inv_pid[a + idx], v);
-      dedup_row<S>(v);
-    } else {
-#pragma unroll
-      for (int j = 0; j < S; ++j) v[j] = -1;
-    }
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      const bool want = v[j] >= 0 && v[j] != q;
-      const uint32_t old = want ? atomicAdd(&cnt[v[j]], 1u) : 1u;
-      const bool fresh = want && old == 0u;
-      const uint64_t bm = __ballot(fresh);
-      if (bm) {
-        uint32_t wbase = 0;
-        if (lane == 0) wbase = atomicAdd(&s_ctl[0], (uint32_t)__popcll(bm));
-        wbase = __shfl(wbase, 0, kWave);
-        if (fresh) touched[wbase + __popcll(bm & ((1ull << lane) - 1ull))] = v[j];
-      }
-    }
-  }
-  __threadfence();
-  __syncthreads();
-  const int nt = (int)s_ctl[0];
-  auto keyfn = [&](int i) {
-    const int32_t v = __hip_atomic_load(&touched[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return rank_key(ld_agent_u32(&cnt[v]), v);
-  };
-  const int m = block_select_topk<BLOCK>(keyfn, nt, A.k, sm);
-  write_row(A, qi, sm.out, m, threadIdx.x, BLOCK);
-  __syncthreads();
-  for (int i = threadIdx.x; i < nt; i += BLOCK)
-    cnt[__hip_atomic_load(&touched[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)] = 0u;
-  __threadfence();
-  __syncthreads();
-}
-
 template <int BLOCK, int S>
 __global__ void __launch_bounds__(BLOCK) k_topk_batched(BatchArgs A) {
   extern __shared__ __align__(16) char lds[];
@@ -271,39 +220,20 @@ __global__ void __launch_bounds__(BLOCK) k_topk_batched(BatchArgs A) {
   uint32_t* s_ctl = reinterpret_cast<uint32_t*>(lds + sizeof(SelectSmem));
   char* region = lds + sizeof(SelectSmem) + 64;
   constexpr int kWaves = BLOCK / kWave;
-  const bool hub = (int)blockIdx.x < A.hub_wgs;
-  bool c_done = !hub;
-  uint32_t* cnt = hub ? A.slot_cnt + (size_t)blockIdx.x * (size_t)A.n : nullptr;
-  int32_t* touched = hub ? A.slot_touched + (size_t)blockIdx.x * (size_t)A.n : nullptr;
   const int nAgroups = (A.nA + kWaves - 1) / kWaves;
   while (true) {
     if (threadIdx.x == 0) {
-      int item = -1;  // encoded: [0, nC) C, [nC, nC+nB) B, then A groups
-      if (!c_done) {
-        const uint32_t x = atomicAdd(&A.queue[0], 1u);
-        if ((int)x < A.nC)
-          item = (int)x;
-        else
-          c_done = true;
-      }
-      if (item < 0) {
-        const uint32_t x = atomicAdd(&A.queue[1], 1u);
-        if ((int)x < A.nB + nAgroups) item = A.nC + (int)x;
-      }
-      s_ctl[1] = (uint32_t)item;
-      s_ctl[2] = c_done ? 1u : 0u;
+      const uint32_t x = atomicAdd(&A.queue[0], 1u);  // [0, nB) B, then A groups
+      s_ctl[1] = (int)x < A.nB + nAgroups ? x : 0xFFFFFFFFu;
     }
     __syncthreads();
     const int item = (int)s_ctl[1];
-    c_done = s_ctl[2] != 0u;
     __syncthreads();
     if (item < 0) break;
-    if (item < A.nC) {
-      block_query_dense<BLOCK, S>(A, A.itemsC[item], cnt, touched, sm, s_ctl + 4);
-    } else if (item < A.nC + A.nB) {
-      block_query_lds<BLOCK, S>(A, A.itemsB[item - A.nC], region, sm, s_ctl + 4);
+    if (item < A.nB) {
+      block_query_lds<BLOCK, S>(A, A.itemsB[item], region, sm, s_ctl + 4);
     } else {
-      const int g = item - A.nC - A.nB;
+      const int g = item - A.nB;
       const int w = threadIdx.x / kWave;
       const int ai = g * kWaves + w;
       if (ai < A.nA)
@@ -340,15 +270,54 @@ struct BatchConfig {
   int wgs_per_cu = 1;   // persistent work-groups per CU
 };
 
+// What one call enqueues: the hub pipeline chunk by chunk, then the
+// persistent kernel over tiers A and B.
+struct Plan {
+  BatchArgs args{};
+  bool run_kernel = false;
+  std::vector<HubArgs> hub;
+  bool operator==(const Plan& o) const {
+    if (run_kernel != o.run_kernel || hub.size() != o.hub.size()) return false;
+    if (std::memcmp(&args, &o.args, sizeof(args)) != 0) return false;
+    for (size_t i = 0; i < hub.size(); ++i)
+      if (std::memcmp(&hub[i], &o.hub[i], sizeof(HubArgs)) != 0) return false;
+    return true;
+  }
+};
+
 struct BatchState {
   // device plan buffers (grown as needed)
   int32_t* d_items = nullptr;
   size_t items_cap = 0;
   uint32_t* d_queue = nullptr;
-  // dense hub slots
-  uint32_t* d_slot_cnt = nullptr;
-  int32_t* d_slot_touched = nullptr;
-  int slots = 0;
+  // hub pipeline buffers (grown as needed)
+  HubQuery* d_hq = nullptr;
+  size_t hq_cap = 0;
+  int32_t* d_stA = nullptr;
+  size_t occ_cap = 0;
+  int32_t* d_stB = nullptr;
+  size_t occB_cap = 0;
+  uint32_t* d_bkt_cnt = nullptr;
+  size_t bkt_cap = 0;
+  uint32_t* d_bkt_fill = nullptr;
+  size_t bkt_fill_cap = 0;
+  uint64_t* d_bkt_start = nullptr;
+  size_t bkt_start_cap = 0;
+  uint64_t* d_cand = nullptr;
+  size_t cand_cap = 0;
+  HubList* d_hx = nullptr;
+  size_t hx_cap = 0;
+  int32_t* d_tile_owner = nullptr;
+  size_t tile_owner_cap = 0;
+  int32_t* d_stile_owner = nullptr;
+  size_t stile_owner_cap = 0;
+  int32_t* d_bkt_owner = nullptr;
+  size_t bkt_owner_cap = 0;
+  uint32_t* d_cand_n = nullptr;
+  size_t cand_n_cap = 0;
+  char* d_scan = nullptr;
+  size_t scan_cap = 0;
+  std::vector<HubQuery> h_hq;  // must outlive the asynchronous upload
   // configuration
   bool tuned = false;
   BatchConfig cfg;
@@ -356,16 +325,17 @@ struct BatchState {
   int forced_wgs = 0;
   int64_t tier_a_override = -1;
   int64_t tier_b_override = -1;
+  int hub_bits_max = 12;
   // graph cache
   hipGraphExec_t exec = nullptr;
   hipStream_t exec_stream = nullptr;
-  BatchArgs exec_args{};
+  Plan exec_plan;
   int exec_block = 0, exec_grid = 0;
   size_t exec_lds = 0;
   // the previous direct launch (a repeat of it gets captured)
   bool last_valid = false;
   hipStream_t last_stream = nullptr;
-  BatchArgs last_args{};
+  Plan last_plan;
   int last_block = 0, last_grid = 0;
   size_t last_lds = 0;
   std::string tune_key;
@@ -384,6 +354,7 @@ void copy_batch_options(panther_ctx* c, Lane* dst) {
   b->forced_wgs = a->forced_wgs;
   b->tier_a_override = a->tier_a_override;
   b->tier_b_override = a->tier_b_override;
+  b->hub_bits_max = a->hub_bits_max;
   b->tuned = false;
   b->no_tune = true;
 }
@@ -394,8 +365,11 @@ void free_batch_state(Lane* lane) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   ctx_free(b->d_items);
   ctx_free(b->d_queue);
-  ctx_free(b->d_slot_cnt);
-  ctx_free(b->d_slot_touched);
+  for (void* p : {(void*)b->d_hq, (void*)b->d_stA, (void*)b->d_stB, (void*)b->d_bkt_cnt,
+                  (void*)b->d_bkt_fill, (void*)b->d_bkt_start, (void*)b->d_cand,
+                  (void*)b->d_cand_n, (void*)b->d_scan, (void*)b->d_hx,
+                  (void*)b->d_tile_owner, (void*)b->d_stile_owner, (void*)b->d_bkt_owner})
+    ctx_free(p);
   delete b;
   lane->batch = nullptr;
 }
@@ -410,6 +384,9 @@ int set_batch_option(panther_ctx* c, const std::string& key, int64_t value) {
     b->tier_a_override = value;
   } else if (key == "batch.tier_b") {
     b->tier_b_override = value;
+  } else if (key == "batch.hub_bits") {
+    if (value < -1 || value > 12) return ctx_fail(c, PANTHER_EINVAL, "batch.hub_bits in -1..12");
+    b->hub_bits_max = value < 0 ? 12 : (int)value;
   } else if (key == "batch.wgs_per_cu") {
     if (value < 0 || value > 2) return ctx_fail(c, PANTHER_EINVAL, "batch.wgs_per_cu in 0..2");
     b->forced_wgs = (int)value;
@@ -480,57 +457,63 @@ void tune_store(const std::string& key, const BatchConfig& cfg) {
 
 }  // namespace
 
-static int ensure_slots(panther_ctx* c, BatchState* b, int want) {
-  if (b->slots >= want) return PANTHER_OK;
-  ctx_free(b->d_slot_cnt);
-  ctx_free(b->d_slot_touched);
-  b->d_slot_cnt = nullptr;
-  b->d_slot_touched = nullptr;
-  b->slots = 0;
+// Grows a device buffer to hold at least `want` elements of `elem` bytes.
+template <typename P>
+static int grow(panther_ctx* c, P*& ptr, size_t& cap, size_t want, size_t elem, const char* what) {
+  if (cap >= want) return PANTHER_OK;
+  ctx_free(ptr);
+  ptr = nullptr;
+  cap = 0;
   void* p;
-  const size_t per = sizeof(uint32_t) * (size_t)c->n;
-  int st = ctx_alloc(c, &p, per * (size_t)want, "hub counters");
+  const int st = ctx_alloc(c, &p, std::max<size_t>(want, 1) * elem, what);
   if (st) return st;
-  b->d_slot_cnt = static_cast<uint32_t*>(p);
-  st = ctx_alloc(c, &p, per * (size_t)want, "hub touched lists");
-  if (st) return st;
-  b->d_slot_touched = static_cast<int32_t*>(p);
-  st = ctx_hip(c, hipMemsetAsync(b->d_slot_cnt, 0, per * (size_t)want, c->stream), "hub counters");
-  if (st) return st;
-  st = ctx_hip(c, hipStreamSynchronize(c->stream), "hub counters");
-  if (st) return st;
-  b->slots = want;
+  ptr = static_cast<P*>(p);
+  cap = std::max<size_t>(want, 1);
   return PANTHER_OK;
 }
 
-// One launch of the persistent kernel for a prepared plan.
-static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
-                          const BatchArgs& args_in, hipStream_t s, bool use_graph) {
+// Enqueues a plan on stream s: the hub chunks, then the persistent kernel.
+static hipError_t enqueue(panther_ctx* c, BatchState* b, const Plan& P, KernelFn fn, int grid,
+                          int block, size_t lds, hipStream_t s) {
+  for (const HubArgs& h : P.hub) {
+    const hipError_t e = enqueue_hub_chunk(h, c->stride, b->d_scan, s);
+    if (e != hipSuccess) return e;
+  }
+  if (P.run_kernel) {
+    k_reset_queue<<<1, 64, 0, s>>>(P.args.queue);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, P.args);
+  }
+  return hipGetLastError();
+}
+
+// One launch of a prepared plan (a graph replay when it repeats).
+static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const Plan& P,
+                          hipStream_t s, bool use_graph) {
   const Layout lay = layout_for(c, cfg);
-  BatchArgs args = args_in;
   const int grid = c->num_cus * cfg.wgs_per_cu;
-  args.hub_wgs = std::min(grid, b->slots);
   KernelFn fn = cfg.block == 256 ? pick_kernel<256>(c->stride) : pick_kernel<512>(c->stride);
   int st = ctx_hip(c, hipFuncSetAttribute((const void*)fn,
                                           hipFuncAttributeMaxDynamicSharedMemorySize,
                                           (int)lay.lds),
                    "batched kernel attribute");
   if (st) return st;
+  if (!P.hub.empty()) {
+    st = ctx_hip(c, hub_set_attributes(), "hub kernel attributes");
+    if (st) return st;
+  }
   const bool same = b->exec && b->exec_stream == s && b->exec_block == cfg.block &&
-                    b->exec_grid == grid && b->exec_lds == lay.lds &&
-                    std::memcmp(&b->exec_args, &args, sizeof(args)) == 0;
+                    b->exec_grid == grid && b->exec_lds == lay.lds && b->exec_plan == P;
   if (use_graph && same) return ctx_hip(c, hipGraphLaunch(b->exec, s), "batched graph replay");
   // capture only once the same launch comes back: a graph pays off for
   // repeated identical batches, not for a stream of different ones
   const bool repeat = b->last_valid && b->last_stream == s && b->last_block == cfg.block &&
-                      b->last_grid == grid && b->last_lds == lay.lds &&
-                      std::memcmp(&b->last_args, &args, sizeof(args)) == 0;
+                      b->last_grid == grid && b->last_lds == lay.lds && b->last_plan == P;
   b->last_valid = true;
   b->last_stream = s;
   b->last_block = cfg.block;
   b->last_grid = grid;
   b->last_lds = lay.lds;
-  b->last_args = args;
+  b->last_plan = P;
   if (use_graph && repeat) {
     if (b->exec) {
       (void)hipGraphExecDestroy(b->exec);
@@ -542,9 +525,9 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-      k_reset_queue<<<1, 64, 0, cs>>>(args.queue);
-      hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.block), lay.lds, cs, args);
+      const hipError_t el = enqueue(c, b, P, fn, grid, cfg.block, lay.lds, cs);
       e = hipStreamEndCapture(cs, &graph);
+      if (el != hipSuccess) e = el;
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
     if (graph) (void)hipGraphDestroy(graph);
@@ -555,19 +538,144 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
     b->exec_block = cfg.block;
     b->exec_grid = grid;
     b->exec_lds = lay.lds;
-    b->exec_args = args;
+    b->exec_plan = P;
     return ctx_hip(c, hipGraphLaunch(b->exec, s), "batched graph launch");
   }
-  k_reset_queue<<<1, 64, 0, s>>>(args.queue);
-  hipLaunchKernelGGL(fn, dim3(grid), dim3(cfg.block), lay.lds, s, args);
-  return ctx_hip(c, hipGetLastError(), "batched kernel");
+  return ctx_hip(c, enqueue(c, b, P, fn, grid, cfg.block, lay.lds, s), "batched kernel");
 }
 
-// Builds the plan for one configuration; returns the kernel arguments.
+// Splits the hub queries (longest first) into chunks whose staging fits a
+// memory budget, and fills the device buffers and per-chunk arguments.
+static int plan_hubs(panther_ctx* c, BatchState* b, const std::vector<std::pair<uint64_t, int32_t>>& C,
+                     const int32_t* dq, int32_t k, int32_t* d_ids, uint32_t* d_counts,
+                     int32_t* d_len, float* theta, hipStream_t s, std::vector<HubArgs>* out) {
+  out->clear();
+  b->h_hq.clear();
+  if (C.empty()) return PANTHER_OK;
+  const uint64_t T = (uint64_t)c->T;
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  // staging bytes per occurrence slot: row order, bucket order
+  const size_t budget = std::min((size_t)8 << 30, free_b / 4);
+  uint64_t occ_limit = std::max<uint64_t>(budget / 8, T * C.front().first);
+  occ_limit = std::min<uint64_t>(occ_limit, (uint64_t)1 << 31);
+  if (T * C.front().first > occ_limit)
+    return ctx_fail(c, PANTHER_ERANGE, "a hub query's path list exceeds the staging limit");
+  struct Chunk {
+    size_t first, nq;
+    uint32_t tiles, stiles, bkts;
+    uint64_t occ, cand;
+  };
+  std::vector<Chunk> chunks;
+  Chunk cur{0, 0, 0, 0, 0, 0, 0};
+  size_t max_bkt = 0, max_nq = 0, max_tiles = 0, max_stiles = 0;
+  uint64_t max_occ = 0, max_cand = 0;
+  auto close = [&]() {
+    if (!cur.nq) return;
+    chunks.push_back(cur);
+    max_bkt = std::max<size_t>(max_bkt, cur.bkts);
+    max_nq = std::max<size_t>(max_nq, cur.nq);
+    max_tiles = std::max<size_t>(max_tiles, cur.tiles);
+    max_stiles = std::max<size_t>(max_stiles, cur.stiles);
+    max_occ = std::max(max_occ, cur.occ);
+    max_cand = std::max(max_cand, cur.cand);
+    cur = Chunk{b->h_hq.size(), 0, 0, 0, 0, 0, 0};
+  };
+  for (const auto& x : C) {
+    const uint64_t L = x.first;
+    const uint64_t occ = T * L;
+    const int bb = std::min(hub_bucket_bits(occ), b->hub_bits_max);
+    const uint32_t tiles = hub_tiles(L);
+    const uint32_t stiles = hub_stiles(L);
+    const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(k, kEmitCap) << bb, occ);
+    if (cur.nq && (cur.occ + occ > occ_limit || (uint64_t)cur.tiles + tiles > 0x7FFFFFFFu ||
+                   (uint64_t)cur.nq + 1 > 0x7FFFFFFFu ||
+                   (uint64_t)cur.bkts + (1u << bb) > 0x7FFFFFFFu))
+      close();
+    HubQuery h{};
+    h.qi = x.second;
+    h.bb = bb;
+    h.tile0 = cur.tiles;
+    h.stile0 = cur.stiles;
+    h.bkt0 = cur.bkts;
+    h.occ0 = cur.occ;
+    h.cand0 = cur.cand;
+    b->h_hq.push_back(h);
+    cur.nq += 1;
+    cur.tiles += tiles;
+    cur.stiles += stiles;
+    cur.bkts += 1u << bb;
+    cur.occ += occ;
+    cur.cand += cand;
+  }
+  close();
+  int st;
+  if ((st = grow(c, b->d_hq, b->hq_cap, b->h_hq.size(), sizeof(HubQuery), "hub plan"))) return st;
+  if ((st = grow(c, b->d_stA, b->occ_cap, max_occ, sizeof(int32_t), "hub staging"))) return st;
+  if ((st = grow(c, b->d_stB, b->occB_cap, max_occ, sizeof(int32_t), "hub staging"))) return st;
+  if ((st = grow(c, b->d_bkt_cnt, b->bkt_cap, max_bkt, sizeof(uint32_t), "hub buckets"))) return st;
+  if ((st = grow(c, b->d_bkt_fill, b->bkt_fill_cap, max_bkt, sizeof(uint32_t), "hub buckets")))
+    return st;
+  if ((st = grow(c, b->d_bkt_start, b->bkt_start_cap, max_bkt + 1, sizeof(uint64_t),
+                 "hub buckets")))
+    return st;
+  if ((st = grow(c, b->d_cand, b->cand_cap, max_cand, sizeof(uint64_t), "hub winners"))) return st;
+  if ((st = grow(c, b->d_cand_n, b->cand_n_cap, max_nq, sizeof(uint32_t), "hub winners")))
+    return st;
+  if ((st = grow(c, b->d_scan, b->scan_cap, scan_temp_bytes((int64_t)max_bkt), 1, "hub scan")))
+    return st;
+  if ((st = grow(c, b->d_hx, b->hx_cap, max_nq, sizeof(HubList), "hub lists"))) return st;
+  if ((st = grow(c, b->d_tile_owner, b->tile_owner_cap, max_tiles, sizeof(int32_t), "hub maps")))
+    return st;
+  if ((st = grow(c, b->d_stile_owner, b->stile_owner_cap, max_stiles, sizeof(int32_t),
+                 "hub maps")))
+    return st;
+  if ((st = grow(c, b->d_bkt_owner, b->bkt_owner_cap, max_bkt, sizeof(int32_t), "hub maps")))
+    return st;
+  st = ctx_hip(c, hipMemcpyAsync(b->d_hq, b->h_hq.data(), sizeof(HubQuery) * b->h_hq.size(),
+                                 hipMemcpyHostToDevice, s),
+               "hub plan upload");
+  if (st) return st;
+  for (const Chunk& ch : chunks) {
+    HubArgs h{};
+    h.queries = dq;
+    h.inv_ptr = c->d_inv_ptr;
+    h.inv_pid = c->d_inv_pid;
+    h.paths = c->d_paths;
+    h.hq = b->d_hq + ch.first;
+    h.hx = b->d_hx;
+    h.tile_owner = b->d_tile_owner;
+    h.stile_owner = b->d_stile_owner;
+    h.bkt_owner = b->d_bkt_owner;
+    h.nq = (int32_t)ch.nq;
+    h.T = c->T;
+    h.k = k;
+    h.n_tiles = ch.tiles;
+    h.n_stiles = ch.stiles;
+    h.n_bkt = ch.bkts;
+    h.stA = b->d_stA;
+    h.stB = b->d_stB;
+    h.bkt_cnt = b->d_bkt_cnt;
+    h.bkt_start = b->d_bkt_start;
+    h.bkt_fill = b->d_bkt_fill;
+    h.cand = b->d_cand;
+    h.cand_n = b->d_cand_n;
+    h.out_ids = d_ids;
+    h.out_counts = d_counts;
+    h.out_len = d_len;
+    h.theta = theta;
+    h.fR = (float)c->R;
+    out->push_back(h);
+  }
+  return PANTHER_OK;
+}
+
+// Builds the plan for one configuration.  With `with_hubs` false the hub
+// queries are left out (the autotuner times the persistent kernel alone).
 static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int32_t* dq,
                 const std::vector<uint64_t>& qlen, int64_t nq, int32_t k, int32_t* d_ids,
-                uint32_t* d_counts, int32_t* d_len, float* theta, hipStream_t s, BatchArgs* out,
-                std::vector<int32_t>* host_items) {
+                uint32_t* d_counts, int32_t* d_len, float* theta, hipStream_t s, bool with_hubs,
+                Plan* out, std::vector<int32_t>* host_items) {
   const Layout lay = layout_for(c, cfg);
   const uint64_t T = (uint64_t)c->T;
   uint64_t LA = (uint64_t)lay.TA / (2 * T);
@@ -604,62 +712,43 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
       pos[c2] = run;
       run += cnt[c2];
     }
-    std::vector<std::pair<uint64_t, int32_t>> out(v.size());
-    for (auto& x : v) out[pos[cls(x.first)]++] = x;
-    v.swap(out);
+    std::vector<std::pair<uint64_t, int32_t>> o(v.size());
+    for (auto& x : v) o[pos[cls(x.first)]++] = x;
+    v.swap(o);
   };
   by_class(B);
   by_class(A);
+  if (!with_hubs) C.clear();
+  int st = plan_hubs(c, b, C, dq, k, d_ids, d_counts, d_len, theta, s, &out->hub);
+  if (st) return st;
   host_items->clear();
-  for (auto& x : C) host_items->push_back(x.second);
   for (auto& x : B) host_items->push_back(x.second);
   for (auto& x : A) host_items->push_back(x.second);
-  if (!C.empty()) {
-    // dense slots: one per hub-capable work-group, within a memory budget
-    const int grid = c->num_cus * cfg.wgs_per_cu;
-    size_t free_b = 0, total_b = 0;
-    (void)hipMemGetInfo(&free_b, &total_b);
-    const size_t per = 8 * (size_t)c->n;
-    size_t budget = std::min((size_t)16 << 30, free_b / 4);
-    int want = (int)std::min<size_t>((size_t)grid, std::max<size_t>(1, budget / per));
-    want = std::min<int>(want, (int)C.size());
-    int st = ensure_slots(c, b, want);
-    if (st) return st;
-  }
   const size_t need = host_items->size();
-  if (b->items_cap < need) {
-    ctx_free(b->d_items);
-    b->d_items = nullptr;
-    b->items_cap = 0;
-    void* p;
-    int st = ctx_alloc(c, &p, sizeof(int32_t) * std::max<size_t>(need, 1024), "batch plan");
-    if (st) return st;
-    b->d_items = static_cast<int32_t*>(p);
-    b->items_cap = std::max<size_t>(need, 1024);
-  }
+  if ((st = grow(c, b->d_items, b->items_cap, std::max<size_t>(need, 1024), sizeof(int32_t),
+                 "batch plan")))
+    return st;
   if (!b->d_queue) {
     void* p;
-    int st = ctx_alloc(c, &p, 64, "batch queue");
+    st = ctx_alloc(c, &p, 64, "batch queue");
     if (st) return st;
     b->d_queue = static_cast<uint32_t*>(p);
   }
-  int st = ctx_hip(c, hipMemcpyAsync(b->d_items, host_items->data(), sizeof(int32_t) * need,
-                                     hipMemcpyHostToDevice, s),
-                   "batch plan upload");
-  if (st) return st;
+  if (need) {
+    st = ctx_hip(c, hipMemcpyAsync(b->d_items, host_items->data(), sizeof(int32_t) * need,
+                                   hipMemcpyHostToDevice, s),
+                 "batch plan upload");
+    if (st) return st;
+  }
   BatchArgs a{};
   a.queries = dq;
-  a.itemsC = b->d_items;
-  a.itemsB = b->d_items + C.size();
-  a.itemsA = b->d_items + C.size() + B.size();
-  a.nC = (int32_t)C.size();
+  a.itemsB = b->d_items;
+  a.itemsA = b->d_items + B.size();
   a.nB = (int32_t)B.size();
   a.nA = (int32_t)A.size();
   a.inv_ptr = c->d_inv_ptr;
   a.inv_pid = c->d_inv_pid;
   a.paths = c->d_paths;
-  a.slot_cnt = b->d_slot_cnt;
-  a.slot_touched = b->d_slot_touched;
   a.queue = b->d_queue;
   a.n = c->n;
   a.k = k;
@@ -670,7 +759,8 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   a.out_len = d_len;
   a.theta = theta;
   a.fR = (float)c->R;
-  *out = a;
+  out->args = a;
+  out->run_kernel = need > 0;
   return PANTHER_OK;
 }
 
@@ -679,7 +769,7 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector
                 float* theta, hipStream_t s) {
   BatchState* b = state(lane);
   std::vector<int32_t> items;
-  BatchArgs args;
+  Plan args;
   // configuration: forced, cached, autotuned, or the default
   std::vector<BatchConfig> cands;
   for (int blk : {512, 256})
@@ -719,7 +809,8 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector
       float best = 1e30f;
       BatchConfig best_cfg = cands[0];
       for (const BatchConfig& cfg : cands) {
-        st = plan(c, b, cfg, dq, qlen, m, k, d_ids, d_counts, d_len, theta, s, &args, &items);
+        st = plan(c, b, cfg, dq, qlen, m, k, d_ids, d_counts, d_len, theta, s, false, &args,
+                  &items);
         if (st) break;
         st = launch_batched(c, b, cfg, args, s, false);  // warm
         if (st) break;
@@ -746,7 +837,8 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector
       b->tuned = true;
     }
   }
-  int st = plan(c, b, b->cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, theta, s, &args, &items);
+  int st = plan(c, b, b->cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, theta, s, true, &args,
+                &items);
   if (st) return st;
   st = launch_batched(c, b, b->cfg, args, s, true);
   if (st) return st;

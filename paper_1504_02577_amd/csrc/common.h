@@ -207,15 +207,16 @@ __device__ __forceinline__ uint32_t key_count(uint64_t key) { return (uint32_t)(
 // ---------------------------------------------------------------------------
 // Block-wide selection of the k largest of n distinct non-zero 64-bit keys,
 // produced on demand by key(i), i in [0, n).  Small sets are sorted whole in
-// LDS.  Larger sets are narrowed by 12-bit radix histograms (most significant
+// LDS.  Larger sets are narrowed by 11-bit radix histograms (most significant
 // digit first) until the class straddling the k-th key fits in LDS; the keys
 // above that class are certainly selected.  The result (min(k, n) keys,
-// descending) is left in s_out.  LDS: s_cand[kCand], s_hist[4096 + 2],
+// descending) is left in s_out.  LDS: s_cand[kCand], s_hist[kHist],
 // s_out[kOutCap], s_misc[8].
 // ---------------------------------------------------------------------------
 constexpr int kCand = 2048;
 constexpr int kOutCap = 1024;
-constexpr int kHist = 4096;
+constexpr int kHistBits = 11;
+constexpr int kHist = 1 << kHistBits;
 
 struct SelectSmem {
   uint64_t cand[kCand];
@@ -250,7 +251,7 @@ __device__ int block_select_topk(KeyFn key, int n, int k, SelectSmem& sm) {
   int need = k;
   uint32_t cls = (uint32_t)n;
   while (shift > 0) {
-    const int dbits = shift < 12 ? shift : 12;
+    const int dbits = shift < kHistBits ? shift : kHistBits;
     const int nsh = shift - dbits;
     const uint32_t nb = 1u << dbits;
     for (int i = tid; i < (int)nb; i += BLOCK) sm.hist[i] = 0;
@@ -261,16 +262,31 @@ __device__ int block_select_topk(KeyFn key, int n, int k, SelectSmem& sm) {
         atomicAdd(&sm.hist[(uint32_t)(x >> nsh) & (nb - 1)], 1u);
     }
     __syncthreads();
-    if (tid == 0) {
-      uint32_t above = 0;
-      int d = (int)nb - 1;
-      for (; d > 0; --d) {
-        if (above + sm.hist[d] >= (uint32_t)need) break;
-        above += sm.hist[d];
+    // the digit d holding the need-th largest key: fewer than `need` keys
+    // of the class lie in digits above d, at least `need` in d and above.
+    // Each thread takes a run of digits in descending order; a block scan
+    // gives the count above its run, and the one thread whose run holds the
+    // crossing records it (the class holds >= need keys, so it exists)
+    {
+      const int per = ((int)nb + BLOCK - 1) / BLOCK;
+      uint64_t loc = 0;
+      for (int i = 0; i < per; ++i) {
+        const int pos = tid * per + i;
+        if (pos < (int)nb) loc += sm.hist[nb - 1 - pos];
       }
-      sm.misc[0] = (uint32_t)d;
-      sm.misc[1] = above;
-      sm.misc[2] = sm.hist[d];
+      uint64_t tot;
+      uint64_t above = block_exclusive_sum<BLOCK>(loc, sm.red, &tot);
+      for (int i = 0; i < per; ++i) {
+        const int pos = tid * per + i;
+        if (pos >= (int)nb) break;
+        const uint32_t h = sm.hist[nb - 1 - pos];
+        if (above < (uint64_t)need && above + h >= (uint64_t)need) {
+          sm.misc[0] = nb - 1 - pos;
+          sm.misc[1] = (uint32_t)above;
+          sm.misc[2] = h;
+        }
+        above += h;
+      }
     }
     __syncthreads();
     const uint32_t d = sm.misc[0];

@@ -1,0 +1,74 @@
+// Hub queries of the batched top-k: the split, on-chip counting pipeline
+// (gather, bucket scatter, per-bucket LDS count and selection, merge).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace panther {
+
+// Occurrences a bucket is sized for (the LDS table holds twice as many).
+constexpr int kBucketTarget = 2048;
+// A bucket emits at most max(k, kEmitCap) candidates to the merge.
+constexpr int kEmitCap = 256;
+
+// One hub query of a chunk; offsets are relative to the chunk's buffers and
+// ascend with the query's position in the chunk.
+struct HubQuery {
+  int32_t qi;       // index of the query in the batch
+  int32_t bb;       // log2 of its bucket count
+  uint32_t tile0;   // first gather tile
+  uint32_t stile0;  // first bucketing tile
+  uint32_t bkt0;    // first bucket
+  uint32_t pad;
+  uint64_t occ0;    // first staging slot (T slots per row of P_q)
+  uint64_t cand0;   // first slot of its per-bucket winners
+};
+
+// Filled on the device from the query id: P_q = inv_pid[a, a + L).
+struct HubList {
+  uint64_t a;
+  uint64_t L;
+  int32_t q;
+  int32_t pad;
+};
+
+struct HubArgs {
+  const int32_t* queries;
+  const uint64_t* inv_ptr;
+  const uint32_t* inv_pid;
+  const int32_t* paths;
+  const HubQuery* hq;  // [nq]
+  HubList* hx;         // [nq]
+  int32_t* tile_owner;   // [n_tiles] gather tile -> query of the chunk
+  int32_t* stile_owner;  // [n_stiles] bucketing tile -> query
+  int32_t* bkt_owner;    // [n_bkt] bucket -> query
+  int32_t nq;
+  int32_t T;
+  int32_t k;
+  uint32_t n_tiles;
+  uint32_t n_stiles;
+  uint32_t n_bkt;
+  int32_t* stA;          // staging in row order
+  int32_t* stB;          // staging in bucket order
+  uint32_t* bkt_cnt;     // [n_bkt]
+  uint64_t* bkt_start;   // [n_bkt + 1]
+  uint32_t* bkt_fill;    // [n_bkt]
+  uint64_t* cand;        // per-bucket winners, grouped by query
+  uint32_t* cand_n;      // [nq]
+  int32_t* out_ids;
+  uint32_t* out_counts;
+  int32_t* out_len;
+  float* theta;          // feature mode: row qi gets count / R
+  float fR;
+};
+
+int hub_bucket_bits(uint64_t occ);
+uint32_t hub_tiles(uint64_t L);
+uint32_t hub_stiles(uint64_t L);
+size_t hub_count_lds();
+hipError_t enqueue_hub_chunk(const HubArgs& A, int stride, void* scan_temp, hipStream_t s);
+hipError_t hub_set_attributes();
+
+}  // namespace panther

@@ -1,0 +1,459 @@
+// Panther query, hub queries of the batched form (Alg. 1 counting and the
+// top-k of Problem 1 for queries with long path lists), split across many
+// work-groups with every count kept on chip.
+//
+// A query q whose list P_q is too long for one work-group's LDS table goes
+// through four steps, each a grid-wide launch over all hub queries of a
+// chunk:
+//   gather   rows of P_q -> their distinct vertices != q, T slots per row
+//            (-1 where a row has fewer), in a staging array;
+//   bucket   each staged vertex's bucket is counted (bucket = top bits of a
+//            bijective hash of the id, 2^bb buckets for query q, bb chosen
+//            so that a bucket holds about kBucketTarget occurrences), the
+//            counts are scanned, and the vertices are moved into bucket
+//            order;
+//   count    one work-group per bucket counts its vertices in an LDS hash
+//            table and selects the bucket's k best (count desc, id asc);
+//   merge    one work-group per query selects the k best of the per-bucket
+//            winners.
+// Buckets partition the candidates of q, so the k best overall are among
+// the per-bucket k best, and the result is exactly that of one dense count
+// of q.  A bucket whose distinct vertices overflow the LDS table is redone
+// in sub-ranges of the hash (the next bits below the bucket bits), doubling
+// the split until it fits; a sub-range of at most half the table's size in
+// hash space holds at most that many distinct vertices, so the doubling
+// ends.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/panther.h"
+#include "common.h"
+#include "runtime.h"
+#include "kernels.h"
+#include "hub.h"
+
+using namespace panther;
+
+namespace {
+
+constexpr int kGatherBlock = 256;
+constexpr int kGatherRows = 4;                        // rows per thread
+constexpr int kTileRows = kGatherBlock * kGatherRows;  // rows per gather tile
+constexpr int kSTileRows = 4096;                      // rows per bucketing tile
+constexpr int kMaxBucketBits = 12;
+constexpr int kCountBlock = 512;
+constexpr int kTable = 2 * kBucketTarget;  // LDS hash entries of the count step
+constexpr int kTableBits = 12;
+constexpr int kProbes = 32;                // bounded probe sequence
+constexpr int kFitBits = kTableBits - 1;   // log2(kTable / 2)
+static_assert(kTable == 1 << kTableBits, "table size");
+
+__device__ __forceinline__ uint32_t vhash(int32_t v) { return (uint32_t)v * 0x9E3779B1u; }
+
+__device__ __forceinline__ uint32_t bucket_of(int32_t v, int bb) {
+  return bb == 0 ? 0u : vhash(v) >> (32 - bb);
+}
+
+// Per query of the chunk: its list bounds, the owner maps of its tiles and
+// buckets, and zeroed bucket counters.
+__global__ void __launch_bounds__(256) k_hub_prep(HubArgs A) {
+  const int j = blockIdx.x;
+  const HubQuery Q = A.hq[j];
+  const bool last = j + 1 == A.nq;
+  const uint32_t t1 = last ? A.n_tiles : A.hq[j + 1].tile0;
+  const uint32_t s1 = last ? A.n_stiles : A.hq[j + 1].stile0;
+  const uint32_t nb = 1u << Q.bb;
+  if (threadIdx.x == 0) {
+    const int32_t q = A.queries[Q.qi];
+    const uint64_t a = A.inv_ptr[q];
+    A.hx[j] = HubList{a, A.inv_ptr[q + 1] - a, q, 0};
+    A.cand_n[j] = 0u;
+  }
+  for (uint32_t t = Q.tile0 + threadIdx.x; t < t1; t += 256) A.tile_owner[t] = j;
+  for (uint32_t t = Q.stile0 + threadIdx.x; t < s1; t += 256) A.stile_owner[t] = j;
+  for (uint32_t b = threadIdx.x; b < nb; b += 256) {
+    A.bkt_owner[Q.bkt0 + b] = j;
+    A.bkt_cnt[Q.bkt0 + b] = 0u;
+    A.bkt_fill[Q.bkt0 + b] = 0u;
+  }
+}
+
+template <int S>
+__global__ void __launch_bounds__(kGatherBlock) k_hub_gather(HubArgs A) {
+  const uint32_t tile = blockIdx.x;
+  const int j = A.tile_owner[tile];
+  const HubQuery Q = A.hq[j];
+  const HubList X = A.hx[j];
+  const int32_t q = X.q;
+  const uint64_t a = X.a;
+  const uint64_t L = X.L;
+  const int T = A.T;
+  const uint64_t r0 = (uint64_t)(tile - Q.tile0) * kTileRows;
+  // rows are held in registers RG at a time (fewer for long rows)
+  constexpr int RG = S <= 16 ? kGatherRows : 1;
+#pragma unroll 1
+  for (int g0 = 0; g0 < kGatherRows; g0 += RG) {
+    uint32_t pid[RG];
+    bool ok[RG];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+      const uint64_t r = r0 + (uint64_t)(g0 + i) * kGatherBlock + threadIdx.x;
+      ok[i] = r < L;
+      pid[i] = ok[i] ? A.inv_pid[a + r] : 0u;
+    }
+    int32_t v[RG][S];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+      if (ok[i]) {
+        load_row<S>(A.paths, (uint64_t)pid[i], v[i]);
+      } else {
+#pragma unroll
+        for (int jj = 0; jj < S; ++jj) v[i][jj] = -1;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+      if (!ok[i]) continue;
+      dedup_row<S>(v[i]);
+      const uint64_t r = r0 + (uint64_t)(g0 + i) * kGatherBlock + threadIdx.x;
+      int32_t* dst = A.stA + Q.occ0 + r * (uint64_t)T;
+      int c = 0;
+#pragma unroll
+      for (int jj = 0; jj < S; ++jj) {
+        const int32_t x = v[i][jj];
+        if (x >= 0 && x != q && c < T) dst[c++] = x;
+      }
+      for (int jj = c; jj < T; ++jj) dst[jj] = -1;
+    }
+  }
+}
+
+// Bucket counts of one bucketing tile (kSTileRows rows of one query).
+__global__ void __launch_bounds__(kGatherBlock) k_hub_hist(HubArgs A) {
+  __shared__ uint32_t hist[1 << kMaxBucketBits];
+  const uint32_t tile = blockIdx.x;
+  const int j = A.stile_owner[tile];
+  const HubQuery Q = A.hq[j];
+  const uint64_t L = A.hx[j].L;
+  const int nb = 1 << Q.bb;
+  const uint64_t r0 = (uint64_t)(tile - Q.stile0) * kSTileRows;
+  const uint64_t rows = L - r0 < (uint64_t)kSTileRows ? L - r0 : (uint64_t)kSTileRows;
+  const uint64_t m = rows * (uint64_t)A.T;
+  const int32_t* src = A.stA + Q.occ0 + r0 * (uint64_t)A.T;
+  for (int b = threadIdx.x; b < nb; b += kGatherBlock) hist[b] = 0u;
+  __syncthreads();
+  for (uint64_t i = threadIdx.x; i < m; i += kGatherBlock) {
+    const int32_t x = src[i];
+    if (x >= 0) atomicAdd(&hist[bucket_of(x, Q.bb)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
+    const uint32_t h = hist[b];
+    if (h) atomicAdd(&A.bkt_cnt[Q.bkt0 + b], h);
+  }
+}
+
+__global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
+  __shared__ uint32_t hist[1 << kMaxBucketBits];
+  __shared__ uint32_t base[1 << kMaxBucketBits];
+  const uint32_t tile = blockIdx.x;
+  const int j = A.stile_owner[tile];
+  const HubQuery Q = A.hq[j];
+  const uint64_t L = A.hx[j].L;
+  const int nb = 1 << Q.bb;
+  const uint64_t r0 = (uint64_t)(tile - Q.stile0) * kSTileRows;
+  const uint64_t rows = L - r0 < (uint64_t)kSTileRows ? L - r0 : (uint64_t)kSTileRows;
+  const uint64_t m = rows * (uint64_t)A.T;
+  const int32_t* src = A.stA + Q.occ0 + r0 * (uint64_t)A.T;
+  for (int b = threadIdx.x; b < nb; b += kGatherBlock) hist[b] = 0u;
+  __syncthreads();
+  for (uint64_t i = threadIdx.x; i < m; i += kGatherBlock) {
+    const int32_t x = src[i];
+    if (x >= 0) atomicAdd(&hist[bucket_of(x, Q.bb)], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
+    const uint32_t h = hist[b];
+    base[b] = h ? (uint32_t)A.bkt_start[Q.bkt0 + b] + atomicAdd(&A.bkt_fill[Q.bkt0 + b], h) : 0u;
+    hist[b] = 0u;
+  }
+  __syncthreads();
+  for (uint64_t i = threadIdx.x; i < m; i += kGatherBlock) {
+    const int32_t x = src[i];
+    if (x >= 0) {
+      const uint32_t b = bucket_of(x, Q.bb);
+      A.stB[base[b] + atomicAdd(&hist[b], 1u)] = x;
+    }
+  }
+}
+
+// Table slot: top bits of a second multiplicative hash, so that the ids of
+// one bucket (equal top bits of vhash) still spread over the whole table.
+__device__ __forceinline__ uint32_t slot_of(int32_t v) {
+  return ((uint32_t)v * 0xCC9E2D51u) >> (32 - kTableBits);
+}
+
+// Counts v in the LDS table; false when `probes` slots found no room.
+__device__ __forceinline__ bool table_add(int32_t* keys, uint32_t* vals, int32_t v, int probes) {
+  uint32_t h = slot_of(v);
+#pragma unroll 1
+  for (int p = 0; p < probes; ++p) {
+    const int32_t cur = *((volatile int32_t*)&keys[h]);
+    if (cur == v) {
+      atomicAdd(&vals[h], 1u);
+      return true;
+    }
+    if (cur == -1) {
+      const int32_t prev = atomicCAS(&keys[h], -1, v);
+      if (prev == -1 || prev == v) {
+        atomicAdd(&vals[h], 1u);
+        return true;
+      }
+    }
+    h = (h + 1) & (uint32_t)(kTable - 1);
+  }
+  return false;
+}
+
+struct CountSmem {
+  int32_t keys[kTable];
+  uint32_t vals[kTable];  // the two arrays are reused as kTable 64-bit keys
+  SelectSmem sel;
+  uint64_t run[kOutCap];  // running best of the sub-ranges (split buckets)
+  uint32_t ctl[8];
+};
+
+// Counts the vertices of stB[s, e) whose hash bits below the bucket bits
+// equal `sub` (all of them when sbits == 0) in the LDS table.  Returns false
+// when the table overflowed.  At the finest split (bb + sbits == 32 -
+// kFitBits) at most kTable / 2 distinct ids qualify and the probe sequence
+// is unbounded, so it never fails there.
+__device__ bool count_part(const HubArgs& A, CountSmem& sm, uint64_t s, uint64_t e, int bb,
+                           int sbits, uint32_t sub) {
+  const int probes = bb + sbits >= 32 - kFitBits ? kTable : kProbes;
+  for (int j = threadIdx.x; j < kTable; j += kCountBlock) {
+    sm.keys[j] = -1;
+    sm.vals[j] = 0u;
+  }
+  if (threadIdx.x == 0) {
+    sm.ctl[0] = 0u;
+    sm.ctl[1] = 0u;
+  }
+  __syncthreads();
+  bool fail = false;
+  for (uint64_t i = s + threadIdx.x; i < e; i += kCountBlock) {
+    const int32_t x = A.stB[i];
+    if (sbits > 0 && ((vhash(x) << bb) >> (32 - sbits)) != sub) continue;
+    if (!table_add(sm.keys, sm.vals, x, probes)) fail = true;
+  }
+  if (fail) sm.ctl[1] = 1u;
+  __syncthreads();
+  const bool overflow = sm.ctl[1] != 0u;
+  __syncthreads();
+  return !overflow;
+}
+
+// Exact selection of the k best entries of the table into sel.out (sorted);
+// returns how many.
+__device__ int select_exact(const HubArgs& A, CountSmem& sm) {
+  // compact the occupied slots into ranking keys over the table's storage
+  constexpr int kPer = kTable / kCountBlock;
+  int32_t kk[kPer];
+  uint32_t vv[kPer];
+  int nv = 0;
+#pragma unroll
+  for (int t = 0; t < kPer; ++t) {
+    kk[t] = sm.keys[threadIdx.x + t * kCountBlock];
+    vv[t] = sm.vals[threadIdx.x + t * kCountBlock];
+    nv += kk[t] >= 0 ? 1 : 0;
+  }
+  if (threadIdx.x == 0) sm.ctl[0] = 0u;
+  __syncthreads();
+  const uint32_t p0 = nv ? atomicAdd(&sm.ctl[0], (uint32_t)nv) : 0u;
+  __syncthreads();
+  uint64_t* comp = reinterpret_cast<uint64_t*>(sm.keys);
+  uint32_t p = p0;
+#pragma unroll
+  for (int t = 0; t < kPer; ++t)
+    if (kk[t] >= 0) comp[p++] = rank_key(vv[t], kk[t]);
+  __syncthreads();
+  const int nc = (int)sm.ctl[0];
+  auto keyfn = [&](int i) { return comp[i]; };
+  return block_select_topk<kCountBlock>(keyfn, nc, A.k, sm.sel);
+}
+
+// Emits, unsorted, every entry of the table whose count reaches the count
+// of the k-th best entry (all entries when there are fewer than k): a
+// superset of the bucket's k best, since the ranking puts larger counts
+// first.  Returns false, emitting nothing, when that set exceeds
+// max(k, kEmitCap) entries.
+__device__ bool emit_by_count(const HubArgs& A, CountSmem& sm, int j, const HubQuery& Q) {
+  constexpr int kBins = 256;  // counts clamped to 255
+  uint32_t* ch = sm.sel.hist;
+  for (int b = threadIdx.x; b < kBins; b += kCountBlock) ch[b] = 0u;
+  if (threadIdx.x == 0) {
+    sm.ctl[2] = 1u;  // threshold count (when there are fewer than k entries)
+    sm.ctl[3] = 0u;  // entries at or above it
+    sm.ctl[4] = 0u;  // emit cursor
+  }
+  __syncthreads();
+  uint32_t total_local = 0;
+  for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
+    if (sm.keys[t] >= 0) {
+      const uint32_t c = sm.vals[t];
+      atomicAdd(&ch[c < kBins - 1 ? c : kBins - 1], 1u);
+      ++total_local;
+    }
+  }
+  __syncthreads();
+  // descending bins, one per thread: the count above a bin by a block scan
+  const int bin = kBins - 1 - (int)threadIdx.x;
+  const uint64_t h = bin >= 0 ? (uint64_t)ch[bin] : 0ull;
+  uint64_t tot;
+  const uint64_t above = block_exclusive_sum<kCountBlock>(h, sm.sel.red, &tot);
+  const uint64_t k = (uint64_t)A.k;
+  if (bin >= 1 && above < k && above + h >= k) {
+    sm.ctl[2] = (uint32_t)bin;
+    sm.ctl[3] = (uint32_t)(above + h);
+  }
+  __syncthreads();
+  const uint32_t thr = sm.ctl[2];
+  const uint32_t n_emit = tot < k ? (uint32_t)tot : sm.ctl[3];
+  const uint32_t cap = (uint32_t)(A.k > kEmitCap ? A.k : kEmitCap);
+  if (n_emit > cap) return false;  // uniform: every thread read the same words
+  __shared__ uint32_t s_pos;
+  if (threadIdx.x == 0) s_pos = n_emit ? atomicAdd(&A.cand_n[j], n_emit) : 0u;
+  __syncthreads();
+  uint64_t* dst = A.cand + Q.cand0 + s_pos;
+  for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
+    const int32_t key = sm.keys[t];
+    if (key >= 0) {
+      const uint32_t c = sm.vals[t];
+      if ((c < kBins - 1 ? c : kBins - 1) >= thr) dst[atomicAdd(&sm.ctl[4], 1u)] = rank_key(c, key);
+    }
+  }
+  (void)total_local;
+  return true;
+}
+
+__global__ void __launch_bounds__(kCountBlock, 2) k_hub_count(HubArgs A) {
+  extern __shared__ __align__(16) char lds[];
+  CountSmem& sm = *reinterpret_cast<CountSmem*>(lds);
+  const uint32_t g = blockIdx.x;
+  const int j = A.bkt_owner[g];
+  const HubQuery Q = A.hq[j];
+  const uint64_t s = A.bkt_start[g];
+  const uint64_t e = A.bkt_start[g + 1];
+  int m;
+  const uint64_t* best = sm.sel.out;
+  if (count_part(A, sm, s, e, Q.bb, 0, 0u)) {
+    if (emit_by_count(A, sm, j, Q)) return;
+    m = select_exact(A, sm);
+  } else {
+    // split by the next hash bits until every part fits
+    m = 0;
+    for (int sbits = 1; sbits <= 32 - kFitBits - Q.bb; ++sbits) {
+      int r = 0;  // keys in sm.run
+      bool ok = true;
+      for (uint32_t sub = 0; sub < (1u << sbits); ++sub) {
+        if (!count_part(A, sm, s, e, Q.bb, sbits, sub)) {
+          ok = false;
+          break;
+        }
+        const int mm = select_exact(A, sm);
+        // merge sel.out[0..mm) into run[0..r): both descending, keep k
+        uint64_t* buf = sm.sel.cand;
+        const int tot = r + mm;
+        const int P = next_pow2(tot < 2 ? 2 : tot);
+        for (int i = threadIdx.x; i < P; i += kCountBlock)
+          buf[i] = i < r ? sm.run[i] : (i < tot ? sm.sel.out[i - r] : 0ull);
+        __syncthreads();
+        block_bitonic_desc<kCountBlock>(buf, P);
+        r = tot < A.k ? tot : A.k;
+        for (int i = threadIdx.x; i < r; i += kCountBlock) sm.run[i] = buf[i];
+        __syncthreads();
+      }
+      if (ok) {
+        m = r;
+        best = sm.run;
+        break;
+      }
+    }
+  }
+  // the finest split holds at most kTable / 2 distinct ids, so m is set
+  __shared__ uint32_t s_pos;
+  if (threadIdx.x == 0) s_pos = m > 0 ? atomicAdd(&A.cand_n[j], (uint32_t)m) : 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += kCountBlock) A.cand[Q.cand0 + s_pos + i] = best[i];
+}
+
+__global__ void __launch_bounds__(kCountBlock) k_hub_merge(HubArgs A) {
+  extern __shared__ __align__(16) char lds[];
+  SelectSmem& sm = *reinterpret_cast<SelectSmem*>(lds);
+  const int j = blockIdx.x;
+  const HubQuery Q = A.hq[j];
+  const int n = (int)A.cand_n[j];
+  const uint64_t* c = A.cand + Q.cand0;
+  auto keyfn = [&](int i) { return c[i]; };
+  const int m = block_select_topk<kCountBlock>(keyfn, n, A.k, sm);
+  const int k = A.k;
+  const int64_t row = (int64_t)Q.qi * k;
+  if (A.theta) {
+    for (int i = threadIdx.x; i < k; i += kCountBlock)
+      A.theta[row + i] = i < m ? (float)key_count(sm.out[i]) / A.fR : 0.0f;
+    return;
+  }
+  for (int i = threadIdx.x; i < k; i += kCountBlock) {
+    const bool ok = i < m;
+    A.out_ids[row + i] = ok ? key_vertex(sm.out[i]) : -1;
+    A.out_counts[row + i] = ok ? key_count(sm.out[i]) : 0u;
+  }
+  if (threadIdx.x == 0) A.out_len[Q.qi] = m;
+}
+
+}  // namespace
+
+namespace panther {
+
+int hub_bucket_bits(uint64_t occ) {
+  int bb = 0;
+  while (bb < kMaxBucketBits && ((uint64_t)kBucketTarget << bb) < occ) ++bb;
+  return bb;
+}
+
+uint32_t hub_tiles(uint64_t L) { return (uint32_t)((L + kTileRows - 1) / kTileRows); }
+uint32_t hub_stiles(uint64_t L) { return (uint32_t)((L + kSTileRows - 1) / kSTileRows); }
+
+size_t hub_count_lds() { return sizeof(CountSmem); }
+
+// Enqueues the four steps for one chunk.  Buffers in `A` must hold the
+// chunk's totals; nothing here allocates or synchronises.
+hipError_t enqueue_hub_chunk(const HubArgs& A, int stride, void* scan_temp, hipStream_t s) {
+  if (A.nq == 0) return hipSuccess;
+  k_hub_prep<<<(uint32_t)A.nq, 256, 0, s>>>(A);
+  switch (stride) {
+    case 4: k_hub_gather<4><<<A.n_tiles, kGatherBlock, 0, s>>>(A); break;
+    case 8: k_hub_gather<8><<<A.n_tiles, kGatherBlock, 0, s>>>(A); break;
+    case 16: k_hub_gather<16><<<A.n_tiles, kGatherBlock, 0, s>>>(A); break;
+    case 32: k_hub_gather<32><<<A.n_tiles, kGatherBlock, 0, s>>>(A); break;
+    default: k_hub_gather<64><<<A.n_tiles, kGatherBlock, 0, s>>>(A); break;
+  }
+  k_hub_hist<<<A.n_stiles, kGatherBlock, 0, s>>>(A);
+  launch_scan_u32_to_u64(A.bkt_cnt, A.bkt_start, A.n_bkt, scan_temp, s);
+  k_hub_scatter<<<A.n_stiles, kGatherBlock, 0, s>>>(A);
+  k_hub_count<<<A.n_bkt, kCountBlock, sizeof(CountSmem), s>>>(A);
+  k_hub_merge<<<(uint32_t)A.nq, kCountBlock, sizeof(SelectSmem), s>>>(A);
+  return hipGetLastError();
+}
+
+hipError_t hub_set_attributes() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_hub_count,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)sizeof(CountSmem));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_hub_merge, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)sizeof(SelectSmem));
+}
+
+}  // namespace panther

@@ -266,7 +266,7 @@ extern "C" int panther_set_option(panther_ctx* c, const char* key, int64_t value
   } else if (k == "test.fail_alloc_after") {
     c->fail_alloc_after = value < 0 ? -1 : value;
   } else if (k == "batch.tier_a" || k == "batch.tier_b" || k == "batch.block" ||
-             k == "batch.wgs_per_cu") {
+             k == "batch.wgs_per_cu" || k == "batch.hub_bits") {
     return set_batch_option(c, k, value);
   } else {
     return ctx_fail(c, PANTHER_EINVAL, "unknown option '%s'", key);

@@ -208,15 +208,17 @@ def test_errors_leave_context_usable(P, oracle, inputs, ba_state):
     fresh.close()
 
 
-@pytest.mark.parametrize("block,wgs,ta,tb", [
-    (512, 1, -1, -1), (256, 1, -1, -1), (512, 2, -1, -1), (256, 2, -1, -1),
-    (512, 1, 0, 0),     # every non-empty list goes to the dense hub tier
-    (256, 1, 4, 0),     # wave tier + hub tier
-    (512, 2, 1, 60),    # all three tiers, small tables
+@pytest.mark.parametrize("block,wgs,ta,tb,hb", [
+    (512, 1, -1, -1, -1), (256, 1, -1, -1, -1), (512, 2, -1, -1, -1), (256, 2, -1, -1, -1),
+    (512, 1, 0, 0, -1),     # every non-empty list goes to the split hub pipeline
+    (256, 1, 4, 0, -1),     # wave tier + hub pipeline
+    (512, 2, 1, 60, -1),    # all three tiers, small tables
+    (512, 1, 0, 0, 0),      # one bucket per hub: large ones overflow the LDS table
+    (512, 1, -1, 60, 1),    # two buckets per hub, overflow and sub-range splits
 ])
-def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb):
+def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb, hb):
     g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
-    _say(f"case: batched tiers block={block} wgs={wgs} ta={ta} tb={tb}")
+    _say(f"case: batched tiers block={block} wgs={wgs} ta={ta} tb={tb} hub_bits={hb}")
     P.load_graph(g)
     P.sample_paths(T, R, seed)
     P.set_option("topk.form", 1)
@@ -224,15 +226,16 @@ def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb):
     P.set_option("batch.wgs_per_cu", wgs)
     P.set_option("batch.tier_a", ta)
     P.set_option("batch.tier_b", tb)
+    P.set_option("batch.hub_bits", hb)
     try:
         qs = np.concatenate([inputs.queries_by_degree(g, 1500, 11),
                              np.arange(0, g.n, 97, dtype=np.int32)])
         for k in (1, 50, 300):
             want = oracle.topk(g.n, paths, inv_ptr, inv_pid, qs, k)
-            _check_topk(P.topk(qs, k), want, f"tiers {block}/{wgs}/{ta}/{tb} k={k}")
+            _check_topk(P.topk(qs, k), want, f"tiers {block}/{wgs}/{ta}/{tb}/{hb} k={k}")
     finally:
         for key, v in (("batch.block", 0), ("batch.wgs_per_cu", 0), ("batch.tier_a", -1),
-                       ("batch.tier_b", -1)):
+                       ("batch.tier_b", -1), ("batch.hub_bits", -1)):
             P.set_option(key, v)
 
 
