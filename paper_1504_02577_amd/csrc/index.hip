@@ -64,18 +64,38 @@ k_radix_up_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shi
   for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
 }
 
-// Ranks and scatters a tile held in registers (thread t holds items
-// j * 256 + t), using `chunk` (64 x 256 uint16 in LDS) for the histograms.
+// LDS of a down-sweep: the tile's pairs (pass 1 stages them here), then the
+// chunk histograms, then the tile reordered by digit.
+struct RankSmem {
+  union {
+    uint16_t chunk[kChunks][kRadix];
+    struct {
+      uint32_t key[kTileItems];
+      uint32_t val[kTileItems];
+    } tile;
+  } u;
+  uint32_t lstart[kRadix];  // first position of digit d in the reordered tile
+  uint64_t gbase[kRadix];   // global position of that item
+  uint32_t scan[kBlock / kWave + 1];
+};
+static_assert(kBlock == kRadix, "one digit per thread in the digit scans");
+
+// Ranks a tile held in registers (thread t holds items j * 256 + t) stably
+// by digit, reorders it by digit in LDS, and writes each digit's run from
+// offset[digit][tile] on, consecutive threads on consecutive addresses.
 __device__ __forceinline__ void rank_scatter_regs(const uint32_t (&k)[16], const uint32_t (&v)[16],
-                                                  int n, int shift, int bits,
-                                                  uint16_t (*chunk)[kRadix],
+                                                  int n, int shift, int bits, RankSmem& sm,
                                                   const uint64_t* __restrict__ offsets,
                                                   uint64_t ntiles, uint64_t tile,
                                                   uint32_t* __restrict__ key_out,
                                                   uint32_t* __restrict__ val_out) {
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint16_t (*chunk)[kRadix] = sm.u.chunk;
   uint32_t rk[16];
-  for (int i = threadIdx.x; i < kChunks * kRadix; i += kBlock) (&chunk[0][0])[i] = 0;
+  {
+    uint32_t* z = reinterpret_cast<uint32_t*>(&chunk[0][0]);
+    for (int i = threadIdx.x; i < kChunks * kRadix / 2; i += kBlock) z[i] = 0u;
+  }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
@@ -94,45 +114,60 @@ __device__ __forceinline__ void rank_scatter_regs(const uint32_t (&k)[16], const
     if (live && below == 0) chunk[c][d] = (uint16_t)__popcll(same);
   }
   __syncthreads();
+  // digit d = thread d: chunk prefix (rank base of each chunk inside the
+  // tile), then the digit starts of the reordered tile by a block scan
   const int nchunks = (n + kWave - 1) / kWave;
-  for (int d = threadIdx.x; d < kRadix; d += kBlock) {
-    uint32_t run = 0;
+  {
+    const int d = threadIdx.x;
+    uint32_t dtot = 0;
+#pragma unroll 8
     for (int c = 0; c < nchunks; ++c) {
       const uint32_t x = chunk[c][d];
-      chunk[c][d] = (uint16_t)run;
-      run += x;
+      chunk[c][d] = (uint16_t)dtot;
+      dtot += x;
     }
+    uint32_t ttot;
+    const uint32_t ls = block_exclusive_sum<kBlock>(dtot, sm.scan, &ttot);
+    sm.lstart[d] = ls;
+    sm.gbase[d] = offsets[(uint64_t)d * ntiles + tile] - ls;
   }
   __syncthreads();
+  uint32_t lp[16];
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int i = j * kBlock + threadIdx.x;
+    lp[j] = 0u;
     if (i < n) {
       const uint32_t d = digit_of(k[j], shift, bits);
       const int c = j * (kBlock / kWave) + wid;
-      const uint64_t pos = offsets[(uint64_t)d * ntiles + tile] + chunk[c][d] + rk[j];
-      if (key_out) key_out[pos] = k[j];
-      val_out[pos] = v[j];
+      lp[j] = sm.lstart[d] + chunk[c][d] + rk[j];
     }
   }
+  __syncthreads();  // the chunk table is dead from here; its LDS holds the tile
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (j * kBlock + (int)threadIdx.x < n) {
+      sm.u.tile.key[lp[j]] = k[j];
+      sm.u.tile.val[lp[j]] = v[j];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const uint32_t key = sm.u.tile.key[i];
+    const uint64_t pos = sm.gbase[digit_of(key, shift, bits)] + (uint64_t)i;
+    if (key_out) key_out[pos] = key;
+    val_out[pos] = sm.u.tile.val[i];
+  }
 }
-
-struct StageSmem {
-  uint32_t key[kTileItems];
-  uint32_t val[kTileItems];
-  uint32_t scan[kBlock / kWave + 1];
-};
 
 template <int S>
 __global__ void __launch_bounds__(kBlock)
 k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shift, int bits,
                    uint64_t ntiles, const uint64_t* __restrict__ offsets,
                    uint32_t* __restrict__ key_out, uint32_t* __restrict__ val_out) {
-  // 32 KB of LDS: first the compacted (vertex, path id) pairs in path-id
-  // order, then -- once they are in registers -- the chunk histograms
-  __shared__ __align__(16) unsigned char raw[sizeof(StageSmem)];
-  StageSmem& st = *reinterpret_cast<StageSmem*>(raw);
-  uint16_t (*chunk)[kRadix] = reinterpret_cast<uint16_t (*)[kRadix]>(raw);
+  // the compacted (vertex, path id) pairs are staged in path-id order in
+  // the tile region, then moved to registers
+  __shared__ RankSmem sm;
   int base = 0;
   const uint64_t p0 = (uint64_t)blockIdx.x * ppt;
   for (int r0 = 0; r0 < ppt; r0 += kBlock) {
@@ -150,13 +185,13 @@ k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int s
 #pragma unroll
     for (int i = 0; i < S; ++i) cnt += v[i] >= 0 ? 1u : 0u;
     uint32_t tot;
-    uint32_t off = block_exclusive_sum<kBlock>(cnt, st.scan, &tot);
+    uint32_t off = block_exclusive_sum<kBlock>(cnt, sm.scan, &tot);
     uint32_t o = (uint32_t)base + off;
 #pragma unroll
     for (int i = 0; i < S; ++i)
       if (v[i] >= 0) {
-        st.key[o] = (uint32_t)v[i];
-        st.val[o] = (uint32_t)pid;
+        sm.u.tile.key[o] = (uint32_t)v[i];
+        sm.u.tile.val[o] = (uint32_t)pid;
         ++o;
       }
     base += (int)tot;
@@ -167,11 +202,11 @@ k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int s
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int i = j * kBlock + threadIdx.x;
-    k[j] = i < n ? st.key[i] : 0u;
-    vv[j] = i < n ? st.val[i] : 0u;
+    k[j] = i < n ? sm.u.tile.key[i] : 0u;
+    vv[j] = i < n ? sm.u.tile.val[i] : 0u;
   }
   __syncthreads();
-  rank_scatter_regs(k, vv, n, shift, bits, chunk, offsets, ntiles, blockIdx.x, key_out, val_out);
+  rank_scatter_regs(k, vv, n, shift, bits, sm, offsets, ntiles, blockIdx.x, key_out, val_out);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -193,7 +228,7 @@ k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict
                    uint64_t nnz, int shift, int bits, uint64_t ntiles,
                    const uint64_t* __restrict__ offsets, uint32_t* __restrict__ key_out,
                    uint32_t* __restrict__ val_out) {
-  __shared__ uint16_t chunk[kChunks][kRadix];
+  __shared__ RankSmem sm;
   const uint64_t a = (uint64_t)blockIdx.x * kTileItems;
   const int n = (int)((nnz - a) < (uint64_t)kTileItems ? (nnz - a) : (uint64_t)kTileItems);
   uint32_t k[16], v[16];
@@ -203,7 +238,7 @@ k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict
     k[j] = i < n ? keys[a + i] : 0u;
     v[j] = i < n ? vals[a + i] : 0u;
   }
-  rank_scatter_regs(k, v, n, shift, bits, chunk, offsets, ntiles, blockIdx.x, key_out, val_out);
+  rank_scatter_regs(k, v, n, shift, bits, sm, offsets, ntiles, blockIdx.x, key_out, val_out);
 }
 
 // inv_ptr from the sorted vertex keys: position i opens the lists of every
