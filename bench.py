@@ -93,8 +93,8 @@ def main():
                     help="paths in the oracle sample (0 = the full R of the workload)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: multi-GPU sharding is designed, not built "
-              "(see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only: multi-GPU sharding is designed, not built; "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
