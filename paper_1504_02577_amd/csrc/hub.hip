@@ -55,6 +55,18 @@ __device__ __forceinline__ uint32_t bucket_of(int32_t v, int bb) {
   return bb == 0 ? 0u : vhash(v) >> (32 - bb);
 }
 
+// kUnroll staged slots per thread, loaded before any is used (-1 past m):
+// the loads of a batch overlap instead of each waiting on the one before.
+constexpr int kUnroll = 8;
+__device__ __forceinline__ void load_batch(const int32_t* __restrict__ src, uint64_t m, uint64_t i0,
+                                           int32_t (&x)[kUnroll]) {
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const uint64_t i = i0 + (uint64_t)u * kGatherBlock + threadIdx.x;
+    x[u] = i < m ? src[i] : -1;
+  }
+}
+
 // Per query of the chunk: its list bounds, the owner maps of its tiles and
 // buckets, and zeroed bucket counters.
 __global__ void __launch_bounds__(256) k_hub_prep(HubArgs A) {
@@ -143,9 +155,12 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_hist(HubArgs A) {
   const int32_t* src = A.stA + Q.occ0 + r0 * (uint64_t)A.T;
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) hist[b] = 0u;
   __syncthreads();
-  for (uint64_t i = threadIdx.x; i < m; i += kGatherBlock) {
-    const int32_t x = src[i];
-    if (x >= 0) atomicAdd(&hist[bucket_of(x, Q.bb)], 1u);
+  for (uint64_t i0 = 0; i0 < m; i0 += kUnroll * kGatherBlock) {
+    int32_t x[kUnroll];
+    load_batch(src, m, i0, x);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.bb)], 1u);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
@@ -168,9 +183,12 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
   const int32_t* src = A.stA + Q.occ0 + r0 * (uint64_t)A.T;
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) hist[b] = 0u;
   __syncthreads();
-  for (uint64_t i = threadIdx.x; i < m; i += kGatherBlock) {
-    const int32_t x = src[i];
-    if (x >= 0) atomicAdd(&hist[bucket_of(x, Q.bb)], 1u);
+  for (uint64_t i0 = 0; i0 < m; i0 += kUnroll * kGatherBlock) {
+    int32_t x[kUnroll];
+    load_batch(src, m, i0, x);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.bb)], 1u);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
@@ -179,12 +197,15 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
     hist[b] = 0u;
   }
   __syncthreads();
-  for (uint64_t i = threadIdx.x; i < m; i += kGatherBlock) {
-    const int32_t x = src[i];
-    if (x >= 0) {
-      const uint32_t b = bucket_of(x, Q.bb);
-      A.stB[base[b] + atomicAdd(&hist[b], 1u)] = x;
-    }
+  for (uint64_t i0 = 0; i0 < m; i0 += kUnroll * kGatherBlock) {
+    int32_t x[kUnroll];
+    load_batch(src, m, i0, x);
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (x[u] >= 0) {
+        const uint32_t b = bucket_of(x[u], Q.bb);
+        A.stB[base[b] + atomicAdd(&hist[b], 1u)] = x[u];
+      }
   }
 }
 
@@ -242,10 +263,19 @@ __device__ bool count_part(const HubArgs& A, CountSmem& sm, uint64_t s, uint64_t
   }
   __syncthreads();
   bool fail = false;
-  for (uint64_t i = s + threadIdx.x; i < e; i += kCountBlock) {
-    const int32_t x = A.stB[i];
-    if (sbits > 0 && ((vhash(x) << bb) >> (32 - sbits)) != sub) continue;
-    if (!table_add(sm.keys, sm.vals, x, probes)) fail = true;
+  for (uint64_t i0 = s; i0 < e; i0 += kUnroll * kCountBlock) {
+    int32_t x[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint64_t i = i0 + (uint64_t)u * kCountBlock + threadIdx.x;
+      x[u] = i < e ? A.stB[i] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (x[u] < 0) continue;
+      if (sbits > 0 && ((vhash(x[u]) << bb) >> (32 - sbits)) != sub) continue;
+      if (!table_add(sm.keys, sm.vals, x[u], probes)) fail = true;
+    }
   }
   if (fail) sm.ctl[1] = 1u;
   __syncthreads();

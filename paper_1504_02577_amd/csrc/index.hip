@@ -50,15 +50,28 @@ k_radix_up_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shi
   for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
   __syncthreads();
   const uint64_t p0 = (uint64_t)blockIdx.x * ppt;
-  for (int r = threadIdx.x; r < ppt; r += kBlock) {
-    const uint64_t pid = p0 + r;
-    if (pid >= R) break;
-    int32_t v[S];
-    load_row<S>(paths, pid, v);
-    dedup_row<S>(v);
+  // RG rows in flight per thread before their digits are counted
+  constexpr int RG = S <= 8 ? 4 : (S <= 16 ? 2 : 1);
+  for (int r0 = 0; r0 < ppt; r0 += RG * kBlock) {
+    int32_t v[RG][S];
 #pragma unroll
-    for (int i = 0; i < S; ++i)
-      if (v[i] >= 0) atomicAdd(&s_hist[digit_of((uint32_t)v[i], shift, bits)], 1u);
+    for (int g = 0; g < RG; ++g) {
+      const int r = r0 + g * kBlock + (int)threadIdx.x;
+      const uint64_t pid = p0 + r;
+      if (r < ppt && pid < R) {
+        load_row<S>(paths, pid, v[g]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < S; ++i) v[g][i] = -1;
+      }
+    }
+#pragma unroll
+    for (int g = 0; g < RG; ++g) {
+      dedup_row<S>(v[g]);
+#pragma unroll
+      for (int i = 0; i < S; ++i)
+        if (v[g][i] >= 0) atomicAdd(&s_hist[digit_of((uint32_t)v[g][i], shift, bits)], 1u);
+    }
   }
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
@@ -155,7 +168,7 @@ __device__ __forceinline__ void rank_scatter_regs(const uint32_t (&k)[16], const
   for (int i = threadIdx.x; i < n; i += kBlock) {
     const uint32_t key = sm.u.tile.key[i];
     const uint64_t pos = sm.gbase[digit_of(key, shift, bits)] + (uint64_t)i;
-    if (key_out) key_out[pos] = key;
+    key_out[pos] = key;
     val_out[pos] = sm.u.tile.val[i];
   }
 }
@@ -168,34 +181,44 @@ k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int s
   // the compacted (vertex, path id) pairs are staged in path-id order in
   // the tile region, then moved to registers
   __shared__ RankSmem sm;
-  int base = 0;
   const uint64_t p0 = (uint64_t)blockIdx.x * ppt;
-  for (int r0 = 0; r0 < ppt; r0 += kBlock) {
-    const uint64_t pid = p0 + r0 + threadIdx.x;
-    int32_t v[S];
-    const bool live = (r0 + (int)threadIdx.x < ppt) && pid < R;
-    if (live) {
-      load_row<S>(paths, pid, v);
-      dedup_row<S>(v);
+  // thread t takes rows [t * rpt, t * rpt + rpt) of the tile, all loaded
+  // before any is used; one block scan orders the pairs by path id
+  constexpr int RMAX = S <= 32 ? 32 / S : 1;
+  const int rpt = (ppt + kBlock - 1) / kBlock;  // <= RMAX for every T with this S
+  int32_t v[RMAX][S];
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int g = 0; g < RMAX; ++g) {
+    const int r = (int)threadIdx.x * rpt + g;
+    const uint64_t pid = p0 + r;
+    if (g < rpt && r < ppt && pid < R) {
+      load_row<S>(paths, pid, v[g]);
     } else {
 #pragma unroll
-      for (int i = 0; i < S; ++i) v[i] = -1;
+      for (int i = 0; i < S; ++i) v[g][i] = -1;
     }
-    uint32_t cnt = 0;
+  }
 #pragma unroll
-    for (int i = 0; i < S; ++i) cnt += v[i] >= 0 ? 1u : 0u;
-    uint32_t tot;
-    uint32_t off = block_exclusive_sum<kBlock>(cnt, sm.scan, &tot);
-    uint32_t o = (uint32_t)base + off;
+  for (int g = 0; g < RMAX; ++g) {
+    dedup_row<S>(v[g]);
+#pragma unroll
+    for (int i = 0; i < S; ++i) cnt += v[g][i] >= 0 ? 1u : 0u;
+  }
+  uint32_t tot;
+  uint32_t o = block_exclusive_sum<kBlock>(cnt, sm.scan, &tot);
+#pragma unroll
+  for (int g = 0; g < RMAX; ++g) {
+    const uint32_t pid = (uint32_t)(p0 + (uint64_t)((int)threadIdx.x * rpt + g));
 #pragma unroll
     for (int i = 0; i < S; ++i)
-      if (v[i] >= 0) {
-        sm.u.tile.key[o] = (uint32_t)v[i];
-        sm.u.tile.val[o] = (uint32_t)pid;
+      if (v[g][i] >= 0) {
+        sm.u.tile.key[o] = (uint32_t)v[g][i];
+        sm.u.tile.val[o] = pid;
         ++o;
       }
-    base += (int)tot;
   }
+  const int base = (int)tot;
   __syncthreads();
   const int n = base;
   uint32_t k[16], vv[16];
@@ -210,14 +233,23 @@ k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int s
 }
 
 __global__ void __launch_bounds__(kBlock)
-k_radix_up_pairs(const uint32_t* __restrict__ keys, uint64_t nnz, int shift, int bits,
-                 uint64_t ntiles, uint32_t* __restrict__ hist) {
+k_radix_up_pairs(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ nnz_dev,
+                 int shift, int bits, uint64_t ntiles, uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_hist[kRadix];
   for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
   __syncthreads();
+  const uint64_t nnz = *nnz_dev;  // tiles past it count nothing
   const uint64_t a = (uint64_t)blockIdx.x * kTileItems;
-  for (uint64_t i = a + threadIdx.x; i < a + kTileItems && i < nnz; i += kBlock)
-    atomicAdd(&s_hist[digit_of(keys[i], shift, bits)], 1u);
+  // all 16 keys of the thread are loaded before any is counted
+  uint32_t k[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint64_t i = a + (uint64_t)j * kBlock + threadIdx.x;
+    k[j] = i < nnz ? keys[i] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (int j = 0; j < 16; ++j)
+    if (k[j] != 0xFFFFFFFFu) atomicAdd(&s_hist[digit_of(k[j], shift, bits)], 1u);
   __syncthreads();
   for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
 }
@@ -225,11 +257,13 @@ k_radix_up_pairs(const uint32_t* __restrict__ keys, uint64_t nnz, int shift, int
 // Passes >= 2: the tile of 4096 consecutive pairs goes straight to registers.
 __global__ void __launch_bounds__(kBlock)
 k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                   uint64_t nnz, int shift, int bits, uint64_t ntiles,
+                   const uint64_t* __restrict__ nnz_dev, int shift, int bits, uint64_t ntiles,
                    const uint64_t* __restrict__ offsets, uint32_t* __restrict__ key_out,
                    uint32_t* __restrict__ val_out) {
   __shared__ RankSmem sm;
+  const uint64_t nnz = *nnz_dev;
   const uint64_t a = (uint64_t)blockIdx.x * kTileItems;
+  if (a >= nnz) return;  // a tile past the pairs: nothing to move
   const int n = (int)((nnz - a) < (uint64_t)kTileItems ? (nnz - a) : (uint64_t)kTileItems);
   uint32_t k[16], v[16];
 #pragma unroll
@@ -241,16 +275,38 @@ k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict
   rank_scatter_regs(k, v, n, shift, bits, sm, offsets, ntiles, blockIdx.x, key_out, val_out);
 }
 
+__global__ void k_copy_u64(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst) {
+  if (threadIdx.x == 0) *dst = *src;
+}
+
 // inv_ptr from the sorted vertex keys: position i opens the lists of every
-// vertex in (key[i-1], key[i]].
+// vertex in (key[i-1], key[i]], and nnz those after the last key.  Thread t
+// takes keys [4t, 4t + 4) with one 16-byte load.
 __global__ void __launch_bounds__(kBlock)
-k_list_bounds(const uint32_t* __restrict__ keys, uint64_t nnz, int32_t n,
+k_list_bounds(const uint32_t* __restrict__ keys, const uint64_t* __restrict__ nnz_dev, int32_t n,
               uint64_t* __restrict__ inv_ptr) {
-  const uint64_t gsz = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i <= nnz; i += gsz) {
-    const int64_t kp = i == 0 ? -1 : (int64_t)keys[i - 1];
-    const int64_t kc = i == nnz ? (int64_t)n : (int64_t)keys[i];
+  const uint64_t nnz = *nnz_dev;
+  const uint64_t i0 = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 4;
+  if (i0 > nnz) return;
+  uint32_t k[4];
+  if (i0 + 4 <= nnz) {
+    const uint4 x = *reinterpret_cast<const uint4*>(keys + i0);
+    k[0] = x.x;
+    k[1] = x.y;
+    k[2] = x.z;
+    k[3] = x.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = i0 + j < nnz ? keys[i0 + j] : (uint32_t)n;
+  }
+  int64_t kp = i0 == 0 ? -1 : (int64_t)keys[i0 - 1];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint64_t i = i0 + j;
+    if (i > nnz) break;
+    const int64_t kc = i == nnz ? (int64_t)n : (int64_t)k[j];
     for (int64_t v = kp + 1; v <= kc; ++v) inv_ptr[v] = i;
+    kp = kc;
   }
 }
 
@@ -297,25 +353,28 @@ void launch_radix_down_paths(int stride, const int32_t* paths, uint64_t R, int T
 #undef PANTHER_DOWN
 }
 
-void launch_radix_up_pairs(const uint32_t* keys, uint64_t nnz, int shift, int bits,
-                           uint32_t* hist, hipStream_t s) {
-  const uint64_t nt = radix_tiles_pairs(nnz);
-  k_radix_up_pairs<<<(unsigned)nt, kBlock, 0, s>>>(keys, nnz, shift, bits, nt, hist);
+void launch_radix_up_pairs(const uint32_t* keys, const uint64_t* nnz_dev, uint64_t nnz_cap,
+                           int shift, int bits, uint32_t* hist, hipStream_t s) {
+  const uint64_t nt = radix_tiles_pairs(nnz_cap);
+  k_radix_up_pairs<<<(unsigned)nt, kBlock, 0, s>>>(keys, nnz_dev, shift, bits, nt, hist);
 }
 
-void launch_radix_down_pairs(const uint32_t* keys, const uint32_t* vals, uint64_t nnz, int shift,
-                             int bits, const uint64_t* offsets, uint32_t* key_out,
-                             uint32_t* val_out, hipStream_t s) {
-  const uint64_t nt = radix_tiles_pairs(nnz);
-  k_radix_down_pairs<<<(unsigned)nt, kBlock, 0, s>>>(keys, vals, nnz, shift, bits, nt, offsets,
+void launch_radix_down_pairs(const uint32_t* keys, const uint32_t* vals, const uint64_t* nnz_dev,
+                             uint64_t nnz_cap, int shift, int bits, const uint64_t* offsets,
+                             uint32_t* key_out, uint32_t* val_out, hipStream_t s) {
+  const uint64_t nt = radix_tiles_pairs(nnz_cap);
+  k_radix_down_pairs<<<(unsigned)nt, kBlock, 0, s>>>(keys, vals, nnz_dev, shift, bits, nt, offsets,
                                                       key_out, val_out);
 }
 
-void launch_list_bounds(const uint32_t* keys, uint64_t nnz, int32_t n, uint64_t* inv_ptr,
-                        hipStream_t s) {
-  uint64_t g = (nnz + 1 + kBlock - 1) / kBlock;
-  if (g > 65536) g = 65536;
-  k_list_bounds<<<(unsigned)g, kBlock, 0, s>>>(keys, nnz, n, inv_ptr);
+void launch_copy_u64(const uint64_t* src, uint64_t* dst, hipStream_t s) {
+  k_copy_u64<<<1, 64, 0, s>>>(src, dst);
+}
+
+void launch_list_bounds(const uint32_t* keys, const uint64_t* nnz_dev, uint64_t nnz_cap, int32_t n,
+                        uint64_t* inv_ptr, hipStream_t s) {
+  const uint64_t g = (nnz_cap / 4 + 1 + kBlock - 1) / kBlock;
+  k_list_bounds<<<(unsigned)g, kBlock, 0, s>>>(keys, nnz_dev, n, inv_ptr);
 }
 
 }  // namespace panther

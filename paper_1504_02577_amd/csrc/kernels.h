@@ -77,13 +77,16 @@ void launch_radix_up_paths(int stride, const int32_t* paths, uint64_t R, int T, 
 void launch_radix_down_paths(int stride, const int32_t* paths, uint64_t R, int T, int shift,
                              int bits, const uint64_t* offsets, uint32_t* key_out,
                              uint32_t* val_out, hipStream_t s);
-void launch_radix_up_pairs(const uint32_t* keys, uint64_t nnz, int shift, int bits,
-                           uint32_t* hist, hipStream_t s);
-void launch_radix_down_pairs(const uint32_t* keys, const uint32_t* vals, uint64_t nnz, int shift,
-                             int bits, const uint64_t* offsets, uint32_t* key_out,
-                             uint32_t* val_out, hipStream_t s);
-void launch_list_bounds(const uint32_t* keys, uint64_t nnz, int32_t n, uint64_t* inv_ptr,
-                        hipStream_t s);
+// pair passes: the pair count is read on the device (nnz_dev); grids are
+// sized for nnz_cap >= nnz
+void launch_radix_up_pairs(const uint32_t* keys, const uint64_t* nnz_dev, uint64_t nnz_cap,
+                           int shift, int bits, uint32_t* hist, hipStream_t s);
+void launch_radix_down_pairs(const uint32_t* keys, const uint32_t* vals, const uint64_t* nnz_dev,
+                             uint64_t nnz_cap, int shift, int bits, const uint64_t* offsets,
+                             uint32_t* key_out, uint32_t* val_out, hipStream_t s);
+void launch_copy_u64(const uint64_t* src, uint64_t* dst, hipStream_t s);
+void launch_list_bounds(const uint32_t* keys, const uint64_t* nnz_dev, uint64_t nnz_cap, int32_t n,
+                        uint64_t* inv_ptr, hipStream_t s);
 
 // ---- count + top-k, plain form: one launch per query ----
 struct TopkScratch {

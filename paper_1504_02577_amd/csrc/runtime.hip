@@ -106,7 +106,7 @@ static void free_paths(panther_ctx* c, bool release) {
   if (release) {
     free_lane(&c->lane0);
     for (DevBuf* b : {&c->b_paths, &c->b_inv_pid, &c->b_inv_ptr, &c->b_keys0, &c->b_keys1,
-                      &c->b_vtmp, &c->b_hist, &c->b_offs, &c->b_stemp, &c->b_queries,
+                      &c->b_vtmp, &c->b_hist, &c->b_offs, &c->b_stemp, &c->b_nnz, &c->b_queries,
                       &c->b_outs})
       ctx_release(*b);
     ctx_free(c->d_cnt);
@@ -451,29 +451,24 @@ static int build_index(panther_ctx* c) {
   const int passes = (bits_total + kRadixPassBits - 1) / kRadixPassBits;
   const int pass_bits = (bits_total + passes - 1) / passes;
   const uint64_t tiles1 = radix_tiles_paths(R, c->T);
+  // buffers are sized for the pair count's bound R (T+1), so the passes
+  // never wait for the host to learn the count
   const uint64_t nnz_cap = R * (uint64_t)(c->T + 1);
-  const uint64_t hist_cap = 256 * std::max<uint64_t>(tiles1, radix_tiles_pairs(nnz_cap));
+  const uint64_t tiles = radix_tiles_pairs(nnz_cap);
+  const uint64_t hist_cap = 256 * std::max<uint64_t>(tiles1, tiles);
   TRY(ctx_ensure(c, c->b_hist, sizeof(uint32_t) * hist_cap, "radix histograms"));
   TRY(ctx_ensure(c, c->b_offs, sizeof(uint64_t) * (hist_cap + 1), "radix offsets"));
   TRY(ctx_ensure(c, c->b_stemp, scan_temp_bytes((int64_t)hist_cap), "scan temp"));
+  TRY(ctx_ensure(c, c->b_nnz, 64, "pair count"));
+  TRY(ctx_ensure(c, c->b_inv_pid, sizeof(uint32_t) * nnz_cap, "index path ids"));
+  TRY(ctx_ensure(c, c->b_inv_ptr, sizeof(uint64_t) * (size_t)(n + 1), "index offsets"));
+  TRY(ctx_ensure(c, c->b_keys0, sizeof(uint32_t) * nnz_cap, "radix keys"));
+  if (passes > 1) TRY(ctx_ensure(c, c->b_keys1, sizeof(uint32_t) * nnz_cap, "radix keys"));
+  if (passes > 1) TRY(ctx_ensure(c, c->b_vtmp, sizeof(uint32_t) * nnz_cap, "radix values"));
   uint32_t* hist = static_cast<uint32_t*>(c->b_hist.p);
   uint64_t* offs = static_cast<uint64_t*>(c->b_offs.p);
+  uint64_t* d_nnz = static_cast<uint64_t*>(c->b_nnz.p);
   void* stemp = c->b_stemp.p;
-  // pass 1: histograms straight from the path rows
-  int shift = 0;
-  int bits = std::min(pass_bits, bits_total - shift);
-  launch_radix_up_paths(c->stride, c->d_paths, R, c->T, shift, bits, hist, s);
-  launch_scan_u32_to_u64(hist, offs, (int64_t)(256 * tiles1), stemp, s);
-  HIPTRY(hipGetLastError(), "index pass 1");
-  uint64_t nnz = 0;
-  HIPTRY(hipMemcpyAsync(&nnz, offs + 256 * tiles1, 8, hipMemcpyDeviceToHost, s), "index");
-  HIPTRY(hipStreamSynchronize(s), "index");
-  c->nnz = (int64_t)nnz;
-  TRY(ctx_ensure(c, c->b_inv_pid, sizeof(uint32_t) * nnz, "index path ids"));
-  TRY(ctx_ensure(c, c->b_inv_ptr, sizeof(uint64_t) * (size_t)(n + 1), "index offsets"));
-  TRY(ctx_ensure(c, c->b_keys0, sizeof(uint32_t) * nnz, "radix keys"));
-  TRY(ctx_ensure(c, c->b_keys1, sizeof(uint32_t) * nnz, "radix keys"));
-  if (passes > 1) TRY(ctx_ensure(c, c->b_vtmp, sizeof(uint32_t) * nnz, "radix values"));
   c->d_inv_pid = static_cast<uint32_t*>(c->b_inv_pid.p);
   c->d_inv_ptr = static_cast<uint64_t*>(c->b_inv_ptr.p);
   uint32_t* keys[2] = {static_cast<uint32_t*>(c->b_keys0.p),
@@ -482,22 +477,28 @@ static int build_index(panther_ctx* c) {
   // pass p writes its values to inv_pid when (passes - p) is even, so the
   // last pass lands in inv_pid
   auto vals_of = [&](int pass) { return ((passes - pass) % 2 == 0) ? c->d_inv_pid : vtmp; };
-  launch_radix_down_paths(c->stride, c->d_paths, R, c->T, shift, bits, offs, keys[0],
-                          vals_of(1), s);
+  // pass 1: histograms straight from the path rows; the scan's total is
+  // the pair count
+  int shift = 0;
+  int bits = std::min(pass_bits, bits_total - shift);
+  launch_radix_up_paths(c->stride, c->d_paths, R, c->T, shift, bits, hist, s);
+  launch_scan_u32_to_u64(hist, offs, (int64_t)(256 * tiles1), stemp, s);
+  launch_copy_u64(offs + 256 * tiles1, d_nnz, s);
+  launch_radix_down_paths(c->stride, c->d_paths, R, c->T, shift, bits, offs, keys[0], vals_of(1),
+                          s);
   HIPTRY(hipGetLastError(), "index pass 1");
-  const uint64_t tiles = radix_tiles_pairs(nnz);
   for (int pass = 2; pass <= passes; ++pass) {
     shift += bits;
     bits = std::min(pass_bits, bits_total - shift);
     const uint32_t* kin = keys[(pass - 2) % 2];
     uint32_t* kout = keys[(pass - 1) % 2];
-    launch_radix_up_pairs(kin, nnz, shift, bits, hist, s);
+    launch_radix_up_pairs(kin, d_nnz, nnz_cap, shift, bits, hist, s);
     launch_scan_u32_to_u64(hist, offs, (int64_t)(256 * tiles), stemp, s);
-    launch_radix_down_pairs(kin, vals_of(pass - 1), nnz, shift, bits, offs, kout, vals_of(pass),
-                            s);
+    launch_radix_down_pairs(kin, vals_of(pass - 1), d_nnz, nnz_cap, shift, bits, offs, kout,
+                            vals_of(pass), s);
     HIPTRY(hipGetLastError(), "index pass");
   }
-  launch_list_bounds(keys[(passes - 1) % 2], nnz, n, c->d_inv_ptr, s);
+  launch_list_bounds(keys[(passes - 1) % 2], d_nnz, nnz_cap, n, c->d_inv_ptr, s);
   HIPTRY(hipGetLastError(), "index bounds");
   return PANTHER_OK;
 }
@@ -533,6 +534,13 @@ extern "C" int panther_sample_paths(panther_ctx* c, int32_t T, int64_t R, uint64
     stage_begin(c, 1, c->stream);
     st = build_index(c);
     stage_end(c, 1, c->stream);
+  }
+  if (!st) {
+    uint64_t nnz = 0;
+    st = ctx_hip(c, hipMemcpyAsync(&nnz, c->b_nnz.p, 8, hipMemcpyDeviceToHost, c->stream),
+                 "pair count");
+    if (!st) st = ctx_hip(c, hipStreamSynchronize(c->stream), "pair count");
+    c->nnz = (int64_t)nnz;
   }
   if (!st && !c->d_cnt) {
     // dense per-vertex scratch of the query kernels

@@ -102,6 +102,8 @@ def test_start_all_vertices_and_isolated(P, oracle, inputs):
         want = oracle.walk(g, 3, 20_000, 99, start_all=start_all)
         assert (P.paths() == want).all()
         inv_ptr, inv_pid = oracle.index(g.n, want)
+        gp, gid = P.index(g.n)  # empty lists of isolated vertices
+        assert (gp == inv_ptr).all() and (gid == inv_pid).all()
         q = np.arange(g.n, dtype=np.int32)  # includes isolated vertices
         P.set_option("topk.form", 1)
         _check_topk(P.topk(q, 7), oracle.topk(g.n, want, inv_ptr, inv_pid, q, 7), "start")
