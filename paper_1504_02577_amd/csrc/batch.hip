@@ -164,7 +164,7 @@ __device__ void wave_query(const BatchArgs& A, int32_t qi, char* region) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = lane; i < (P >> 1); i += kWave) {
-        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
         const int hi = lo + stride;
         const bool desc = (lo & size) == 0;
         const uint64_t x = sorted[lo], y = sorted[hi];
@@ -317,7 +317,15 @@ struct BatchState {
   size_t cand_n_cap = 0;
   char* d_scan = nullptr;
   size_t scan_cap = 0;
-  std::vector<HubQuery> h_hq;  // must outlive the asynchronous upload
+  std::vector<HubQuery> h_hq;
+  // page-locked staging of the plan; `uploaded` guards its reuse
+  PinnedBuf pin_items, pin_hq;
+  hipEvent_t uploaded = nullptr;
+  bool upload_pending = false;
+  // second stream: the hub pipeline runs beside the persistent kernel
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  size_t hub_budget = 0;  // staging budget in bytes, fixed at first use
   // configuration
   bool tuned = false;
   BatchConfig cfg;
@@ -340,6 +348,7 @@ struct BatchState {
   size_t last_lds = 0;
   std::string tune_key;
   bool no_tune = false;  // serving lanes reuse a stored or default configuration
+  bool no_fork = false;  // serving lanes: one stream each (lanes overlap one another)
 };
 
 static BatchState* state(Lane* lane) {
@@ -357,12 +366,19 @@ void copy_batch_options(panther_ctx* c, Lane* dst) {
   b->hub_bits_max = a->hub_bits_max;
   b->tuned = false;
   b->no_tune = true;
+  b->no_fork = true;
 }
 
 void free_batch_state(Lane* lane) {
   if (!lane->batch) return;
   BatchState* b = lane->batch;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->uploaded) (void)hipEventDestroy(b->uploaded);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->side) (void)hipStreamDestroy(b->side);
+  pinned_release(b->pin_items);
+  pinned_release(b->pin_hq);
   ctx_free(b->d_items);
   ctx_free(b->d_queue);
   for (void* p : {(void*)b->d_hq, (void*)b->d_stA, (void*)b->d_stB, (void*)b->d_bkt_cnt,
@@ -473,15 +489,30 @@ static int grow(panther_ctx* c, P*& ptr, size_t& cap, size_t want, size_t elem, 
 }
 
 // Enqueues a plan on stream s: the hub chunks, then the persistent kernel.
+// When both parts have work, the hub chunks go to a second stream forked
+// from s and joined back, so they overlap the persistent kernel.
 static hipError_t enqueue(panther_ctx* c, BatchState* b, const Plan& P, KernelFn fn, int grid,
                           int block, size_t lds, hipStream_t s) {
+  const bool fork = !P.hub.empty() && P.run_kernel && !b->no_fork;
+  hipStream_t hs = s;
+  if (fork) {
+    hipError_t e = hipEventRecord(b->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+    if (e != hipSuccess) return e;
+    hs = b->side;
+  }
   for (const HubArgs& h : P.hub) {
-    const hipError_t e = enqueue_hub_chunk(h, c->stride, b->d_scan, s);
+    const hipError_t e = enqueue_hub_chunk(h, c->stride, b->d_scan, hs);
     if (e != hipSuccess) return e;
   }
   if (P.run_kernel) {
     k_reset_queue<<<1, 64, 0, s>>>(P.args.queue);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, P.args);
+  }
+  if (fork) {
+    hipError_t e = hipEventRecord(b->ev_join, b->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join, 0);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }
@@ -500,6 +531,12 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
   if (!P.hub.empty()) {
     st = ctx_hip(c, hub_set_attributes(), "hub kernel attributes");
     if (st) return st;
+    if (!b->side && !b->no_fork) {
+      st = ctx_hip(c, hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking), "hub stream");
+      if (!st) st = ctx_hip(c, hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "hub events");
+      if (!st) st = ctx_hip(c, hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming), "hub events");
+      if (st) return st;
+    }
   }
   const bool same = b->exec && b->exec_stream == s && b->exec_block == cfg.block &&
                     b->exec_grid == grid && b->exec_lds == lay.lds && b->exec_plan == P;
@@ -546,17 +583,21 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
 
 // Splits the hub queries (longest first) into chunks whose staging fits a
 // memory budget, and fills the device buffers and per-chunk arguments.
-static int plan_hubs(panther_ctx* c, BatchState* b, const std::vector<std::pair<uint64_t, int32_t>>& C,
+static int plan_hubs(panther_ctx* c, BatchState* b,
+                     const std::vector<std::pair<uint64_t, int32_t>>& C,
                      const int32_t* dq, int32_t k, int32_t* d_ids, uint32_t* d_counts,
                      int32_t* d_len, float* theta, hipStream_t s, std::vector<HubArgs>* out) {
   out->clear();
   b->h_hq.clear();
   if (C.empty()) return PANTHER_OK;
   const uint64_t T = (uint64_t)c->T;
-  size_t free_b = 0, total_b = 0;
-  (void)hipMemGetInfo(&free_b, &total_b);
+  if (!b->hub_budget) {
+    size_t free_b = 0, total_b = 0;
+    (void)hipMemGetInfo(&free_b, &total_b);
+    b->hub_budget = std::max<size_t>(std::min((size_t)8 << 30, free_b / 4), (size_t)1 << 28);
+  }
   // staging bytes per occurrence slot: row order, bucket order
-  const size_t budget = std::min((size_t)8 << 30, free_b / 4);
+  const size_t budget = b->hub_budget;
   uint64_t occ_limit = std::max<uint64_t>(budget / 8, T * C.front().first);
   occ_limit = std::min<uint64_t>(occ_limit, (uint64_t)1 << 31);
   if (T * C.front().first > occ_limit)
@@ -632,7 +673,10 @@ static int plan_hubs(panther_ctx* c, BatchState* b, const std::vector<std::pair<
     return st;
   if ((st = grow(c, b->d_bkt_owner, b->bkt_owner_cap, max_bkt, sizeof(int32_t), "hub maps")))
     return st;
-  st = ctx_hip(c, hipMemcpyAsync(b->d_hq, b->h_hq.data(), sizeof(HubQuery) * b->h_hq.size(),
+  if ((st = pinned_ensure(c, b->pin_hq, sizeof(HubQuery) * b->h_hq.size(), "hub plan")))
+    return st;
+  std::memcpy(b->pin_hq.p, b->h_hq.data(), sizeof(HubQuery) * b->h_hq.size());
+  st = ctx_hip(c, hipMemcpyAsync(b->d_hq, b->pin_hq.p, sizeof(HubQuery) * b->h_hq.size(),
                                  hipMemcpyHostToDevice, s),
                "hub plan upload");
   if (st) return st;
@@ -673,7 +717,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b, const std::vector<std::pair<
 // Builds the plan for one configuration.  With `with_hubs` false the hub
 // queries are left out (the autotuner times the persistent kernel alone).
 static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int32_t* dq,
-                const std::vector<uint64_t>& qlen, int64_t nq, int32_t k, int32_t* d_ids,
+                const uint64_t* qlen, int64_t nq, int32_t k, int32_t* d_ids,
                 uint32_t* d_counts, int32_t* d_len, float* theta, hipStream_t s, bool with_hubs,
                 Plan* out, std::vector<int32_t>* host_items) {
   const Layout lay = layout_for(c, cfg);
@@ -719,6 +763,12 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   by_class(B);
   by_class(A);
   if (!with_hubs) C.clear();
+  // the pinned staging of the previous plan must have been consumed
+  if (b->upload_pending) {
+    int st0 = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan");
+    if (st0) return st0;
+    b->upload_pending = false;
+  }
   int st = plan_hubs(c, b, C, dq, k, d_ids, d_counts, d_len, theta, s, &out->hub);
   if (st) return st;
   host_items->clear();
@@ -735,11 +785,20 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
     b->d_queue = static_cast<uint32_t*>(p);
   }
   if (need) {
-    st = ctx_hip(c, hipMemcpyAsync(b->d_items, host_items->data(), sizeof(int32_t) * need,
+    if ((st = pinned_ensure(c, b->pin_items, sizeof(int32_t) * need, "batch plan"))) return st;
+    std::memcpy(b->pin_items.p, host_items->data(), sizeof(int32_t) * need);
+    st = ctx_hip(c, hipMemcpyAsync(b->d_items, b->pin_items.p, sizeof(int32_t) * need,
                                    hipMemcpyHostToDevice, s),
                  "batch plan upload");
     if (st) return st;
   }
+  if (!b->uploaded) {
+    st = ctx_hip(c, hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming), "batch plan");
+    if (st) return st;
+  }
+  st = ctx_hip(c, hipEventRecord(b->uploaded, s), "batch plan");
+  if (st) return st;
+  b->upload_pending = true;
   BatchArgs a{};
   a.queries = dq;
   a.itemsB = b->d_items;
@@ -764,9 +823,9 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   return PANTHER_OK;
 }
 
-int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector<uint64_t>& qlen,
-                int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
-                float* theta, hipStream_t s) {
+int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* qlen, int64_t nq,
+                int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
+                hipStream_t s) {
   BatchState* b = state(lane);
   std::vector<int32_t> items;
   Plan args;
@@ -840,8 +899,6 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector
   int st = plan(c, b, b->cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, theta, s, true, &args,
                 &items);
   if (st) return st;
-  st = launch_batched(c, b, b->cfg, args, s, true);
-  if (st) return st;
-  // the host plan vector must outlive the asynchronous upload
-  return ctx_hip(c, hipStreamSynchronize(s), "batched");
+  // the plan's pinned staging is guarded by b->uploaded; nothing here waits
+  return launch_batched(c, b, b->cfg, args, s, true);
 }

@@ -154,7 +154,7 @@ __device__ __forceinline__ void block_bitonic_desc(K* s, int P) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < (P >> 1); i += BLOCK) {
-        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
         const int hi = lo + stride;
         const bool desc = (lo & size) == 0;
         K a = s[lo], b = s[hi];
@@ -173,7 +173,7 @@ __device__ __forceinline__ void block_bitonic_asc(K* s, int P) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = threadIdx.x; i < (P >> 1); i += BLOCK) {
-        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
         const int hi = lo + stride;
         const bool asc = (lo & size) == 0;
         K a = s[lo], b = s[hi];

@@ -48,7 +48,7 @@ __device__ void wave_sort_pairs(double* d, int32_t* v, int cnt) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = lane; i < (P >> 1); i += kWave) {
-        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
         const int hi = lo + stride;
         const bool asc = (lo & size) == 0;
         const double a = d[lo], b = d[hi];

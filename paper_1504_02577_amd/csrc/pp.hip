@@ -59,8 +59,8 @@ int ensure_features(panther_ctx* c, int32_t D, hipStream_t s) {
   int32_t* ids = static_cast<int32_t*>(pp->b_iota.p);
   k_iota<<<(unsigned)((c->n + 255) / 256), 256, 0, s>>>(ids, c->n);
   HIPTRY(hipGetLastError(), "features");
-  std::vector<uint64_t> qlen;
-  TRY(query_lengths(c, &c->lane0, ids, c->n, s, qlen));
+  const uint64_t* qlen = nullptr;
+  TRY(query_lengths(c, &c->lane0, ids, c->n, s, &qlen));
   stage_begin(c, 3, s);
   TRY(run_batched(c, &c->lane0, ids, qlen, c->n, D, nullptr, nullptr, nullptr, c->d_theta, s));
   stage_end(c, 3, s);

@@ -79,7 +79,7 @@ __device__ void wave_sort_keys(uint64_t* a, int cnt) {
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = lane; i < (P >> 1); i += kWave) {
-        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
         const int hi = lo + stride;
         const bool asc = (lo & size) == 0;
         const uint64_t x = a[lo], y = a[hi];
@@ -106,7 +106,6 @@ struct PoolArgs {
   int32_t sort_cap;      // per-wave sort buffer entries: next power of two >= cap
   uint64_t* buf;         // [nq][slices][cap] pool buffers
   uint64_t* part;        // [nq][slices][P] sorted slice pools (slices > 1)
-  int32_t* part_cnt;     // [nq][slices]
   int32_t* pool_ids;     // [nq][P] result when slices == 1, ascending key order, -1 padded
   float* pool_d2;        // [nq][P]
 };
@@ -244,46 +243,27 @@ k_pp_pool(PoolArgs A) {
         A.pool_d2[(q0 + ql) * P + i] = ok ? __uint_as_float((uint32_t)(sb[i] >> 32)) : INFINITY;
       }
     } else {
+      // fixed-length slice pools, padded with the largest key
       uint64_t* o = A.part + ((q0 + ql) * A.slices + slice) * P;
-      for (int i = lane; i < m; i += kWave) o[i] = sb[i];
-      if (lane == 0) A.part_cnt[(q0 + ql) * A.slices + slice] = m;
+      for (int i = lane; i < P; i += kWave) o[i] = i < m ? sb[i] : ~0ull;
     }
     wsync();
   }
 }
 
 // One work-group per query: the P smallest keys over all slice pools.
+// Slice pools are P keys long, padded with ~0, which complement to 0: a
+// selected 0 is padding.
 __global__ void __launch_bounds__(kBlock)
 k_pp_merge(PoolArgs A) {
   __shared__ SelectSmem sm;
-  __shared__ int32_t pre[257];
   const int64_t qi = blockIdx.x;
   const int S = A.slices, P = A.P;
-  if (threadIdx.x == 0) {
-    int run = 0;
-    for (int s2 = 0; s2 < S; ++s2) {
-      pre[s2] = run;
-      run += A.part_cnt[qi * S + s2];
-    }
-    pre[S] = run;
-  }
-  __syncthreads();
-  const int total = pre[S];
   const uint64_t* base = A.part + qi * (int64_t)S * P;
-  auto key = [&](int i) {
-    int lo = 0, hi = S - 1;  // slice s with pre[s] <= i < pre[s+1]
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (pre[mid] <= i)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    return ~base[(int64_t)lo * P + (i - pre[lo])];  // larger = better
-  };
-  const int m = block_select_topk<kBlock>(key, total, P, sm);
+  auto key = [&](int i) { return ~base[i]; };  // larger = better
+  const int m = block_select_topk<kBlock>(key, S * P, P, sm);
   for (int i = threadIdx.x; i < P; i += kBlock) {
-    const bool ok = i < m;
+    const bool ok = i < m && sm.out[i] != 0ull;
     const uint64_t k2 = ok ? ~sm.out[i] : 0ull;
     A.pool_ids[qi * P + i] = ok ? (int32_t)(uint32_t)k2 : -1;
     A.pool_d2[qi * P + i] = ok ? __uint_as_float((uint32_t)(k2 >> 32)) : INFINITY;
@@ -348,7 +328,7 @@ k_pp_rerank(RerankArgs A) {
   for (int size = 2; size <= PP; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       for (int i = lane; i < (PP >> 1); i += kWave) {
-        const int lo = 2 * stride * (i / stride) + (i % stride);
+        const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
         const int hi = lo + stride;
         const bool asc = (lo & size) == 0;
         const double x = d[lo], y = d[hi];
@@ -436,25 +416,23 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   int64_t S = (2 * (int64_t)c->num_cus + tiles - 1) / tiles;
   S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
   S = std::min<int64_t>(S, std::max<int64_t>(1, c->n / 4096));
-  S = std::min<int64_t>(S, std::max<int64_t>(1, 32768 / P));  // bounds the merge work
+  S = std::min<int64_t>(S, std::max<int64_t>(1, 262144 / P));  // bounds the merge work
   const int64_t rps = ((c->n + S - 1) / S + kChunk - 1) / kChunk * kChunk;
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
   const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;
-  const size_t cnt_bytes = S > 1 ? sizeof(int32_t) * (size_t)nq * S : 0;
   const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
-  TRY(ctx_ensure(c, lane->b_pool, buf_bytes + part_bytes + cnt_bytes + ids_bytes + 256, "pools"));
+  TRY(ctx_ensure(c, lane->b_pool, buf_bytes + part_bytes + ids_bytes + 256, "pools"));
   TRY(ctx_ensure(c, lane->b_stats, 64, "pp stats"));
   char* base = static_cast<char*>(lane->b_pool.p);
   uint64_t* buf = reinterpret_cast<uint64_t*>(base);
   uint64_t* part = reinterpret_cast<uint64_t*>(base + buf_bytes);
-  int32_t* part_cnt = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes);
-  int32_t* pool_ids = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes + cnt_bytes);
+  int32_t* pool_ids = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes);
   float* pool_d2 = reinterpret_cast<float*>(pool_ids + (size_t)nq * P);
   HIPTRY(hipMemsetAsync(lane->b_stats.p, 0, 64, s), "pp stats");
   int sort_cap = 2;
   while (sort_cap < cap) sort_cap <<= 1;
   PoolArgs pa{static_cast<const __bf16*>(pp->b_bf16.p), static_cast<const float*>(pp->b_norm.p),
-              c->n, dq, nq, P, cap, (int32_t)S, (int32_t)rps, sort_cap, buf, part, part_cnt,
+              c->n, dq, nq, P, cap, (int32_t)S, (int32_t)rps, sort_cap, buf, part,
               pool_ids, pool_d2};
   const size_t sort_lds = sizeof(uint64_t) * (size_t)sort_cap * (kBlock / kWave);
   HIPTRY(hipFuncSetAttribute((const void*)k_pp_pool, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -18,6 +18,12 @@ struct DevBuf {
   size_t cap = 0;
 };
 
+// Page-locked host memory (staging of plans and query lengths).
+struct PinnedBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+};
+
 // Panther++ data shared by every lane: bf16 copy of theta and its norms.
 struct PPState {
   DevBuf b_bf16, b_norm, b_iota;
@@ -30,6 +36,7 @@ struct PPState {
 struct Lane {
   BatchState* batch = nullptr;
   DevBuf b_qlen, b_pool, b_out, b_stats, b_q;
+  PinnedBuf h_qlen;  // path-list lengths of the last call's queries
   bool have_stats = false;
   double max_rel_err = 0.0;
   double mean_pre_recall = 0.0;
@@ -109,9 +116,12 @@ int ctx_alloc(panther_ctx* c, void** p, size_t bytes, const char* what);  // thr
 // Makes b hold at least `bytes`; the contents are not preserved on growth.
 int ctx_ensure(panther_ctx* c, DevBuf& b, size_t bytes, const char* what);
 void ctx_release(DevBuf& b);
-// Path-list lengths of the queries, gathered on the device and copied back.
+int pinned_ensure(panther_ctx* c, PinnedBuf& b, size_t bytes, const char* what);
+void pinned_release(PinnedBuf& b);
+// Path-list lengths of the queries, gathered on the device and copied back
+// to the lane's pinned buffer (*len points there until the lane's next call).
 int query_lengths(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, hipStream_t s,
-                  std::vector<uint64_t>& len);
+                  const uint64_t** len);
 void ctx_free(void* p);
 // Stage timing: stage i is bracketed by events 2i and 2i+1.
 void stage_begin(panther_ctx* c, int stage, hipStream_t s);
@@ -123,9 +133,10 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
 
 // batched form (batch.hip).  With theta != nullptr the pass writes Panther++
 // feature rows (k = D) instead of ids/counts.
-int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const std::vector<uint64_t>& qlen,
-                int64_t nq, int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len,
-                float* theta, hipStream_t s);
+// Enqueues the work on s; returns without waiting for it.
+int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* qlen, int64_t nq,
+                int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
+                hipStream_t s);
 int set_batch_option(panther_ctx* c, const std::string& key, int64_t value);
 // copies the forced batch options of lane 0 to another lane
 void copy_batch_options(panther_ctx* c, Lane* dst);

@@ -85,6 +85,23 @@ void ctx_release(DevBuf& b) {
   b.cap = 0;
 }
 
+int pinned_ensure(panther_ctx* c, PinnedBuf& b, size_t bytes, const char* what) {
+  if (bytes <= b.cap && b.p) return PANTHER_OK;
+  pinned_release(b);
+  void* p = nullptr;
+  if (hipHostMalloc(&p, bytes < 4096 ? 4096 : bytes, hipHostMallocDefault) != hipSuccess || !p)
+    return ctx_fail(c, PANTHER_ENOMEM, "out of pinned host memory (%s)", what);
+  b.p = p;
+  b.cap = bytes < 4096 ? 4096 : bytes;
+  return PANTHER_OK;
+}
+
+void pinned_release(PinnedBuf& b) {
+  if (b.p) (void)hipHostFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
 
 static void free_features(panther_ctx* c) {
   ctx_free(c->d_theta);
@@ -650,20 +667,22 @@ void free_lane(Lane* lane) {
   free_batch_state(lane);
   for (DevBuf* b : {&lane->b_qlen, &lane->b_pool, &lane->b_out, &lane->b_stats, &lane->b_q})
     ctx_release(*b);
+  pinned_release(lane->h_qlen);
   lane->have_stats = false;
 }
 
 int query_lengths(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, hipStream_t s,
-                  std::vector<uint64_t>& len) {
-  TRY(ctx_ensure(c, lane->b_qlen, sizeof(uint64_t) * (size_t)std::max<int64_t>(nq, 1),
-                 "query lengths"));
+                  const uint64_t** len) {
+  const size_t bytes = sizeof(uint64_t) * (size_t)std::max<int64_t>(nq, 1);
+  TRY(ctx_ensure(c, lane->b_qlen, bytes, "query lengths"));
+  TRY(pinned_ensure(c, lane->h_qlen, bytes, "query lengths"));
   launch_query_lengths(c->d_inv_ptr, dq, nq, static_cast<uint64_t*>(lane->b_qlen.p), s);
   HIPTRY(hipGetLastError(), "query lengths");
-  len.resize((size_t)nq);
-  HIPTRY(hipMemcpyAsync(len.data(), lane->b_qlen.p, sizeof(uint64_t) * (size_t)nq,
+  HIPTRY(hipMemcpyAsync(lane->h_qlen.p, lane->b_qlen.p, sizeof(uint64_t) * (size_t)nq,
                         hipMemcpyDeviceToHost, s),
          "query lengths");
   HIPTRY(hipStreamSynchronize(s), "query lengths");
+  *len = static_cast<const uint64_t*>(lane->h_qlen.p);
   return PANTHER_OK;
 }
 
@@ -707,8 +726,8 @@ extern "C" int panther_topk_similar(panther_ctx* c, const int32_t* queries, int6
   }
   TRY(order_begin(c, s));
   stage_begin(c, 2, s);
-  std::vector<uint64_t> qlen;
-  TRY(query_lengths(c, &c->lane0, dq, nq, s, qlen));
+  const uint64_t* qlen = nullptr;
+  TRY(query_lengths(c, &c->lane0, dq, nq, s, &qlen));
   if (c->topk_form == PANTHER_FORM_PLAIN) {
     TopkScratch sc{c->d_cnt, c->d_touched, c->d_ctl};
     for (int64_t i = 0; i < nq; ++i) {

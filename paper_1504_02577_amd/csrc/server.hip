@@ -158,8 +158,8 @@ static void run_batch(panther_server* sv, LaneWorker* w, Batch& b) {
                                      hipMemcpyHostToDevice, s),
                    "server upload");
     if (!st && kind == 0) {
-      std::vector<uint64_t> qlen;
-      st = query_lengths(c, &w->lane, dq, nq, s, qlen);
+      const uint64_t* qlen = nullptr;
+      st = query_lengths(c, &w->lane, dq, nq, s, &qlen);
       if (!st)
         st = run_batched(c, &w->lane, dq, qlen, nq, kmax, d_ids, d_cnt, d_len, nullptr, s);
       if (!st)
