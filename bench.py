@@ -16,6 +16,8 @@ Other workloads (one JSON line each, not the headline):
                         (k=20) in the BF16 matrix-core form, FP64 form timed
                         on a 1,024-query subset
   --workload serve      continuous-batching server under Poisson arrivals
+  --workload allv       all-vertex top-5 (every vertex of the graph is a
+                        query, the paper's Table 2 workload) on --allv-graph
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
 """
@@ -89,6 +91,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=50_000.0)
     ap.add_argument("--serve-graph", default="rmat20")
+    ap.add_argument("--allv-graph", default="rmat20")
+    ap.add_argument("--allv-k", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="paths in the oracle sample (0 = the full R of the workload)")
     args = ap.parse_args()
@@ -113,6 +117,8 @@ def main():
         return bench_pp(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "allv":
+        return bench_allv(args)
     t0 = time.time()
     g, q, p = inputs.workload(args.workload)
     T, R, seed, k = p["T"], p["R"], p["seed"], p["k"]
@@ -207,6 +213,59 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(g, q, T, k, seed, args.cpu_sample or R)
+    P.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_allv(args):
+    """All-vertex top-k: one call answers the top-k of every vertex."""
+    import torch
+    from paper_1504_02577_amd import inputs
+    from paper_1504_02577_amd.panther import Panther
+
+    g, _, p = inputs.workload(args.allv_graph)
+    T, R, seed, k = p["T"], p["R"], p["seed"], args.allv_k
+    P = Panther(0)
+    P.load_graph(g)
+    P.set_option("timing", 1)
+    P.sample_paths(T, R, seed)
+    dev = torch.device("cuda:0")
+    out = (torch.empty((g.n, k), dtype=torch.int32, device=dev),
+           torch.empty((g.n, k), dtype=torch.uint32, device=dev),
+           torch.empty(g.n, dtype=torch.int32, device=dev))
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(args.warmup):
+        P.topk_all(g.n, k, out=out, stream=stream)
+    torch.cuda.synchronize()
+    dev_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P.topk_all(g.n, k, out=out, stream=stream)
+        dev_ms.append(P.stage_times()["topk"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res = {"metric": "vertices/s", "value": g.n / dt, "unit": "vertices/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic",
+           "config": {"workload": f"allv: top-{k} of all {g.n} vertices of {args.allv_graph}, "
+                                  f"T={T}, R={R}", "parallelism": "single GPU"},
+           "device_ms": float(np.mean(dev_ms)), "roofline": None}
+    if not args.no_cpu_baseline:
+        import oracle
+
+        oracle.build()
+        paths = oracle.walk(g, T, R, seed)
+        inv_ptr, inv_pid = oracle.index(g.n, paths)
+        sample = min(g.n, 200_000)
+        t1 = time.perf_counter()
+        oracle.topk(g.n, paths, inv_ptr, inv_pid, np.arange(sample, dtype=np.int32), k)
+        dt1 = time.perf_counter() - t1
+        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": sample / dt1, "unit": "vertices/s", "cores": cores,
+                               "kind": "oracle",
+                               "sample": f"oracle top-{k} of vertices 0..{sample - 1} on the "
+                                         f"oracle's own paths and index, {dt1:.2f} s"}
     P.close()
     print(json.dumps(res), flush=True)
 

@@ -151,6 +151,17 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * Errors: EINVAL (unknown key or value out of range). */
 int panther_set_option(panther_ctx *ctx, const char *key, int64_t value);
 
+/* All-vertex top-k (Sec. 4, Table 2's workload): the Panther top-k of
+ * every vertex v in [0, n), as if panther_topk_similar were called with
+ * queries 0..n-1 in the batched form.  Layout: out_ids int32[n][k],
+ * out_counts uint32[n][k], out_len int32[n] (padding as there).  With
+ * mem == PANTHER_MEM_DEVICE and a stream the call is asynchronous.
+ * Errors: ESTATE (no paths), EINVAL (k < 1 or k > 1024, NULL buffers, bad
+ * mem), ENOMEM, EDEVICE. */
+int panther_topk_all(panther_ctx *ctx, int32_t k, int32_t *out_ids,
+                     uint32_t *out_counts, int32_t *out_len, int mem,
+                     void *stream);
+
 /* Copies the sampled paths, row-major int32[R][T+1]. ESTATE without paths. */
 int panther_get_paths(panther_ctx *ctx, int32_t *out, int mem);
 

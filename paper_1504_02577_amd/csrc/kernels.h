@@ -99,6 +99,7 @@ void launch_topk_plain(int stride, int32_t q, const uint64_t* inv_ptr, const uin
                        int32_t* out_ids, uint32_t* out_counts, int32_t* out_len,
                        hipStream_t s);
 
+void launch_iota(int32_t* out, int32_t n, hipStream_t s);
 void launch_query_lengths(const uint64_t* inv_ptr, const int32_t* queries, int64_t nq,
                           uint64_t* out, hipStream_t s);
 

@@ -82,6 +82,7 @@ struct panther_ctx {
   int64_t nnz = 0;
   // storage reused across sample_paths / query calls
   DevBuf b_paths, b_inv_pid, b_inv_ptr, b_keys0, b_keys1, b_vtmp, b_hist, b_offs, b_stemp, b_nnz;
+  DevBuf b_allv;  // vertex ids 0..n-1 (all-vertex top-k)
   DevBuf b_queries, b_outs;
   // dense query scratch (plain form, hub queries)
   uint32_t* d_cnt = nullptr;

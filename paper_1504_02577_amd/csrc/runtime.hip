@@ -123,7 +123,7 @@ static void free_paths(panther_ctx* c, bool release) {
   if (release) {
     free_lane(&c->lane0);
     for (DevBuf* b : {&c->b_paths, &c->b_inv_pid, &c->b_inv_ptr, &c->b_keys0, &c->b_keys1,
-                      &c->b_vtmp, &c->b_hist, &c->b_offs, &c->b_stemp, &c->b_nnz, &c->b_queries,
+                      &c->b_vtmp, &c->b_hist, &c->b_offs, &c->b_stemp, &c->b_nnz, &c->b_allv, &c->b_queries,
                       &c->b_outs})
       ctx_release(*b);
     ctx_free(c->d_cnt);
@@ -683,6 +683,60 @@ int query_lengths(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, hip
          "query lengths");
   HIPTRY(hipStreamSynchronize(s), "query lengths");
   *len = static_cast<const uint64_t*>(lane->h_qlen.p);
+  return PANTHER_OK;
+}
+
+// ---------------------------------------------------------------------------
+// all-vertex top-k: the batched form over queries 0..n-1
+// ---------------------------------------------------------------------------
+extern "C" int panther_topk_all(panther_ctx* c, int32_t k, int32_t* out_ids, uint32_t* out_counts,
+                                int32_t* out_len, int mem, void* stream) {
+  if (!c) return PANTHER_EINVAL;
+  c->err.clear();
+  if (!c->has_paths) return ctx_fail(c, PANTHER_ESTATE, "topk_all before sample_paths");
+  if (k < 1 || k > 1024) return ctx_fail(c, PANTHER_EINVAL, "k must lie in [1, 1024]");
+  if (mem != PANTHER_MEM_HOST && mem != PANTHER_MEM_DEVICE)
+    return ctx_fail(c, PANTHER_EINVAL, "bad mem");
+  if (!out_ids || !out_counts || !out_len) return ctx_fail(c, PANTHER_EINVAL, "null buffer");
+  if (hipSetDevice(c->device) != hipSuccess) return ctx_fail(c, PANTHER_EDEVICE, "hipSetDevice");
+  hipStream_t s = pick_stream(c, stream);
+  const int64_t n = c->n;
+  TRY(ctx_ensure(c, c->b_allv, sizeof(int32_t) * (size_t)n, "vertex ids"));
+  int32_t* ids = static_cast<int32_t*>(c->b_allv.p);
+  int32_t* d_ids = out_ids;
+  uint32_t* d_cnt = out_counts;
+  int32_t* d_len = out_len;
+  Temp tmp;
+  if (mem == PANTHER_MEM_HOST) {
+    void* p;
+    TRY(ctx_alloc(c, &p, (sizeof(int32_t) + sizeof(uint32_t)) * (size_t)n * (size_t)k +
+                             sizeof(int32_t) * (size_t)n,
+                  "all-vertex outputs"));
+    tmp.add(p);
+    d_ids = static_cast<int32_t*>(p);
+    d_cnt = reinterpret_cast<uint32_t*>(d_ids + (size_t)n * k);
+    d_len = reinterpret_cast<int32_t*>(d_cnt + (size_t)n * k);
+  }
+  TRY(order_begin(c, s));
+  stage_begin(c, 2, s);
+  launch_iota(ids, (int32_t)n, s);
+  HIPTRY(hipGetLastError(), "vertex ids");
+  const uint64_t* qlen = nullptr;
+  TRY(query_lengths(c, &c->lane0, ids, n, s, &qlen));
+  TRY(run_batched(c, &c->lane0, ids, qlen, n, k, d_ids, d_cnt, d_len, nullptr, s));
+  stage_end(c, 2, s);
+  TRY(order_end(c, s));
+  if (mem == PANTHER_MEM_HOST) {
+    HIPTRY(hipMemcpyAsync(out_ids, d_ids, sizeof(int32_t) * (size_t)n * k, hipMemcpyDeviceToHost,
+                          s),
+           "all-vertex outputs");
+    HIPTRY(hipMemcpyAsync(out_counts, d_cnt, sizeof(uint32_t) * (size_t)n * k,
+                          hipMemcpyDeviceToHost, s),
+           "all-vertex outputs");
+    HIPTRY(hipMemcpyAsync(out_len, d_len, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s),
+           "all-vertex outputs");
+    HIPTRY(hipStreamSynchronize(s), "topk_all");
+  }
   return PANTHER_OK;
 }
 

@@ -98,6 +98,17 @@ __global__ void k_query_lengths(const uint64_t* __restrict__ inv_ptr,
 
 }  // namespace
 
+namespace {
+__global__ void k_iota_ids(int32_t* out, int32_t n) {
+  const int32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = i;
+}
+}  // namespace
+
+void launch_iota(int32_t* out, int32_t n, hipStream_t s) {
+  k_iota_ids<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, n);
+}
+
 void launch_query_lengths(const uint64_t* inv_ptr, const int32_t* queries, int64_t nq,
                           uint64_t* out, hipStream_t s) {
   if (nq > 0)

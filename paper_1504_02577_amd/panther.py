@@ -35,7 +35,7 @@ PANTHER_PP_BF16 = 1
 
 EXPORTS = [
     "panther_create", "panther_destroy", "panther_last_error", "panther_load_graph",
-    "panther_sample_paths", "panther_topk_similar", "panther_pp_topk",
+    "panther_sample_paths", "panther_topk_similar", "panther_topk_all", "panther_pp_topk",
     "panther_sample_size", "panther_set_option", "panther_get_paths", "panther_index_nnz",
     "panther_get_index", "panther_get_features", "panther_pp_stats", "panther_synchronize",
     "panther_stage_times", "panther_server_start", "panther_server_submit",
@@ -86,6 +86,7 @@ def lib():
         "panther_sample_paths": (ctypes.c_int, [P, i32, i64, u64]),
         "panther_topk_similar": (ctypes.c_int, [P, P, i64, i32, P, P, P, ctypes.c_int, P]),
         "panther_pp_topk": (ctypes.c_int, [P, P, i64, i32, i32, P, P, ctypes.c_int, P]),
+        "panther_topk_all": (ctypes.c_int, [P, i32, P, P, P, ctypes.c_int, P]),
         "panther_sample_size": (i64, [dbl, dbl, dbl, i32]),
         "panther_set_option": (ctypes.c_int, [P, ctypes.c_char_p, i64]),
         "panther_get_paths": (ctypes.c_int, [P, P, ctypes.c_int]),
@@ -140,6 +141,10 @@ def panther_sample_paths(ctx, T, R, seed):
 def panther_topk_similar(ctx, queries, nq, k, out_ids, out_counts, out_len, mem, stream=None):
     return lib().panther_topk_similar(ctx, queries, nq, k, out_ids, out_counts, out_len, mem,
                                       stream)
+
+
+def panther_topk_all(ctx, k, out_ids, out_counts, out_len, mem, stream=None):
+    return lib().panther_topk_all(ctx, k, out_ids, out_counts, out_len, mem, stream)
 
 
 def panther_pp_topk(ctx, queries, nq, D, k, out_ids, out_dist, mem, stream=None):
@@ -328,6 +333,22 @@ class Panther:
         self._check(panther_topk_similar(
             self.h, qp, int(queries.shape[0]), k, _buf(ids, np.int32)[0],
             _buf(cnt, np.uint32)[0], _buf(ln, np.int32)[0], PANTHER_MEM_DEVICE, stream))
+        return out
+
+    def topk_all(self, n, k, out=None, stream=None):
+        """Top-k of every vertex 0..n-1: host numpy (ids, counts, len), or into
+        the device tensors of `out`."""
+        if out is None:
+            ids = np.empty((n, k), np.int32)
+            cnt = np.empty((n, k), np.uint32)
+            ln = np.empty(n, np.int32)
+            self._check(panther_topk_all(
+                self.h, k, ids.ctypes.data_as(ctypes.c_void_p), cnt.ctypes.data_as(ctypes.c_void_p),
+                ln.ctypes.data_as(ctypes.c_void_p), PANTHER_MEM_HOST, stream))
+            return ids, cnt, ln
+        ids, cnt, ln = out
+        self._check(panther_topk_all(self.h, k, _buf(ids, np.int32)[0], _buf(cnt, np.uint32)[0],
+                                     _buf(ln, np.int32)[0], PANTHER_MEM_DEVICE, stream))
         return out
 
     def pp_topk(self, queries, D, k, out=None, stream=None):

@@ -241,6 +241,27 @@ def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb, hb)
             P.set_option(key, v)
 
 
+@pytest.mark.parametrize("k", [5, 50])
+def test_all_vertex_topk(P, oracle, rmat14, k):
+    """panther_topk_all equals the oracle's top-k of every vertex (the
+    paper's all-vertex workload), host and device outputs."""
+    import torch
+
+    g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
+    _say(f"case: all-vertex top-{k}")
+    P.load_graph(g)
+    P.sample_paths(T, R, seed)
+    q = np.arange(g.n, dtype=np.int32)
+    want = oracle.topk(g.n, paths, inv_ptr, inv_pid, q, k)
+    _check_topk(P.topk_all(g.n, k), want, f"all-vertex k={k}")
+    out = (torch.full((g.n, k), 7, dtype=torch.int32, device="cuda"),
+           torch.full((g.n, k), 7, dtype=torch.uint32, device="cuda"),
+           torch.full((g.n,), 7, dtype=torch.int32, device="cuda"))
+    P.topk_all(g.n, k, out=out, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    _check_topk(tuple(t.cpu().numpy() for t in out), want, f"all-vertex device k={k}")
+
+
 def test_batched_graph_replays(P, oracle, inputs, rmat14):
     """Repeated calls with the same buffers replay the captured graph; each
     replay, with other device work and synchronisations in between, must
