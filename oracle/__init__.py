@@ -65,6 +65,7 @@ def lib():
         L.or_dist2.argtypes = [P, P, i32]
         L.or_dist2.restype = dbl
         L.or_knn.argtypes = [i32, i32, P, P, i64, i32, P, P]
+        L.or_knn_cross.argtypes = [i32, i64, P, i32, P, i32, P, P]
         L.or_sample_size.argtypes = [dbl, dbl, dbl, i32]
         L.or_sample_size.restype = i64
         _lib = L
@@ -207,6 +208,21 @@ def knn(theta, queries, k: int):
     ids = np.zeros((q.shape[0], k), np.int32)
     dist = np.zeros((q.shape[0], k), np.float64)
     _check(lib().or_knn(n, D, _p(theta), _p(q), q.shape[0], k, _p(ids), _p(dist)), "knn")
+    return ids, dist
+
+
+def knn_cross(theta_q, theta_db, k: int):
+    """Cross-graph kNN: row i of theta_q (a query's features in its own
+    graph) against every row of theta_db (the other graph); no row is
+    excluded."""
+    tq = _c(theta_q, np.float32)
+    tdb = _c(theta_db, np.float32)
+    nq, D = tq.shape
+    assert tdb.shape[1] == D
+    ids = np.zeros((nq, k), np.int32)
+    dist = np.zeros((nq, k), np.float64)
+    _check(lib().or_knn_cross(D, nq, _p(tq), tdb.shape[0], _p(tdb), k, _p(ids), _p(dist)),
+           "knn_cross")
     return ids, dist
 
 

@@ -412,6 +412,52 @@ int or_knn(int32_t n, int32_t D, const float *theta, const int32_t *queries,
   return status;
 }
 
+/* Cross-graph nearest neighbours (Sec. 3.3 applied across two networks, the
+ * identity-resolution setting of Fig. 1a): query i has the feature row
+ * theta_q[i] of its own graph; the database is every row v of the other
+ * graph's theta_db.  All nq_db rows are candidates (the query is not one of
+ * them); order (squared distance ascending, id ascending); padding
+ * (-1, +inf) when nq_db < k. */
+int or_knn_cross(int32_t D, int64_t nq, const float *theta_q, int32_t n_db,
+                 const float *theta_db, int32_t k, int32_t *out_ids, double *out_dist) {
+  if (k < 1 || D < 1) return OR_EINVAL;
+  int status = OR_OK;
+#pragma omp parallel
+  {
+    double *bd = (double *)malloc(sizeof(double) * (size_t)k);
+    int32_t *bi = (int32_t *)malloc(sizeof(int32_t) * (size_t)k);
+    if (!bd || !bi) {
+#pragma omp atomic write
+      status = OR_ENOMEM;
+    } else {
+#pragma omp for schedule(dynamic, 1)
+      for (int64_t i = 0; i < nq; ++i) {
+        const float *tq = theta_q + i * D;
+        int32_t have = 0;
+        for (int32_t v = 0; v < n_db; ++v) {
+          double d2 = or_dist2(tq, theta_db + (int64_t)v * D, D);
+          if (have == k && !(d2 < bd[k - 1])) continue;
+          int32_t pos = have < k ? have : k - 1;
+          while (pos > 0 && d2 < bd[pos - 1]) {
+            bd[pos] = bd[pos - 1];
+            bi[pos] = bi[pos - 1];
+            --pos;
+          }
+          bd[pos] = d2;
+          bi[pos] = v;
+          if (have < k) ++have;
+        }
+        for (int32_t j = 0; j < k; ++j) {
+          out_ids[i * k + j] = j < have ? bi[j] : -1;
+          out_dist[i * k + j] = j < have ? sqrt(bd[j]) : INFINITY;
+        }
+      }
+    }
+    free(bd); free(bi);
+  }
+  return status;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sample size (Sec. 3.2): Theorem 1 with the VC bound of Lemma 1,           */
 /* R = c / eps^2 * (log2 C(T,2) + 1 + ln(1/delta)), rounded up.              */

@@ -74,6 +74,53 @@ def test_knn_padding(oracle):
     assert np.isinf(dist[0, 2:]).all() and (dist[0, :2] == 0).all()
 
 
+def _exact_cross(tq, tdb, k):
+    rq = [Fraction(float(x)) for x in tq]
+    d2 = sorted((sum((a - Fraction(float(b))) ** 2 for a, b in zip(rq, tdb[v])), v)
+                for v in range(tdb.shape[0]))
+    return d2[:k]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_knn_cross_vs_exact_rationals(oracle, seed):
+    """Cross-graph kNN: a query row of one graph against every row of the
+    other, ranked by exact rational squared distance, ties by id."""
+    rng = np.random.default_rng(10 + seed)
+    D, k = 6, 8
+    tdb = (rng.integers(0, 30, (45, D)) / 1000.0).astype(np.float32)
+    tq = (rng.integers(0, 30, (4, D)) / 1000.0).astype(np.float32)
+    tq[1] = tdb[17]            # an exact twin: distance 0, rank first ...
+    tdb[3] = tdb[17]           # ... behind an identical row of smaller id
+    ids, dist = oracle.knn_cross(tq, tdb, k)
+    for i in range(tq.shape[0]):
+        want = _exact_cross(tq[i], tdb, k)
+        assert np.allclose(dist[i], [math.sqrt(float(d)) for d, _ in want], rtol=1e-12, atol=0)
+        for j, (d, v) in enumerate(want):
+            others = [dd for dd, _ in want if dd != d]
+            assert ids[i, j] == v or any(abs(float(d - dd)) < 1e-12 for dd in others)
+    assert ids[1, 0] == 3 and ids[1, 1] == 17 and dist[1, 0] == 0.0 and dist[1, 1] == 0.0
+
+
+def test_knn_cross_reduces_to_single_graph(oracle, ba1k, ba1k_paths):
+    """With both sides the same graph, dropping the query itself from its
+    cross-graph list of k+1 leaves exactly its single-graph list of k."""
+    paths, inv_ptr, inv_pid = ba1k_paths
+    theta = oracle.features(ba1k.n, paths, inv_ptr, inv_pid, 12)
+    qs = np.array([0, 3, 77, 500, 999], np.int32)
+    k = 10
+    ci, cd = oracle.knn_cross(theta[qs], theta, k + 1)
+    si, sd = oracle.knn(theta, qs, k)
+    for i, q in enumerate(qs):
+        keep = ci[i] != q
+        assert (ci[i][keep][:k] == si[i]).all()
+        assert (cd[i][keep][:k] == sd[i]).all()
+
+
+def test_knn_cross_padding(oracle):
+    ids, dist = oracle.knn_cross(np.zeros((1, 3), np.float32), np.ones((2, 3), np.float32), 4)
+    assert ids[0].tolist() == [0, 1, -1, -1] and np.isinf(dist[0, 2:]).all()
+
+
 def test_dist2_is_fma_chain(oracle):
     """Squared distance of float32 rows in double, one fma per coordinate:
     exact for values whose differences square without rounding."""
