@@ -176,6 +176,24 @@ int panther_get_index(panther_ctx *ctx, int64_t *inv_ptr, uint32_t *inv_pid,
 /* Computes (if needed) and copies theta, fp32[n][D]. */
 int panther_get_features(panther_ctx *ctx, int32_t D, float *out, int mem);
 
+/* Cross-graph Panther++ (Sec. 3.3 across two networks, the identity
+ * resolution of Fig. 1a).  queries[i] = q is a vertex of qctx's graph; the
+ * result is the k vertices v of dbctx's graph of smallest Euclidean
+ * distance between theta(q), computed from qctx's paths, and theta(v),
+ * computed from dbctx's paths, ordered by (distance ascending, id
+ * ascending); every v is a candidate.  The form is dbctx's "pp.form"; the
+ * BF16 form scales both sides' features by dbctx's R before rounding, and
+ * the FP64 rerank restores exact distances.  Features for D are computed
+ * in each context when missing.  Layout and padding as panther_pp_topk.
+ * Both contexts must live on one device; errors are reported on dbctx.
+ * Errors: ESTATE (no paths on either side), EINVAL (the same context
+ * twice, different devices, D or k out of range, NULL buffers, bad mem),
+ * ERANGE (a query outside [0, n) of qctx's graph), ENOMEM, EDEVICE. */
+int panther_pp_topk_cross(panther_ctx *qctx, panther_ctx *dbctx,
+                          const int32_t *queries, int64_t nq, int32_t D,
+                          int32_t k, int32_t *out_ids, double *out_dist,
+                          int mem, void *stream);
+
 /* Statistics of the last BF16-form panther_pp_topk call: for each query,
  * how many returned ids the pool stage had ranked within the first k
  * before the rerank (*mean_pre_recall, in [0,1]) and the largest relative

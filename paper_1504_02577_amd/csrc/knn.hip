@@ -7,6 +7,9 @@
 // - (double)theta_v[d]; d2 = fma(delta, delta, d2) -- one fused multiply-add
 // per coordinate in coordinate order.
 //
+// The cross-graph form takes the query rows from another graph's features
+// and ranks every row of this one (no row is the query itself).
+//
 // A work-group takes QT queries (their rows in LDS as doubles) and streams
 // all n rows, one row per thread per round.  Each query keeps a candidate
 // buffer in LDS with a threshold (the kp-th best (d2, id) kept so far):
@@ -68,6 +71,7 @@ __device__ void wave_sort_pairs(double* d, int32_t* v, int cnt) {
 template <int QT>
 __global__ void __launch_bounds__(kBlock)
 k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
+           const float* __restrict__ qtheta, int32_t exclude_self,
            const int32_t* __restrict__ queries, int64_t nq, int32_t k, int32_t kp,
            int32_t* __restrict__ out_ids, double* __restrict__ out_dist) {
   extern __shared__ __align__(16) char lds[];
@@ -89,7 +93,7 @@ k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
   __syncthreads();
   for (int i = threadIdx.x; i < QT * D; i += kBlock) {
     const int32_t q = qid[i / D];
-    qv[i] = q >= 0 ? (double)theta[(int64_t)q * D + (i % D)] : 0.0;
+    qv[i] = q >= 0 ? (double)qtheta[(int64_t)q * D + (i % D)] : 0.0;
   }
   __syncthreads();
   for (int64_t base = 0; base < n; base += kBlock) {
@@ -111,7 +115,7 @@ k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
 #pragma unroll
     for (int q = 0; q < QT; ++q) {
       const int32_t me = qid[q];
-      if (v < n && me >= 0 && (int32_t)v != me &&
+      if (v < n && me >= 0 && (!exclude_self || (int32_t)v != me) &&
           pair_less(acc[q], (int32_t)v, tau_d[q], tau_v[q])) {
         const uint32_t pos = atomicAdd(&cnt[q], 1u);
         bd[q * kBuf + pos] = acc[q];
@@ -154,8 +158,11 @@ size_t knn_fp64_lds(int D) {
          sizeof(uint32_t) * (QT + 1) + (sizeof(double) + 2 * sizeof(int32_t)) * QT + 64;
 }
 
-int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const int32_t* queries, int64_t nq,
-                    int32_t k, int32_t* out_ids, double* out_dist, hipStream_t s) {
+// qtheta: the queries' feature rows (theta itself for one graph, the other
+// graph's for the cross-graph form, which excludes no row).
+int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const float* qtheta,
+                    bool exclude_self, const int32_t* queries, int64_t nq, int32_t k,
+                    int32_t* out_ids, double* out_dist, hipStream_t s) {
   constexpr int QT = 16;
   int kp = 1;
   while (kp < k) kp <<= 1;
@@ -164,8 +171,9 @@ int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const int32_t* que
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return (int)e;
   const unsigned grid = (unsigned)((nq + QT - 1) / QT);
-  if (grid) k_knn_fp64<QT><<<grid, kBlock, lds, s>>>(theta, n, D, queries, nq, k, kp, out_ids,
-                                                      out_dist);
+  if (grid)
+    k_knn_fp64<QT><<<grid, kBlock, lds, s>>>(theta, n, D, qtheta, exclude_self ? 1 : 0, queries,
+                                              nq, k, kp, out_ids, out_dist);
   return (int)hipGetLastError();
 }
 

@@ -16,10 +16,11 @@ using namespace panther;
 
 namespace panther {
 size_t knn_fp64_lds(int D);
-int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const int32_t* queries, int64_t nq,
-                    int32_t k, int32_t* out_ids, double* out_dist, hipStream_t s);
+int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const float* qtheta,
+                    bool exclude_self, const int32_t* queries, int64_t nq, int32_t k,
+                    int32_t* out_ids, double* out_dist, hipStream_t s);
 int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
-                int32_t* d_ids, double* d_dist, hipStream_t s);
+                int32_t* d_ids, double* d_dist, hipStream_t s, const float* qtheta);
 }  // namespace panther
 
 namespace {
@@ -142,11 +143,92 @@ extern "C" int panther_pp_topk(panther_ctx* c, const int32_t* queries, int64_t n
 int run_pp(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
            int32_t* d_ids, double* d_dist, hipStream_t s) {
   if (c->pp_form == PANTHER_PP_FP64) {
-    const int e = launch_knn_fp64(c->d_theta, c->n, D, dq, nq, k, d_ids, d_dist, s);
+    const int e = launch_knn_fp64(c->d_theta, c->n, D, c->d_theta, true, dq, nq, k, d_ids, d_dist,
+                                  s);
     HIPTRY((hipError_t)e, "pp fp64 knn");
     return PANTHER_OK;
   }
-  return run_pp_bf16(c, lane, dq, nq, D, k, d_ids, d_dist, s);
+  return run_pp_bf16(c, lane, dq, nq, D, k, d_ids, d_dist, s, nullptr);
+}
+
+// Cross-graph Panther++: queries are vertices of qc's graph, the database
+// is every vertex of dbc's graph; each side has its own paths and features.
+extern "C" int panther_pp_topk_cross(panther_ctx* qc, panther_ctx* dbc, const int32_t* queries,
+                                     int64_t nq, int32_t D, int32_t k, int32_t* out_ids,
+                                     double* out_dist, int mem, void* stream) {
+  if (!qc || !dbc) return PANTHER_EINVAL;
+  panther_ctx* const c = dbc;  // errors of the call are reported on the database context
+  qc->err.clear();
+  dbc->err.clear();
+  if (!qc->has_paths || !dbc->has_paths)
+    return ctx_fail(dbc, PANTHER_ESTATE, "pp_topk_cross before sample_paths on both graphs");
+  if (qc->device != dbc->device)
+    return ctx_fail(dbc, PANTHER_EINVAL, "the two contexts must be on the same device");
+  if (qc == dbc) return ctx_fail(dbc, PANTHER_EINVAL, "use panther_pp_topk within one graph");
+  if (D < 1 || D > 256) return ctx_fail(dbc, PANTHER_EINVAL, "D must lie in [1, 256]");
+  if (k < 1 || k > 256) return ctx_fail(dbc, PANTHER_EINVAL, "k must lie in [1, 256]");
+  if (nq < 0) return ctx_fail(dbc, PANTHER_EINVAL, "nq must be >= 0");
+  if (mem != PANTHER_MEM_HOST && mem != PANTHER_MEM_DEVICE)
+    return ctx_fail(dbc, PANTHER_EINVAL, "bad mem");
+  if (nq == 0) return PANTHER_OK;
+  if (!queries || !out_ids || !out_dist) return ctx_fail(dbc, PANTHER_EINVAL, "null buffer");
+  if (dbc->pp_form == PANTHER_PP_BF16 && D > 64)
+    return ctx_fail(dbc, PANTHER_EINVAL, "the BF16 form supports D <= 64");
+  if (hipSetDevice(dbc->device) != hipSuccess)
+    return ctx_fail(dbc, PANTHER_EDEVICE, "hipSetDevice");
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : dbc->stream;
+  std::vector<int32_t> hq;
+  const int32_t* dq = nullptr;
+  void* owned = nullptr;
+  // query ids are checked against the query graph
+  int st = stage_queries(qc, queries, nq, mem, s, hq, &dq, &owned);
+  struct Own {
+    void* p;
+    ~Own() { ctx_free(p); }
+  } own{owned};
+  if (st) {
+    if (qc->err.size()) dbc->err = qc->err;
+    return st;
+  }
+  TRY(order_begin(qc, s));
+  TRY(order_begin(dbc, s));
+  st = ensure_features(qc, D, s);
+  if (st) {
+    dbc->err = qc->err;
+    return st;
+  }
+  TRY(ensure_features(dbc, D, s));
+  Lane* lane = &dbc->lane0;
+  int32_t* d_ids = out_ids;
+  double* d_dist = out_dist;
+  if (mem == PANTHER_MEM_HOST) {
+    TRY(ctx_ensure(dbc, lane->b_out, (sizeof(int32_t) + sizeof(double)) * (size_t)nq * k,
+                   "pp outputs"));
+    d_dist = static_cast<double*>(lane->b_out.p);
+    d_ids = reinterpret_cast<int32_t*>(d_dist + (size_t)nq * k);
+  }
+  stage_begin(dbc, 4, s);
+  if (dbc->pp_form == PANTHER_PP_FP64) {
+    const int e = launch_knn_fp64(dbc->d_theta, dbc->n, D, qc->d_theta, false, dq, nq, k, d_ids,
+                                  d_dist, s);
+    HIPTRY((hipError_t)e, "pp fp64 cross knn");
+  } else {
+    TRY(prepare_bf16(dbc, D, s));
+    TRY(run_pp_bf16(dbc, lane, dq, nq, D, k, d_ids, d_dist, s, qc->d_theta));
+  }
+  stage_end(dbc, 4, s);
+  TRY(order_end(dbc, s));
+  TRY(order_end(qc, s));
+  if (mem == PANTHER_MEM_HOST) {
+    HIPTRY(hipMemcpyAsync(out_ids, d_ids, sizeof(int32_t) * (size_t)nq * k, hipMemcpyDeviceToHost,
+                          s),
+           "pp outputs");
+    HIPTRY(hipMemcpyAsync(out_dist, d_dist, sizeof(double) * (size_t)nq * k,
+                          hipMemcpyDeviceToHost, s),
+           "pp outputs");
+  }
+  HIPTRY(hipStreamSynchronize(s), "pp_topk_cross");
+  return PANTHER_OK;
 }
 
 extern "C" int panther_pp_stats(panther_ctx* c, double* max_rel_err, double* mean_pre_recall) {

@@ -64,6 +64,24 @@ k_bf16_rows(const float* __restrict__ theta, int32_t n, int32_t D, float s,
   norm[v] = acc;
 }
 
+// bf16 rows of the queries' own features (another graph's theta), scaled
+// by the database's s, gathered by query position
+__global__ void __launch_bounds__(kBlock)
+k_bf16_query_rows(const float* __restrict__ theta_q, int32_t D, const int32_t* __restrict__ queries,
+                  int64_t nq, float s, __bf16* __restrict__ out, float* __restrict__ norm) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nq) return;
+  const int32_t q = queries[i];
+  float acc = 0.f;
+  for (int d = 0; d < kDP; ++d) {
+    const __bf16 b = d < D ? (__bf16)(theta_q[(int64_t)q * D + d] * s) : (__bf16)0.f;
+    out[i * kDP + d] = b;
+    const float f = (float)b;
+    acc = fmaf(f, f, acc);
+  }
+  norm[i] = acc;
+}
+
 __device__ __forceinline__ uint64_t pool_key(float d2, int32_t v) {
   const float c = d2 > 0.f ? d2 : 0.f;
   return ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)v;
@@ -108,6 +126,12 @@ struct PoolArgs {
   uint64_t* part;        // [nq][slices][P] sorted slice pools (slices > 1)
   int32_t* pool_ids;     // [nq][P] result when slices == 1, ascending key order, -1 padded
   float* pool_d2;        // [nq][P]
+  // query operands: rows[q] / norm[q] of the database itself, or (cross
+  // form) qrows[i] / qnorm[i] gathered per query position i
+  const __bf16* qrows;
+  const float* qnorm;
+  int32_t q_by_pos;
+  int32_t exclude_self;  // single graph: the query's own row is no candidate
 };
 
 // grid (query tiles, database slices)
@@ -129,7 +153,7 @@ k_pp_pool(PoolArgs A) {
   for (int i = threadIdx.x; i < kQW; i += kBlock) {
     const int32_t q = q0 + i < A.nq ? A.queries[q0 + i] : -1;
     qid[i] = q;
-    qn_s[i] = q >= 0 ? A.norm[q] : 0.f;
+    qn_s[i] = q >= 0 ? (A.q_by_pos ? A.qnorm[q0 + i] : A.norm[q]) : 0.f;
     cnt[i] = 0u;
     tau[i] = ~0ull;
     tauf_s[i] = INFINITY;
@@ -140,10 +164,11 @@ k_pp_pool(PoolArgs A) {
 #pragma unroll
   for (int m = 0; m < kTiles; ++m) {
     const int32_t q = qid[m * 16 + (lane & 15)];
+    const int64_t qr = A.q_by_pos ? q0 + m * 16 + (lane & 15) : (int64_t)q;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       if (q >= 0) {
-        a[m][ks] = *reinterpret_cast<const bf16x8*>(A.rows + (int64_t)q * kDP + ks * 32 +
+        a[m][ks] = *reinterpret_cast<const bf16x8*>(A.qrows + qr * kDP + ks * 32 +
                                                     8 * (lane >> 4));
       } else {
 #pragma unroll
@@ -189,7 +214,8 @@ k_pp_pool(PoolArgs A) {
           d2 = d2 > 0.f ? d2 : 0.f;
           if (d2 <= tauf_s[ql]) {  // float prefilter; the exact key test follows
             const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)v;
-            if (key < tau[ql] && qid[ql] >= 0 && qid[ql] != (int32_t)v) {
+            if (key < tau[ql] && qid[ql] >= 0 &&
+                (!A.exclude_self || qid[ql] != (int32_t)v)) {
               const uint32_t pos = atomicAdd(&cnt[ql], 1u);
               A.buf[((q0 + ql) * A.slices + slice) * cap + pos] = key;
             }
@@ -271,7 +297,8 @@ k_pp_merge(PoolArgs A) {
 }
 
 struct RerankArgs {
-  const float* theta;    // [n][D]
+  const float* theta;    // [n][D] database rows
+  const float* qtheta;   // query rows by query id (theta itself, or the other graph's)
   int32_t D;
   const int32_t* queries;
   int64_t nq;
@@ -296,7 +323,7 @@ k_pp_rerank(RerankArgs A) {
   const int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + wid;
   if (qi >= A.nq) return;
   const int32_t q = A.queries[qi];
-  const float* tq = A.theta + (int64_t)q * A.D;
+  const float* tq = A.qtheta + (int64_t)q * A.D;
   const int P = A.P;
   double* d = sd[wid];
   int32_t* v = sv[wid];
@@ -396,8 +423,11 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
 
 namespace panther {
 
+// Pool pass + rerank over the database context c.  qtheta (null: c's own
+// features) holds the queries' feature rows when they come from another
+// graph; their bf16 operands are then gathered per query first.
 int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
-                int32_t* d_ids, double* d_dist, hipStream_t s) {
+                int32_t* d_ids, double* d_dist, hipStream_t s, const float* qtheta) {
   PPState* pp = c->pp;
   if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
   if (!pp || pp->bf16_D != D) return ctx_fail(c, PANTHER_ESTATE, "bf16 rows not prepared");
@@ -433,7 +463,21 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   while (sort_cap < cap) sort_cap <<= 1;
   PoolArgs pa{static_cast<const __bf16*>(pp->b_bf16.p), static_cast<const float*>(pp->b_norm.p),
               c->n, dq, nq, P, cap, (int32_t)S, (int32_t)rps, sort_cap, buf, part,
-              pool_ids, pool_d2};
+              pool_ids, pool_d2, static_cast<const __bf16*>(pp->b_bf16.p),
+              static_cast<const float*>(pp->b_norm.p), 0, 1};
+  if (qtheta) {
+    TRY(ctx_ensure(c, lane->b_qrows, (sizeof(__bf16) * kDP + sizeof(float)) * (size_t)nq,
+                   "query bf16 rows"));
+    __bf16* qr = static_cast<__bf16*>(lane->b_qrows.p);
+    float* qn = reinterpret_cast<float*>(qr + (size_t)nq * kDP);
+    k_bf16_query_rows<<<(unsigned)((nq + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        qtheta, D, dq, nq, scale, qr, qn);
+    HIPTRY(hipGetLastError(), "query bf16 rows");
+    pa.qrows = qr;
+    pa.qnorm = qn;
+    pa.q_by_pos = 1;
+    pa.exclude_self = 0;
+  }
   const size_t sort_lds = sizeof(uint64_t) * (size_t)sort_cap * (kBlock / kWave);
   HIPTRY(hipFuncSetAttribute((const void*)k_pp_pool, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)sort_lds),
@@ -445,7 +489,7 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
     HIPTRY(hipGetLastError(), "pp merge");
   }
   unsigned long long* st = static_cast<unsigned long long*>(lane->b_stats.p);
-  RerankArgs ra{c->d_theta, D, dq, nq, P, k, pool_ids, pool_d2,
+  RerankArgs ra{c->d_theta, qtheta ? qtheta : c->d_theta, D, dq, nq, P, k, pool_ids, pool_d2,
                 1.0f / (scale * scale), d_ids, d_dist, st, st + 1, st + 2};
   k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, 0, s>>>(ra);
   HIPTRY(hipGetLastError(), "pp rerank");

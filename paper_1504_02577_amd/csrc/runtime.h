@@ -35,7 +35,7 @@ struct PPState {
 // over the same read-only graph, paths, index and features.
 struct Lane {
   BatchState* batch = nullptr;
-  DevBuf b_qlen, b_pool, b_out, b_stats, b_q;
+  DevBuf b_qlen, b_pool, b_out, b_stats, b_q, b_qrows;
   PinnedBuf h_qlen;  // path-list lengths of the last call's queries
   bool have_stats = false;
   double max_rel_err = 0.0;

@@ -142,6 +142,20 @@ def rmat_graph(scale: int, edge_factor: int = 16, a: float = 0.57,
     return _csr_from_undirected(n, u, v, w, f"rmat{scale}")
 
 
+def permuted_copy(g: Graph, seed: int):
+    """An isomorphic copy of g with vertex ids permuted: vertex v of g is
+    perm[v] of the copy, and every edge keeps its weight.  Returns (copy,
+    perm)."""
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(g.n).astype(np.int32)
+    deg = np.diff(g.row_ptr.astype(np.int64))
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    keep = src < g.col  # each undirected pair once; pairs stay distinct under perm
+    u = perm[src[keep]].astype(np.int64)
+    v = perm[g.col[keep]].astype(np.int64)
+    return _csr_from_undirected(g.n, u, v, g.w[keep], g.name + "_perm"), perm
+
+
 def start_vertices(g: Graph) -> np.ndarray:
     """Vertices with at least one incident edge of positive weight."""
     rp = g.row_ptr.astype(np.int64)

@@ -36,6 +36,7 @@ PANTHER_PP_BF16 = 1
 EXPORTS = [
     "panther_create", "panther_destroy", "panther_last_error", "panther_load_graph",
     "panther_sample_paths", "panther_topk_similar", "panther_topk_all", "panther_pp_topk",
+    "panther_pp_topk_cross",
     "panther_sample_size", "panther_set_option", "panther_get_paths", "panther_index_nnz",
     "panther_get_index", "panther_get_features", "panther_pp_stats", "panther_synchronize",
     "panther_stage_times", "panther_server_start", "panther_server_submit",
@@ -87,6 +88,7 @@ def lib():
         "panther_topk_similar": (ctypes.c_int, [P, P, i64, i32, P, P, P, ctypes.c_int, P]),
         "panther_pp_topk": (ctypes.c_int, [P, P, i64, i32, i32, P, P, ctypes.c_int, P]),
         "panther_topk_all": (ctypes.c_int, [P, i32, P, P, P, ctypes.c_int, P]),
+        "panther_pp_topk_cross": (ctypes.c_int, [P, P, P, i64, i32, i32, P, P, ctypes.c_int, P]),
         "panther_sample_size": (i64, [dbl, dbl, dbl, i32]),
         "panther_set_option": (ctypes.c_int, [P, ctypes.c_char_p, i64]),
         "panther_get_paths": (ctypes.c_int, [P, P, ctypes.c_int]),
@@ -141,6 +143,11 @@ def panther_sample_paths(ctx, T, R, seed):
 def panther_topk_similar(ctx, queries, nq, k, out_ids, out_counts, out_len, mem, stream=None):
     return lib().panther_topk_similar(ctx, queries, nq, k, out_ids, out_counts, out_len, mem,
                                       stream)
+
+
+def panther_pp_topk_cross(qctx, dbctx, queries, nq, D, k, out_ids, out_dist, mem, stream=None):
+    return lib().panther_pp_topk_cross(qctx, dbctx, queries, nq, D, k, out_ids, out_dist, mem,
+                                       stream)
 
 
 def panther_topk_all(ctx, k, out_ids, out_counts, out_len, mem, stream=None):
@@ -334,6 +341,19 @@ class Panther:
             self.h, qp, int(queries.shape[0]), k, _buf(ids, np.int32)[0],
             _buf(cnt, np.uint32)[0], _buf(ln, np.int32)[0], PANTHER_MEM_DEVICE, stream))
         return out
+
+    def pp_topk_cross(self, db, queries, D, k):
+        """Panther++ of this context's vertices `queries` against every vertex
+        of the context `db` (another graph); host numpy (ids, dist)."""
+        q = np.ascontiguousarray(queries, np.int32)
+        nq = q.shape[0]
+        ids = np.empty((nq, k), np.int32)
+        dist = np.empty((nq, k), np.float64)
+        st = panther_pp_topk_cross(self.h, db.h, q.ctypes.data_as(ctypes.c_void_p), nq, D, k,
+                                   ids.ctypes.data_as(ctypes.c_void_p),
+                                   dist.ctypes.data_as(ctypes.c_void_p), PANTHER_MEM_HOST, None)
+        db._check(st)
+        return ids, dist
 
     def topk_all(self, n, k, out=None, stream=None):
         """Top-k of every vertex 0..n-1: host numpy (ids, counts, len), or into

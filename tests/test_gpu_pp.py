@@ -139,3 +139,66 @@ def test_pp_errors_and_device_buffers(P, oracle, ba):
     P.pp_topk(dq, 50, 10, out=out, stream=torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     check_knn(out[0].cpu().numpy(), out[1].cpu().numpy(), wi, wd, "device")
+
+
+@pytest.fixture(scope="module")
+def two_copies(oracle, inputs):
+    g = inputs.ba_graph(1000, 5)
+    gb, perm = inputs.permuted_copy(g, 4)
+    R = 400_000
+    pa = oracle.walk(g, 5, R, 1)
+    pb = oracle.walk(gb, 5, R, 2)
+    ta = oracle.features(g.n, pa, *oracle.index(g.n, pa), 20)
+    tb = oracle.features(gb.n, pb, *oracle.index(gb.n, pb), 20)
+    return g, gb, perm, R, ta, tb
+
+
+@pytest.mark.parametrize("form", [0, 1])
+@pytest.mark.parametrize("k", [1, 10, 64])
+def test_knn_cross_graph(P, oracle, two_copies, form, k):
+    """Queries from one graph against every vertex of a permuted copy, each
+    with its own paths: FP64 form bit-exact, BF16 form within 1e-9."""
+    from paper_1504_02577_amd.panther import Panther
+
+    g, gb, perm, R, ta, tb = two_copies
+    _say(f"case: cross-graph knn form={form} k={k}")
+    P.load_graph(g)
+    P.sample_paths(5, R, 1)
+    B = Panther(0)
+    try:
+        B.load_graph(gb)
+        B.sample_paths(5, R, 2)
+        B.set_option("pp.form", form)
+        q = np.arange(0, g.n, 5, dtype=np.int32)
+        wi, wd = oracle.knn_cross(ta[q], tb, k)
+        gi, gd = P.pp_topk_cross(B, q, 20, k)
+        check_knn(gi, gd, wi, wd, f"cross form={form} k={k}", exact_ids=(form == 0))
+        if k == 10:
+            rate = np.mean([perm[x] in gi[i] for i, x in enumerate(q)])
+            _say(f"  twin in top-10: {rate:.3f}")
+    finally:
+        B.close()
+
+
+def test_knn_cross_errors(P, oracle, two_copies):
+    from paper_1504_02577_amd.panther import Panther, PantherError
+
+    g, gb, perm, R, ta, tb = two_copies
+    _say("case: cross-graph errors")
+    P.load_graph(g)
+    P.sample_paths(5, R, 1)
+    B = Panther(0)
+    try:
+        with pytest.raises(PantherError):  # no paths on the database side
+            P.pp_topk_cross(B, np.array([0], np.int32), 20, 5)
+        B.load_graph(gb)
+        B.sample_paths(5, R, 2)
+        with pytest.raises(PantherError):  # query outside the query graph
+            P.pp_topk_cross(B, np.array([g.n], np.int32), 20, 5)
+        with pytest.raises(PantherError):  # the same context twice
+            P.pp_topk_cross(P, np.array([0], np.int32), 20, 5)
+        gi, gd = P.pp_topk_cross(B, np.array([3], np.int32), 20, 5)  # still usable
+        wi, wd = oracle.knn_cross(ta[[3]], tb, 5)
+        check_knn(gi, gd, wi, wd, "after errors")
+    finally:
+        B.close()

@@ -116,6 +116,26 @@ def test_knn_cross_reduces_to_single_graph(oracle, ba1k, ba1k_paths):
         assert (cd[i][keep][:k] == sd[i]).all()
 
 
+def test_two_copy_twins(oracle, inputs):
+    """Two copies of one graph with permuted ids, each with its own paths:
+    a vertex's twin in the other copy ranks among its nearest neighbours
+    across the graphs, and more often as R grows (the estimates converge,
+    Theorem 1).  This is the identity-resolution use of Panther++."""
+    g = inputs.ba_graph(1000, 5)
+    gb, perm = inputs.permuted_copy(g, 4)
+    assert gb.m == g.m
+    qs = np.arange(0, g.n, 7, dtype=np.int32)
+    rate = {}
+    for R in (100_000, 400_000):
+        pa = oracle.walk(g, 5, R, 1)
+        pb = oracle.walk(gb, 5, R, 2)
+        ta = oracle.features(g.n, pa, *oracle.index(g.n, pa), 20)
+        tb = oracle.features(gb.n, pb, *oracle.index(gb.n, pb), 20)
+        ids, _ = oracle.knn_cross(ta[qs], tb, 10)
+        rate[R] = np.mean([perm[q] in ids[i] for i, q in enumerate(qs)])
+    assert rate[400_000] >= 0.9 and rate[400_000] > rate[100_000]
+
+
 def test_knn_cross_padding(oracle):
     ids, dist = oracle.knn_cross(np.zeros((1, 3), np.float32), np.ones((2, 3), np.float32), 4)
     assert ids[0].tolist() == [0, 1, -1, -1] and np.isinf(dist[0, 2:]).all()
