@@ -313,6 +313,10 @@ struct BatchState {
   size_t stile_owner_cap = 0;
   int32_t* d_bkt_owner = nullptr;
   size_t bkt_owner_cap = 0;
+  uint64_t* d_bkt_cand0 = nullptr;
+  size_t bkt_cand0_cap = 0;
+  uint32_t* d_redo = nullptr;
+  size_t redo_cap = 0;
   uint32_t* d_cand_n = nullptr;
   size_t cand_n_cap = 0;
   char* d_scan = nullptr;
@@ -384,7 +388,8 @@ void free_batch_state(Lane* lane) {
   for (void* p : {(void*)b->d_hq, (void*)b->d_stA, (void*)b->d_stB, (void*)b->d_bkt_cnt,
                   (void*)b->d_bkt_fill, (void*)b->d_bkt_start, (void*)b->d_cand,
                   (void*)b->d_cand_n, (void*)b->d_scan, (void*)b->d_hx,
-                  (void*)b->d_tile_owner, (void*)b->d_stile_owner, (void*)b->d_bkt_owner})
+                  (void*)b->d_tile_owner, (void*)b->d_stile_owner, (void*)b->d_bkt_owner,
+                  (void*)b->d_bkt_cand0, (void*)b->d_redo})
     ctx_free(p);
   delete b;
   lane->batch = nullptr;
@@ -673,6 +678,10 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     return st;
   if ((st = grow(c, b->d_bkt_owner, b->bkt_owner_cap, max_bkt, sizeof(int32_t), "hub maps")))
     return st;
+  if ((st = grow(c, b->d_bkt_cand0, b->bkt_cand0_cap, max_bkt, sizeof(uint64_t), "hub maps")))
+    return st;
+  if ((st = grow(c, b->d_redo, b->redo_cap, max_bkt + 16, sizeof(uint32_t), "hub maps")))
+    return st;
   if ((st = pinned_ensure(c, b->pin_hq, sizeof(HubQuery) * b->h_hq.size(), "hub plan")))
     return st;
   std::memcpy(b->pin_hq.p, b->h_hq.data(), sizeof(HubQuery) * b->h_hq.size());
@@ -691,6 +700,9 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     h.tile_owner = b->d_tile_owner;
     h.stile_owner = b->d_stile_owner;
     h.bkt_owner = b->d_bkt_owner;
+    h.bkt_cand0 = b->d_bkt_cand0;
+    h.redo = b->d_redo;
+    h.redo_n = b->d_redo + max_bkt;
     h.nq = (int32_t)ch.nq;
     h.T = c->T;
     h.k = k;

@@ -44,6 +44,9 @@ struct HubArgs {
   int32_t* tile_owner;   // [n_tiles] gather tile -> query of the chunk
   int32_t* stile_owner;  // [n_stiles] bucketing tile -> query
   int32_t* bkt_owner;    // [n_bkt] bucket -> query
+  uint64_t* bkt_cand0;   // [n_bkt] the owner's first winner slot
+  uint32_t* redo;        // [n_bkt] buckets left to the rare count path
+  uint32_t* redo_n;      // their number
   int32_t nq;
   int32_t T;
   int32_t k;

@@ -47,6 +47,7 @@ constexpr int kTable = 2 * kBucketTarget;  // LDS hash entries of the count step
 constexpr int kTableBits = 12;
 constexpr int kProbes = 32;                // bounded probe sequence
 constexpr int kFitBits = kTableBits - 1;   // log2(kTable / 2)
+constexpr uint32_t kRareGrid = 256;        // work-groups of the rare count path
 static_assert(kTable == 1 << kTableBits, "table size");
 
 __device__ __forceinline__ uint32_t vhash(int32_t v) { return (uint32_t)v * 0x9E3779B1u; }
@@ -86,9 +87,11 @@ __global__ void __launch_bounds__(256) k_hub_prep(HubArgs A) {
   for (uint32_t t = Q.stile0 + threadIdx.x; t < s1; t += 256) A.stile_owner[t] = j;
   for (uint32_t b = threadIdx.x; b < nb; b += 256) {
     A.bkt_owner[Q.bkt0 + b] = j;
+    A.bkt_cand0[Q.bkt0 + b] = Q.cand0;
     A.bkt_cnt[Q.bkt0 + b] = 0u;
     A.bkt_fill[Q.bkt0 + b] = 0u;
   }
+  if (j == 0 && threadIdx.x == 0) *A.redo_n = 0u;
 }
 
 template <int S>
@@ -237,11 +240,22 @@ __device__ __forceinline__ bool table_add(int32_t* keys, uint32_t* vals, int32_t
   return false;
 }
 
+// LDS of the count step's common path: the table and a count histogram.
+struct TableSmem {
+  int32_t keys[kTable];
+  uint32_t vals[kTable];
+  uint32_t ch[256];
+  uint64_t red[32];
+  uint32_t ctl[8];
+};
+
+// LDS of the rare path (buckets the common path hands over): the table,
+// the exact block selection and the running best of the sub-ranges.
 struct CountSmem {
   int32_t keys[kTable];
   uint32_t vals[kTable];  // the two arrays are reused as kTable 64-bit keys
   SelectSmem sel;
-  uint64_t run[kOutCap];  // running best of the sub-ranges (split buckets)
+  uint64_t run[kOutCap];
   uint32_t ctl[8];
 };
 
@@ -250,16 +264,16 @@ struct CountSmem {
 // when the table overflowed.  At the finest split (bb + sbits == 32 -
 // kFitBits) at most kTable / 2 distinct ids qualify and the probe sequence
 // is unbounded, so it never fails there.
-__device__ bool count_part(const HubArgs& A, CountSmem& sm, uint64_t s, uint64_t e, int bb,
-                           int sbits, uint32_t sub) {
+__device__ bool count_part(const HubArgs& A, int32_t* keys, uint32_t* vals, uint32_t* ctl,
+                           uint64_t s, uint64_t e, int bb, int sbits, uint32_t sub) {
   const int probes = bb + sbits >= 32 - kFitBits ? kTable : kProbes;
   for (int j = threadIdx.x; j < kTable; j += kCountBlock) {
-    sm.keys[j] = -1;
-    sm.vals[j] = 0u;
+    keys[j] = -1;
+    vals[j] = 0u;
   }
   if (threadIdx.x == 0) {
-    sm.ctl[0] = 0u;
-    sm.ctl[1] = 0u;
+    ctl[0] = 0u;
+    ctl[1] = 0u;
   }
   __syncthreads();
   bool fail = false;
@@ -274,12 +288,12 @@ __device__ bool count_part(const HubArgs& A, CountSmem& sm, uint64_t s, uint64_t
     for (int u = 0; u < kUnroll; ++u) {
       if (x[u] < 0) continue;
       if (sbits > 0 && ((vhash(x[u]) << bb) >> (32 - sbits)) != sub) continue;
-      if (!table_add(sm.keys, sm.vals, x[u], probes)) fail = true;
+      if (!table_add(keys, vals, x[u], probes)) fail = true;
     }
   }
-  if (fail) sm.ctl[1] = 1u;
+  if (fail) ctl[1] = 1u;
   __syncthreads();
-  const bool overflow = sm.ctl[1] != 0u;
+  const bool overflow = ctl[1] != 0u;
   __syncthreads();
   return !overflow;
 }
@@ -318,30 +332,27 @@ __device__ int select_exact(const HubArgs& A, CountSmem& sm) {
 // superset of the bucket's k best, since the ranking puts larger counts
 // first.  Returns false, emitting nothing, when that set exceeds
 // max(k, kEmitCap) entries.
-__device__ bool emit_by_count(const HubArgs& A, CountSmem& sm, int j, const HubQuery& Q) {
+__device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t cand0) {
   constexpr int kBins = 256;  // counts clamped to 255
-  uint32_t* ch = sm.sel.hist;
-  for (int b = threadIdx.x; b < kBins; b += kCountBlock) ch[b] = 0u;
+  for (int b = threadIdx.x; b < kBins; b += kCountBlock) sm.ch[b] = 0u;
   if (threadIdx.x == 0) {
     sm.ctl[2] = 1u;  // threshold count (when there are fewer than k entries)
     sm.ctl[3] = 0u;  // entries at or above it
     sm.ctl[4] = 0u;  // emit cursor
   }
   __syncthreads();
-  uint32_t total_local = 0;
   for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
     if (sm.keys[t] >= 0) {
       const uint32_t c = sm.vals[t];
-      atomicAdd(&ch[c < kBins - 1 ? c : kBins - 1], 1u);
-      ++total_local;
+      atomicAdd(&sm.ch[c < kBins - 1 ? c : kBins - 1], 1u);
     }
   }
   __syncthreads();
   // descending bins, one per thread: the count above a bin by a block scan
   const int bin = kBins - 1 - (int)threadIdx.x;
-  const uint64_t h = bin >= 0 ? (uint64_t)ch[bin] : 0ull;
+  const uint64_t h = bin >= 0 ? (uint64_t)sm.ch[bin] : 0ull;
   uint64_t tot;
-  const uint64_t above = block_exclusive_sum<kCountBlock>(h, sm.sel.red, &tot);
+  const uint64_t above = block_exclusive_sum<kCountBlock>(h, sm.red, &tot);
   const uint64_t k = (uint64_t)A.k;
   if (bin >= 1 && above < k && above + h >= k) {
     sm.ctl[2] = (uint32_t)bin;
@@ -352,10 +363,9 @@ __device__ bool emit_by_count(const HubArgs& A, CountSmem& sm, int j, const HubQ
   const uint32_t n_emit = tot < k ? (uint32_t)tot : sm.ctl[3];
   const uint32_t cap = (uint32_t)(A.k > kEmitCap ? A.k : kEmitCap);
   if (n_emit > cap) return false;  // uniform: every thread read the same words
-  __shared__ uint32_t s_pos;
-  if (threadIdx.x == 0) s_pos = n_emit ? atomicAdd(&A.cand_n[j], n_emit) : 0u;
+  if (threadIdx.x == 0) sm.ctl[5] = n_emit ? atomicAdd(&A.cand_n[j], n_emit) : 0u;
   __syncthreads();
-  uint64_t* dst = A.cand + Q.cand0 + s_pos;
+  uint64_t* dst = A.cand + cand0 + sm.ctl[5];
   for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
     const int32_t key = sm.keys[t];
     if (key >= 0) {
@@ -363,59 +373,78 @@ __device__ bool emit_by_count(const HubArgs& A, CountSmem& sm, int j, const HubQ
       if ((c < kBins - 1 ? c : kBins - 1) >= thr) dst[atomicAdd(&sm.ctl[4], 1u)] = rank_key(c, key);
     }
   }
-  (void)total_local;
   return true;
 }
 
-__global__ void __launch_bounds__(kCountBlock, 2) k_hub_count(HubArgs A) {
-  extern __shared__ __align__(16) char lds[];
-  CountSmem& sm = *reinterpret_cast<CountSmem*>(lds);
+// Common path: one work-group per bucket, a small LDS footprint so that
+// several work-groups share a CU.  A bucket whose table overflows, or whose
+// candidate superset exceeds the emit cap, is handed to k_hub_count_rare.
+__global__ void __launch_bounds__(kCountBlock) k_hub_count(HubArgs A) {
+  __shared__ TableSmem sm;
   const uint32_t g = blockIdx.x;
   const int j = A.bkt_owner[g];
-  const HubQuery Q = A.hq[j];
+  const uint64_t cand0 = A.bkt_cand0[g];
   const uint64_t s = A.bkt_start[g];
   const uint64_t e = A.bkt_start[g + 1];
-  int m;
-  const uint64_t* best = sm.sel.out;
-  if (count_part(A, sm, s, e, Q.bb, 0, 0u)) {
-    if (emit_by_count(A, sm, j, Q)) return;
-    m = select_exact(A, sm);
-  } else {
-    // split by the next hash bits until every part fits
-    m = 0;
-    for (int sbits = 1; sbits <= 32 - kFitBits - Q.bb; ++sbits) {
-      int r = 0;  // keys in sm.run
-      bool ok = true;
-      for (uint32_t sub = 0; sub < (1u << sbits); ++sub) {
-        if (!count_part(A, sm, s, e, Q.bb, sbits, sub)) {
-          ok = false;
+  if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, 0, 0, 0u) && emit_by_count(A, sm, j, cand0))
+    return;
+  if (threadIdx.x == 0) A.redo[atomicAdd(A.redo_n, 1u)] = g;
+}
+
+// Rare path, a fixed grid looping over the handed-over buckets: exact
+// selection, and recounting in hash sub-ranges when the table overflowed.
+__global__ void __launch_bounds__(kCountBlock) k_hub_count_rare(HubArgs A) {
+  extern __shared__ __align__(16) char lds[];
+  CountSmem& sm = *reinterpret_cast<CountSmem*>(lds);
+  const uint32_t nredo = *A.redo_n;
+  for (uint32_t r = blockIdx.x; r < nredo; r += gridDim.x) {
+    const uint32_t g = A.redo[r];
+    const int j = A.bkt_owner[g];
+    const HubQuery Q = A.hq[j];
+    const uint64_t s = A.bkt_start[g];
+    const uint64_t e = A.bkt_start[g + 1];
+    int m;
+    const uint64_t* best = sm.sel.out;
+    if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.bb, 0, 0u)) {
+      m = select_exact(A, sm);
+    } else {
+      // split by the next hash bits until every part fits
+      m = 0;
+      for (int sbits = 1; sbits <= 32 - kFitBits - Q.bb; ++sbits) {
+        int rr = 0;  // keys in sm.run
+        bool ok = true;
+        for (uint32_t sub = 0; sub < (1u << sbits); ++sub) {
+          if (!count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.bb, sbits, sub)) {
+            ok = false;
+            break;
+          }
+          const int mm = select_exact(A, sm);
+          // merge sel.out[0..mm) into run[0..rr): both descending, keep k
+          uint64_t* buf = sm.sel.cand;
+          const int tot = rr + mm;
+          const int P = next_pow2(tot < 2 ? 2 : tot);
+          for (int i = threadIdx.x; i < P; i += kCountBlock)
+            buf[i] = i < rr ? sm.run[i] : (i < tot ? sm.sel.out[i - rr] : 0ull);
+          __syncthreads();
+          block_bitonic_desc<kCountBlock>(buf, P);
+          rr = tot < A.k ? tot : A.k;
+          for (int i = threadIdx.x; i < rr; i += kCountBlock) sm.run[i] = buf[i];
+          __syncthreads();
+        }
+        if (ok) {
+          m = rr;
+          best = sm.run;
           break;
         }
-        const int mm = select_exact(A, sm);
-        // merge sel.out[0..mm) into run[0..r): both descending, keep k
-        uint64_t* buf = sm.sel.cand;
-        const int tot = r + mm;
-        const int P = next_pow2(tot < 2 ? 2 : tot);
-        for (int i = threadIdx.x; i < P; i += kCountBlock)
-          buf[i] = i < r ? sm.run[i] : (i < tot ? sm.sel.out[i - r] : 0ull);
-        __syncthreads();
-        block_bitonic_desc<kCountBlock>(buf, P);
-        r = tot < A.k ? tot : A.k;
-        for (int i = threadIdx.x; i < r; i += kCountBlock) sm.run[i] = buf[i];
-        __syncthreads();
-      }
-      if (ok) {
-        m = r;
-        best = sm.run;
-        break;
       }
     }
+    // the finest split holds at most kTable / 2 distinct ids, so m is set
+    if (threadIdx.x == 0) sm.ctl[5] = m > 0 ? atomicAdd(&A.cand_n[j], (uint32_t)m) : 0u;
+    __syncthreads();
+    const uint32_t pos = sm.ctl[5];
+    for (int i = threadIdx.x; i < m; i += kCountBlock) A.cand[Q.cand0 + pos + i] = best[i];
+    __syncthreads();
   }
-  // the finest split holds at most kTable / 2 distinct ids, so m is set
-  __shared__ uint32_t s_pos;
-  if (threadIdx.x == 0) s_pos = m > 0 ? atomicAdd(&A.cand_n[j], (uint32_t)m) : 0u;
-  __syncthreads();
-  for (int i = threadIdx.x; i < m; i += kCountBlock) A.cand[Q.cand0 + s_pos + i] = best[i];
 }
 
 __global__ void __launch_bounds__(kCountBlock) k_hub_merge(HubArgs A) {
@@ -472,13 +501,15 @@ hipError_t enqueue_hub_chunk(const HubArgs& A, int stride, void* scan_temp, hipS
   k_hub_hist<<<A.n_stiles, kGatherBlock, 0, s>>>(A);
   launch_scan_u32_to_u64(A.bkt_cnt, A.bkt_start, A.n_bkt, scan_temp, s);
   k_hub_scatter<<<A.n_stiles, kGatherBlock, 0, s>>>(A);
-  k_hub_count<<<A.n_bkt, kCountBlock, sizeof(CountSmem), s>>>(A);
+  k_hub_count<<<A.n_bkt, kCountBlock, 0, s>>>(A);
+  k_hub_count_rare<<<A.n_bkt < kRareGrid ? A.n_bkt : kRareGrid, kCountBlock, sizeof(CountSmem),
+                     s>>>(A);
   k_hub_merge<<<(uint32_t)A.nq, kCountBlock, sizeof(SelectSmem), s>>>(A);
   return hipGetLastError();
 }
 
 hipError_t hub_set_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void*)k_hub_count,
+  hipError_t e = hipFuncSetAttribute((const void*)k_hub_count_rare,
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)sizeof(CountSmem));
   if (e != hipSuccess) return e;
