@@ -82,6 +82,11 @@ k_bf16_query_rows(const float* __restrict__ theta_q, int32_t D, const int32_t* _
   norm[i] = acc;
 }
 
+__global__ void k_fill_u64(unsigned long long* a, int64_t n, unsigned long long v) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
 __device__ __forceinline__ uint64_t pool_key(float d2, int32_t v) {
   const float c = d2 > 0.f ? d2 : 0.f;
   return ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)v;
@@ -111,6 +116,71 @@ __device__ void wave_sort_keys(uint64_t* a, int cnt) {
   }
 }
 
+// The P smallest of the c > P distinct keys a[0..c) by one wavefront: an
+// MSD radix select (8-bit digits, histogram in `hist`, 256 words) finds the
+// P-th smallest key T, then a[0..P) is compacted in place to the keys <= T
+// (in input order).  Returns T.
+__device__ uint64_t wave_select_cut(uint64_t* a, int c, int P, uint32_t* hist) {
+  const int lane = threadIdx.x & (kWave - 1);
+  uint64_t prefix = 0;  // digits fixed so far
+  int need = P;         // rank of T within the current class (1-based)
+  for (int shift = 56; shift >= 0; shift -= 8) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) hist[lane * 4 + b] = 0u;
+    wsync();
+    const uint64_t hi_mask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+    for (int i = lane; i < c; i += kWave) {
+      const uint64_t x = a[i];
+      if ((x & hi_mask) == prefix) atomicAdd(&hist[(uint32_t)(x >> shift) & 255u], 1u);
+    }
+    wsync();
+    // lane l owns digits 4l .. 4l+3; the digit where the running count
+    // reaches `need` holds T
+    uint32_t h[4], sum = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      h[b] = hist[lane * 4 + b];
+      sum += h[b];
+    }
+    uint32_t inc = sum;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t y = __shfl_up(inc, off, kWave);
+      if (lane >= off) inc += y;
+    }
+    uint32_t below = inc - sum;
+    int dsel = -1;
+    uint32_t below_sel = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (dsel < 0 && below < (uint32_t)need && below + h[b] >= (uint32_t)need) {
+        dsel = lane * 4 + b;
+        below_sel = below;
+      }
+      below += h[b];
+    }
+    const uint64_t m = __ballot(dsel >= 0);
+    const int src = __ffsll((long long)m) - 1;
+    const int d = __shfl(dsel, src, kWave);
+    need -= (int)__shfl(below_sel, src, kWave);
+    prefix |= (uint64_t)d << shift;
+    wsync();
+  }
+  const uint64_t T = prefix;
+  // in-place compaction: a position is written only after it was read
+  int base = 0;
+  for (int i0 = 0; i0 < c; i0 += kWave) {
+    const int i = i0 + lane;
+    const uint64_t x = i < c ? a[i] : ~0ull;
+    const bool keep = i < c && x <= T;
+    const uint64_t bm = __ballot(keep);
+    if (keep) a[base + __popcll(bm & ((1ull << lane) - 1ull))] = x;
+    base += __popcll(bm);
+    wsync();
+  }
+  return T;
+}
+
 struct PoolArgs {
   const __bf16* rows;    // [n][64]
   const float* norm;     // [n]
@@ -132,6 +202,10 @@ struct PoolArgs {
   const float* qnorm;
   int32_t q_by_pos;
   int32_t exclude_self;  // single graph: the query's own row is no candidate
+  // slices > 1: per query, the smallest P-th best key any slice has
+  // reached so far -- an upper bound on the query's P-th best key overall,
+  // so every slice may drop keys at or above it
+  unsigned long long* gtau;
 };
 
 // grid (query tiles, database slices)
@@ -143,6 +217,7 @@ k_pp_pool(PoolArgs A) {
   __shared__ int32_t qid[kQW];
   __shared__ float qn_s[kQW];
   extern __shared__ __align__(16) uint64_t sortmem[];  // [waves][cap]
+  __shared__ uint32_t s_hist[kBlock / kWave][256];     // per-wave radix select
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t q0 = (int64_t)blockIdx.x * kQW;
   const int slice = blockIdx.y;
@@ -229,6 +304,19 @@ k_pp_pool(PoolArgs A) {
     if (++chunk_no % check_every != 0 && cb + kChunk < r1) continue;
     __threadfence_block();
     __syncthreads();
+    // adopt the other slices' bound where it is tighter (one load per query)
+    if (A.gtau) {
+      for (int ql = threadIdx.x; ql < kQW; ql += kBlock) {
+        if (qid[ql] < 0) continue;
+        const unsigned long long gb =
+            __hip_atomic_load(&A.gtau[q0 + ql], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (gb < tau[ql]) {
+          tau[ql] = gb;
+          tauf_s[ql] = __uint_as_float((uint32_t)(gb >> 32));
+        }
+      }
+      __syncthreads();
+    }
     // cut back buffers that the next check_every chunks could overflow
     for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
       const int c = (int)cnt[ql];
@@ -238,12 +326,15 @@ k_pp_pool(PoolArgs A) {
         for (int i = lane; i < c; i += kWave)
           sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wsync();
-        wave_sort_keys(sb, c);
+        const uint64_t T = wave_select_cut(sb, c, P, s_hist[wid]);
         for (int i = lane; i < P; i += kWave) g[i] = sb[i];
         if (lane == 0) {
           cnt[ql] = (uint32_t)P;
-          tau[ql] = sb[P - 1];
-          tauf_s[ql] = __uint_as_float((uint32_t)(sb[P - 1] >> 32));
+          if (T < tau[ql]) {
+            tau[ql] = T;
+            tauf_s[ql] = __uint_as_float((uint32_t)(T >> 32));
+          }
+          if (A.gtau && qid[ql] >= 0) atomicMin(&A.gtau[q0 + ql], (unsigned long long)tau[ql]);
         }
         wsync();
       }
@@ -260,7 +351,12 @@ k_pp_pool(PoolArgs A) {
     for (int i = lane; i < c; i += kWave)
       sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     wsync();
-    wave_sort_keys(sb, c);
+    // one slice: the pool in ascending key order; several: the slice's P
+    // best in any order (the merge selects across slices)
+    if (A.slices == 1)
+      wave_sort_keys(sb, c);
+    else if (c > P)
+      (void)wave_select_cut(sb, c, P, s_hist[wid]);
     const int m = c < P ? c : P;
     if (A.slices == 1) {
       for (int i = lane; i < P; i += kWave) {
@@ -269,7 +365,7 @@ k_pp_pool(PoolArgs A) {
         A.pool_d2[(q0 + ql) * P + i] = ok ? __uint_as_float((uint32_t)(sb[i] >> 32)) : INFINITY;
       }
     } else {
-      // fixed-length slice pools, padded with the largest key
+      // fixed-length slice pools (unordered), padded with the largest key
       uint64_t* o = A.part + ((q0 + ql) * A.slices + slice) * P;
       for (int i = lane; i < P; i += kWave) o[i] = i < m ? sb[i] : ~0ull;
     }
@@ -451,12 +547,16 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
   const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;
   const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
-  TRY(ctx_ensure(c, lane->b_pool, buf_bytes + part_bytes + ids_bytes + 256, "pools"));
+  const size_t gtau_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq : 0;
+  TRY(ctx_ensure(c, lane->b_pool, buf_bytes + part_bytes + gtau_bytes + ids_bytes + 256,
+                 "pools"));
   TRY(ctx_ensure(c, lane->b_stats, 64, "pp stats"));
   char* base = static_cast<char*>(lane->b_pool.p);
   uint64_t* buf = reinterpret_cast<uint64_t*>(base);
   uint64_t* part = reinterpret_cast<uint64_t*>(base + buf_bytes);
-  int32_t* pool_ids = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes);
+  unsigned long long* gtau =
+      S > 1 ? reinterpret_cast<unsigned long long*>(base + buf_bytes + part_bytes) : nullptr;
+  int32_t* pool_ids = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes + gtau_bytes);
   float* pool_d2 = reinterpret_cast<float*>(pool_ids + (size_t)nq * P);
   HIPTRY(hipMemsetAsync(lane->b_stats.p, 0, 64, s), "pp stats");
   int sort_cap = 2;
@@ -464,7 +564,11 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   PoolArgs pa{static_cast<const __bf16*>(pp->b_bf16.p), static_cast<const float*>(pp->b_norm.p),
               c->n, dq, nq, P, cap, (int32_t)S, (int32_t)rps, sort_cap, buf, part,
               pool_ids, pool_d2, static_cast<const __bf16*>(pp->b_bf16.p),
-              static_cast<const float*>(pp->b_norm.p), 0, 1};
+              static_cast<const float*>(pp->b_norm.p), 0, 1, gtau};
+  if (gtau) {
+    k_fill_u64<<<(unsigned)((nq + kBlock - 1) / kBlock), kBlock, 0, s>>>(gtau, nq, ~0ull);
+    HIPTRY(hipGetLastError(), "pool bounds");
+  }
   if (qtheta) {
     TRY(ctx_ensure(c, lane->b_qrows, (sizeof(__bf16) * kDP + sizeof(float)) * (size_t)nq,
                    "query bf16 rows"));
