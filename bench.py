@@ -15,7 +15,9 @@ Other workloads (one JSON line each, not the headline):
   --workload rmat22_pp  Panther++: features (D=50) and 65,536 kNN queries
                         (k=20) in the BF16 matrix-core form, FP64 form timed
                         on a 1,024-query subset
-  --workload serve      continuous-batching server under Poisson arrivals
+  --workload serve      continuous-batching server under Poisson arrivals on
+                        the R-MAT 24 state (--serve-graph rmat20 for the
+                        smaller one)
   --workload allv       all-vertex top-5 (every vertex of the graph is a
                         query, the paper's Table 2 workload) on --allv-graph
   --workload twocopy    cross-graph Panther++ between R-MAT 20 and a copy
@@ -94,7 +96,7 @@ def main():
                     help="also run one 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=50_000.0)
-    ap.add_argument("--serve-graph", default="rmat20")
+    ap.add_argument("--serve-graph", default="rmat24")
     ap.add_argument("--allv-graph", default="rmat20")
     ap.add_argument("--allv-k", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=0,
