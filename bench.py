@@ -20,6 +20,11 @@ Other workloads (one JSON line each, not the headline):
                         smaller one)
   --workload allv       all-vertex top-5 (every vertex of the graph is a
                         query, the paper's Table 2 workload) on --allv-graph
+  --workload bigR       R-MAT 24 with R from the sample-size bound for
+                        eps = sqrt(1/|E|) (Theorem 1, about 8.6e8 paths, more
+                        than 2^32 index entries): one sampling + index step,
+                        the 10^5-query batch, and a sampled check of paths and
+                        lists against the oracle
   --workload twocopy    cross-graph Panther++ between R-MAT 20 and a copy
                         with permuted ids (each with its own paths): 65,536
                         degree-weighted queries, k=10, D=50, and how often a
@@ -127,6 +132,8 @@ def main():
         return bench_allv(args)
     if args.workload == "twocopy":
         return bench_twocopy(args)
+    if args.workload == "bigR":
+        return bench_bigR(args)
     t0 = time.time()
     g, q, p = inputs.workload(args.workload)
     T, R, seed, k = p["T"], p["R"], p["seed"], p["k"]
@@ -274,6 +281,77 @@ def bench_allv(args):
                                "kind": "oracle",
                                "sample": f"oracle top-{k} of vertices 0..{sample - 1} on the "
                                          f"oracle's own paths and index, {dt1:.2f} s"}
+    P.close()
+    print(json.dumps(res), flush=True)
+
+
+def bench_bigR(args):
+    """Sample-size-driven R at R-MAT 24: R = sample_size(sqrt(1/|E|), 0.5,
+    0.1, T) paths, nnz above 2^32."""
+    import torch
+    import oracle
+    from paper_1504_02577_amd import inputs
+    from paper_1504_02577_amd.panther import Panther, panther_sample_size
+
+    g, q, p = inputs.workload("rmat24")
+    T, seed, k = p["T"], p["seed"], p["k"]
+    E = g.m // 2
+    R = int(panther_sample_size(math.sqrt(1.0 / E), 0.5, 0.1, T))
+    log(f"bigR: |E| = {E}, R = {R}")
+    P = Panther(0)
+    P.load_graph(g)
+    P.set_option("timing", 1)
+    steps = max(1, args.steps)
+    stage = {"walk": [], "index": []}
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.sample_paths(T, R, seed)
+        st = P.stage_times()
+        for kk in stage:
+            stage[kk].append(st[kk])
+    dt = (time.perf_counter() - t0) / steps
+    nnz = P.nnz()
+    dq = torch.from_numpy(q).cuda()
+    out = (torch.empty((len(q), k), dtype=torch.int32, device="cuda"),
+           torch.empty((len(q), k), dtype=torch.uint32, device="cuda"),
+           torch.empty(len(q), dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream().cuda_stream
+    P.topk(dq, k, out=out, stream=stream)
+    torch.cuda.synchronize()
+    tq = time.perf_counter()
+    P.topk(dq, k, out=out, stream=stream)
+    torch.cuda.synchronize()
+    tq = time.perf_counter() - tq
+    # sampled parity: paths of random ids against the oracle's own walk of
+    # those ids; lists of sampled vertices against a scan of all paths
+    oracle.build()
+    rng = np.random.default_rng(17)
+    pids = np.sort(rng.integers(0, R, 4096))
+    want = oracle.walk_pids(g, T, seed, pids)
+    paths = P.paths_device()
+    got = paths[torch.from_numpy(pids).cuda()].cpu().numpy()
+    paths_ok = bool((got == want).all())
+    ptr, pid = P.index_device(g.n)
+    vs = np.concatenate([q[:4], rng.integers(0, g.n, 4)]).astype(np.int64)
+    lists_ok = True
+    for v in vs.tolist():
+        a, b = int(ptr[v]), int(ptr[v + 1])
+        lst = pid[a:b].to(torch.int64)
+        has = (paths == v).any(1)
+        lists_ok &= int(has.sum()) == b - a
+        if b > a:
+            lists_ok &= bool((lst[1:] > lst[:-1]).all()) and bool(has[lst].all())
+    del paths, ptr, pid
+    res = {"metric": "path-steps/s", "value": R * T / dt, "unit": "path-steps/s", "n_gpus": 1,
+           "steps": steps, "warmup": 0, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+           "config": {"workload": f"bigR: R-MAT 24, R = {R} from the sample-size bound with "
+                                  f"eps = sqrt(1/|E|), |E| = {E}, T={T}; step = sampling + index",
+                      "parallelism": "single GPU"},
+           "stage_ms": {kk: float(np.mean(v)) for kk, v in stage.items()}, "nnz": int(nnz),
+           "topk_batched_ms": tq * 1e3, "topk_queries": len(q),
+           "sampled_paths_equal_oracle": paths_ok, "sampled_lists_valid": bool(lists_ok),
+           "roofline": None}
     P.close()
     print(json.dumps(res), flush=True)
 

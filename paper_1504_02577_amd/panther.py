@@ -398,6 +398,27 @@ class Panther:
                                       PANTHER_MEM_HOST))
         return out
 
+    def paths_device(self):
+        """The paths as a device tensor int32[R][T+1]."""
+        import torch
+
+        T, R = self._TR
+        out = torch.empty((R, T + 1), dtype=torch.int32, device="cuda")
+        self._check(panther_get_paths(self.h, ctypes.c_void_p(out.data_ptr()), PANTHER_MEM_DEVICE))
+        return out
+
+    def index_device(self, n):
+        """The inverted index as device tensors (int64[n+1], int32 view of
+        uint32[nnz])."""
+        import torch
+
+        nnz = self.nnz()
+        ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+        pid = torch.empty(max(nnz, 1), dtype=torch.int32, device="cuda")
+        self._check(panther_get_index(self.h, ctypes.c_void_p(ptr.data_ptr()),
+                                      ctypes.c_void_p(pid.data_ptr()), PANTHER_MEM_DEVICE))
+        return ptr, pid[:nnz]
+
     def nnz(self):
         v = panther_index_nnz(self.h)
         if v < 0:
