@@ -435,6 +435,7 @@ def bench_pp(args):
         times.append(time.perf_counter() - t)
     pp_ms = P.stage_times()["pp"]
     err, rec = P.pp_stats()
+    cert_nq, cert_redo = P.pp_certified()
     bf16_ids = out[0].cpu().numpy()
     sub = q[:1024]
     P.set_option("pp.form", 0)
@@ -454,6 +455,7 @@ def bench_pp(args):
                                f"D={D}, {len(q)} queries, k={k}, pool {p['pool']}"},
         "features_ms": feat_ms, "pp_kernels_ms": pp_ms,
         "pre_rerank_recall": rec, "bf16_max_rel_err": err,
+        "certified_queries": cert_nq - cert_redo, "recomputed_exactly": cert_redo,
         "fp64_form_queries_per_s": len(sub) / fp64_s,
         "fp64_vs_bf16_id_agreement_1024": agree,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",

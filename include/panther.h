@@ -146,7 +146,10 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * LDS-derived default; longer lists go to the split hub pipeline),
  * "batch.hub_bits" (largest log2 bucket count per hub query, 0..12, -1 =
  * 12; smaller values make buckets overflow their LDS table and take the
- * sub-range path, for tests), "test.fail_alloc_after" (the next n device allocations
+ * sub-range path, for tests), "test.pp_recompute_all" (0..2, default 0;
+ * 1: the BF16 form recomputes every query whose pool is full by the exact
+ * path, certified or not; 2: also overflows every candidate list so that
+ * the full brute force runs; for tests), "test.fail_alloc_after" (the next n device allocations
  * succeed, the one after fails with ENOMEM; -1 disables).
  * Errors: EINVAL (unknown key or value out of range). */
 int panther_set_option(panther_ctx *ctx, const char *key, int64_t value);
@@ -201,6 +204,19 @@ int panther_pp_topk_cross(panther_ctx *qctx, panther_ctx *dbctx,
  * returned neighbours (*max_rel_err).  ESTATE if no such call. */
 int panther_pp_stats(panther_ctx *ctx, double *max_rel_err,
                      double *mean_pre_recall);
+
+/* Certificate of the last BF16-form call (single- or cross-graph): every
+ * vertex outside a query's candidate pool has a BF16 distance at least the
+ * pool's largest, and the BF16 distance differs from the exact one by at
+ * most a bound from the rounding of the bfloat16 rows (2^-8 relative per
+ * coordinate) and of the FP32 evaluation; when the pool's largest minus
+ * that bound exceeds the k-th exact distance the result is certified
+ * exact, otherwise the query is recomputed by the exact FP64 brute force.
+ * Either way the returned neighbours equal the FP64 form's.  *queries gets
+ * the call's query count, *recomputed how many were recomputed.
+ * ESTATE if no such call. */
+int panther_pp_certified(panther_ctx *ctx, int64_t *queries,
+                         int64_t *recomputed);
 
 /* Device time of the stages of the most recent calls, in milliseconds,
  * measured with HIP events on the stream each stage ran on, when the

@@ -17,6 +17,7 @@
 // more than kp entries is bitonic-sorted by one wavefront and cut back to
 // kp, which tightens the threshold.  A round adds at most 256 entries, so a
 // 512-entry buffer never overflows for kp <= 256.
+#include <algorithm>
 #include <cmath>
 
 #include "common.h"
@@ -72,7 +73,8 @@ template <int QT>
 __global__ void __launch_bounds__(kBlock)
 k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
            const float* __restrict__ qtheta, int32_t exclude_self,
-           const int32_t* __restrict__ queries, int64_t nq, int32_t k, int32_t kp,
+           const int32_t* __restrict__ queries, const int32_t* __restrict__ rows, int64_t nq,
+           int32_t k, int32_t kp,
            int32_t* __restrict__ out_ids, double* __restrict__ out_dist) {
   extern __shared__ __align__(16) char lds[];
   double* qv = reinterpret_cast<double*>(lds);      // [QT][D]
@@ -85,7 +87,7 @@ k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t q0 = (int64_t)blockIdx.x * QT;
   for (int i = threadIdx.x; i < QT; i += kBlock) {
-    qid[i] = (q0 + i < nq) ? queries[q0 + i] : -1;
+    qid[i] = (q0 + i < nq) ? queries[rows ? rows[q0 + i] : q0 + i] : -1;
     cnt[i] = 0u;
     tau_d[i] = INFINITY;
     tau_v[i] = 0x7FFFFFFF;
@@ -140,7 +142,7 @@ k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
     if (qid[q] < 0) continue;
     const int c = (int)cnt[q];
     wave_sort_pairs(bd + q * kBuf, bv + q * kBuf, c);
-    const int64_t qi = q0 + q;
+    const int64_t qi = rows ? (int64_t)rows[q0 + q] : q0 + q;
     for (int j = lane; j < k; j += kWave) {
       const bool ok = j < c;
       out_ids[qi * k + j] = ok ? bv[q * kBuf + j] : -1;
@@ -150,7 +152,180 @@ k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
   }
 }
 
+// Exact candidates of queries whose approximate search is not certified.
+// Query i (queries[rows[i]]) keeps every row v whose pair (d2, v) is at most
+// its bound (tau_d[i], tau_v[i]) -- the k-th exact pair among rows already
+// found, so the true top k is a subset.  A work-group takes QF queries and
+// one slice of rows; survivors are appended to the query's list (cap
+// entries; cand_n counts all of them, so a count above cap marks overflow).
+template <int QF>
+__global__ void __launch_bounds__(kBlock)
+k_knn_range(const float* __restrict__ theta, int32_t n, int32_t D,
+            const float* __restrict__ qtheta, int32_t exclude_self,
+            const int32_t* __restrict__ queries, const int32_t* __restrict__ rows, int64_t nr,
+            const double* __restrict__ tau_d, const int32_t* __restrict__ tau_v,
+            int64_t rows_per_wg, uint32_t cap, double* __restrict__ cand_d,
+            int32_t* __restrict__ cand_v, unsigned int* __restrict__ cand_n) {
+  extern __shared__ __align__(16) char lds[];
+  double* qv = reinterpret_cast<double*>(lds);  // [QF][D]
+  __shared__ double td[QF];
+  __shared__ int32_t tv[QF], qid[QF];
+  const int64_t i0 = (int64_t)blockIdx.x * QF;
+  for (int i = threadIdx.x; i < QF; i += kBlock) {
+    const bool ok = i0 + i < nr;
+    qid[i] = ok ? queries[rows[i0 + i]] : -1;
+    td[i] = ok ? tau_d[i0 + i] : -1.0;
+    tv[i] = ok ? tau_v[i0 + i] : -1;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < QF * D; i += kBlock) {
+    const int32_t q = qid[i / D];
+    qv[i] = q >= 0 ? (double)qtheta[(int64_t)q * D + (i % D)] : 0.0;
+  }
+  __syncthreads();
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_wg;
+  const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
+  for (int64_t v = r0 + threadIdx.x; v < r1; v += kBlock) {
+    double acc[QF];
+#pragma unroll
+    for (int q = 0; q < QF; ++q) acc[q] = 0.0;
+    const float* row = theta + v * D;
+    for (int d = 0; d < D; ++d) {
+      const double x = (double)row[d];
+#pragma unroll
+      for (int q = 0; q < QF; ++q) {
+        const double delta = qv[q * D + d] - x;
+        acc[q] = fma(delta, delta, acc[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < QF; ++q) {
+      const int32_t me = qid[q];
+      if (me >= 0 && (!exclude_self || (int32_t)v != me) &&
+          (acc[q] < td[q] || (acc[q] == td[q] && (int32_t)v <= tv[q]))) {
+        const unsigned pos = atomicAdd(&cand_n[i0 + q], 1u);
+        if (pos < cap) {
+          cand_d[(i0 + q) * cap + pos] = acc[q];
+          cand_v[(i0 + q) * cap + pos] = (int32_t)v;
+        }
+      }
+    }
+  }
+}
+
+constexpr int kSelCap = 4096;
+
+// One work-group per listed query: sort its candidates by (d2, id) and
+// write the first k to output row rows[i].  A list that overflowed is left
+// alone and its index is appended to ov_list.
+__global__ void __launch_bounds__(kBlock)
+k_knn_cand_select(const int32_t* __restrict__ rows, const double* __restrict__ cand_d,
+                  const int32_t* __restrict__ cand_v, const unsigned int* __restrict__ cand_n,
+                  uint32_t cap, int32_t k, int32_t* __restrict__ out_ids,
+                  double* __restrict__ out_dist, int32_t* __restrict__ ov_list,
+                  unsigned long long* __restrict__ ov_n) {
+  __shared__ double sd[kSelCap];
+  __shared__ int32_t sv[kSelCap];
+  const int64_t i = blockIdx.x;
+  const unsigned c = cand_n[i];
+  const int64_t qi = rows[i];
+  if (c > cap) {
+    if (threadIdx.x == 0) ov_list[atomicAdd(ov_n, 1ull)] = (int32_t)qi;
+    return;
+  }
+  int P = 2;
+  while (P < (int)c) P <<= 1;
+  for (int j = threadIdx.x; j < P; j += kBlock) {
+    const bool ok = j < (int)c;
+    sd[j] = ok ? cand_d[i * cap + j] : INFINITY;
+    sv[j] = ok ? cand_v[i * cap + j] : 0x7FFFFFFF;
+  }
+  __syncthreads();
+  for (int size = 2; size <= P; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int j = threadIdx.x; j < (P >> 1); j += kBlock) {
+        const int lo = ((j & ~(stride - 1)) << 1) | (j & (stride - 1));  // stride: power of two
+        const int hi = lo + stride;
+        const bool asc = (lo & size) == 0;
+        const double a = sd[lo], b = sd[hi];
+        const int32_t x = sv[lo], y = sv[hi];
+        if (pair_less(b, y, a, x) == asc) {
+          sd[lo] = b;
+          sd[hi] = a;
+          sv[lo] = y;
+          sv[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int j = threadIdx.x; j < k; j += kBlock) {
+    const bool ok = j < (int)c;
+    out_ids[qi * k + j] = ok ? sv[j] : -1;
+    out_dist[qi * k + j] = ok ? sqrt(sd[j]) : INFINITY;
+  }
+}
+
 }  // namespace
+
+int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const float* qtheta,
+                    bool exclude_self, const int32_t* queries, const int32_t* rows, int64_t nq,
+                    int32_t k, int32_t* out_ids, double* out_dist, hipStream_t s);
+
+size_t knn_range_bytes(int64_t nr) {
+  return (sizeof(double) + sizeof(int32_t)) * (size_t)nr * kSelCap + sizeof(unsigned) * nr +
+         sizeof(int32_t) * nr + 256;
+}
+
+// Exact recompute of listed queries from a known bound: rows[i] (i < nr)
+// names the output row of query queries[rows[i]], and (tau_d[i], tau_v[i])
+// is an exact (d2, id) pair that at least k rows reach.  work: device
+// memory of knn_range_bytes(nr) bytes.  A list keeps up to
+// min(cap, 4096) candidates; lists that outgrow it are recomputed by the
+// full brute force (one host synchronisation).
+int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* qtheta,
+                         bool exclude_self, const int32_t* queries, const int32_t* rows,
+                         int64_t nr, const double* tau_d, const int32_t* tau_v, int32_t k,
+                         int num_cus, void* work, unsigned long long* ov_n_dev,
+                         int32_t* out_ids, double* out_dist, hipStream_t s, uint32_t cap) {
+  cap = std::min<uint32_t>(cap, kSelCap);
+  constexpr int QF = 8;
+  if (nr <= 0) return 0;
+  char* w = static_cast<char*>(work);
+  double* cand_d = reinterpret_cast<double*>(w);
+  int32_t* cand_v = reinterpret_cast<int32_t*>(cand_d + (size_t)nr * kSelCap);
+  unsigned* cand_n = reinterpret_cast<unsigned*>(cand_v + (size_t)nr * kSelCap);
+  int32_t* ov_list = reinterpret_cast<int32_t*>(cand_n + nr);
+  hipError_t e = hipMemsetAsync(cand_n, 0, sizeof(unsigned) * nr, s);
+  if (e != hipSuccess) return (int)e;
+  e = hipMemsetAsync(ov_n_dev, 0, sizeof(unsigned long long), s);
+  if (e != hipSuccess) return (int)e;
+  const int64_t gx = (nr + QF - 1) / QF;
+  int64_t gy = std::max<int64_t>(1, (4 * (int64_t)num_cus + gx - 1) / gx);
+  gy = std::min<int64_t>(gy, std::max<int64_t>(1, ((int64_t)n + 4 * kBlock - 1) / (4 * kBlock)));
+  const int64_t rpw = ((int64_t)n + gy - 1) / gy;
+  const size_t lds = sizeof(double) * QF * D;
+  e = hipFuncSetAttribute((const void*)k_knn_range<QF>,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return (int)e;
+  k_knn_range<QF><<<dim3((unsigned)gx, (unsigned)gy), kBlock, lds, s>>>(
+      theta, n, D, qtheta, exclude_self ? 1 : 0, queries, rows, nr, tau_d, tau_v, rpw,
+      cap, cand_d, cand_v, cand_n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  k_knn_cand_select<<<(unsigned)nr, kBlock, 0, s>>>(rows, cand_d, cand_v, cand_n, cap, k,
+                                                   out_ids, out_dist, ov_list, ov_n_dev);
+  e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  unsigned long long ov = 0;
+  e = hipMemcpyAsync(&ov, ov_n_dev, sizeof ov, hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return (int)e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return (int)e;
+  if (ov == 0) return 0;
+  return launch_knn_fp64(theta, n, D, qtheta, exclude_self, queries, ov_list, (int64_t)ov, k,
+                         out_ids, out_dist, s);
+}
 
 size_t knn_fp64_lds(int D) {
   constexpr int QT = 16;
@@ -159,10 +334,12 @@ size_t knn_fp64_lds(int D) {
 }
 
 // qtheta: the queries' feature rows (theta itself for one graph, the other
-// graph's for the cross-graph form, which excludes no row).
+// graph's for the cross-graph form, which excludes no row).  rows (may be
+// null): the call answers queries[rows[i]] into output row rows[i] for
+// i < nq, instead of queries[i] into row i.
 int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const float* qtheta,
-                    bool exclude_self, const int32_t* queries, int64_t nq, int32_t k,
-                    int32_t* out_ids, double* out_dist, hipStream_t s) {
+                    bool exclude_self, const int32_t* queries, const int32_t* rows, int64_t nq,
+                    int32_t k, int32_t* out_ids, double* out_dist, hipStream_t s) {
   constexpr int QT = 16;
   int kp = 1;
   while (kp < k) kp <<= 1;
@@ -173,7 +350,7 @@ int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const float* qthet
   const unsigned grid = (unsigned)((nq + QT - 1) / QT);
   if (grid)
     k_knn_fp64<QT><<<grid, kBlock, lds, s>>>(theta, n, D, qtheta, exclude_self ? 1 : 0, queries,
-                                              nq, k, kp, out_ids, out_dist);
+                                              rows, nq, k, kp, out_ids, out_dist);
   return (int)hipGetLastError();
 }
 

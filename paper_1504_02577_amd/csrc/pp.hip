@@ -17,8 +17,8 @@ using namespace panther;
 namespace panther {
 size_t knn_fp64_lds(int D);
 int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const float* qtheta,
-                    bool exclude_self, const int32_t* queries, int64_t nq, int32_t k,
-                    int32_t* out_ids, double* out_dist, hipStream_t s);
+                    bool exclude_self, const int32_t* queries, const int32_t* rows, int64_t nq,
+                    int32_t k, int32_t* out_ids, double* out_dist, hipStream_t s);
 int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
                 int32_t* d_ids, double* d_dist, hipStream_t s, const float* qtheta);
 }  // namespace panther
@@ -35,7 +35,8 @@ __global__ void k_iota(int32_t* out, int32_t n) {
 void free_pp_state(panther_ctx* c) {
   c->lane0.have_stats = false;
   if (!c->pp) return;
-  for (DevBuf* b : {&c->pp->b_bf16, &c->pp->b_norm, &c->pp->b_iota}) ctx_release(*b);
+  for (DevBuf* b : {&c->pp->b_bf16, &c->pp->b_norm, &c->pp->b_iota, &c->pp->b_dbmax})
+    ctx_release(*b);
   delete c->pp;
   c->pp = nullptr;
 }
@@ -143,8 +144,8 @@ extern "C" int panther_pp_topk(panther_ctx* c, const int32_t* queries, int64_t n
 int run_pp(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
            int32_t* d_ids, double* d_dist, hipStream_t s) {
   if (c->pp_form == PANTHER_PP_FP64) {
-    const int e = launch_knn_fp64(c->d_theta, c->n, D, c->d_theta, true, dq, nq, k, d_ids, d_dist,
-                                  s);
+    const int e = launch_knn_fp64(c->d_theta, c->n, D, c->d_theta, true, dq, nullptr, nq, k, d_ids,
+                                  d_dist, s);
     HIPTRY((hipError_t)e, "pp fp64 knn");
     return PANTHER_OK;
   }
@@ -209,8 +210,8 @@ extern "C" int panther_pp_topk_cross(panther_ctx* qc, panther_ctx* dbc, const in
   }
   stage_begin(dbc, 4, s);
   if (dbc->pp_form == PANTHER_PP_FP64) {
-    const int e = launch_knn_fp64(dbc->d_theta, dbc->n, D, qc->d_theta, false, dq, nq, k, d_ids,
-                                  d_dist, s);
+    const int e = launch_knn_fp64(dbc->d_theta, dbc->n, D, qc->d_theta, false, dq, nullptr, nq, k,
+                                  d_ids, d_dist, s);
     HIPTRY((hipError_t)e, "pp fp64 cross knn");
   } else {
     TRY(prepare_bf16(dbc, D, s));
@@ -228,6 +229,14 @@ extern "C" int panther_pp_topk_cross(panther_ctx* qc, panther_ctx* dbc, const in
            "pp outputs");
   }
   HIPTRY(hipStreamSynchronize(s), "pp_topk_cross");
+  return PANTHER_OK;
+}
+
+extern "C" int panther_pp_certified(panther_ctx* c, int64_t* queries, int64_t* recomputed) {
+  if (!c) return PANTHER_EINVAL;
+  if (!c->lane0.have_stats) return ctx_fail(c, PANTHER_ESTATE, "no BF16 Panther++ call");
+  if (queries) *queries = c->lane0.stat_nq;
+  if (recomputed) *recomputed = c->lane0.stat_fallback;
   return PANTHER_OK;
 }
 

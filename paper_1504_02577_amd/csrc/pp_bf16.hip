@@ -82,6 +82,39 @@ k_bf16_query_rows(const float* __restrict__ theta_q, int32_t D, const int32_t* _
   norm[i] = acc;
 }
 
+// Database bounds for the pool certificate, each rounded up to float and
+// combined by an integer max of the (non-negative) float bits:
+// out[0] >= max_v |theta_v|, out[1] >= max_v |bf16(theta_v * s) - theta_v * s|
+// (the rounding error of a scaled row, in scaled units).
+__global__ void __launch_bounds__(kBlock)
+k_row_bounds(const float* __restrict__ theta, int32_t n, int32_t D, float s, unsigned int* out) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  float f = 0.f, g = 0.f;
+  if (v < n) {
+    double a = 0.0, b = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const float t = theta[(int64_t)v * D + d];
+      const double x = (double)t;
+      a = fma(x, x, a);
+      const double y = (double)(t * s);
+      const double r = (double)(float)(__bf16)(t * s) - y;
+      b = fma(r, r, b);
+    }
+    f = (float)(sqrt(a) * (1.0 + 1.0 / (1 << 20)));
+    g = (float)(sqrt(b) * (1.0 + 1.0 / (1 << 20)));
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    const float o = __shfl_xor(f, off, kWave);
+    f = o > f ? o : f;
+    const float p = __shfl_xor(g, off, kWave);
+    g = p > g ? p : g;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMax(out, __float_as_uint(f));
+    atomicMax(out + 1, __float_as_uint(g));
+  }
+}
+
 __global__ void k_fill_u64(unsigned long long* a, int64_t n, unsigned long long v) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) a[i] = v;
@@ -394,6 +427,13 @@ k_pp_merge(PoolArgs A) {
 
 struct RerankArgs {
   const float* theta;    // [n][D] database rows
+  const float* db_max;   // [0] >= max_v |theta_v|, [1] >= max_v of a row's bf16 rounding error
+  double scale;          // s: the bf16 rows are bf16(theta * s)
+  int32_t* fb_list;      // queries whose pool boundary is not certified
+  double* fb_tau_d;      // and their k-th exact pair (d2, id)
+  int32_t* fb_tau_v;
+  unsigned long long* fb_n;
+  int32_t force;         // flag every query whose pool is full
   const float* qtheta;   // query rows by query id (theta itself, or the other graph's)
   int32_t D;
   const int32_t* queries;
@@ -497,6 +537,74 @@ k_pp_rerank(RerankArgs A) {
     atomicAdd(A.stat_hits, (unsigned long long)hits);
     atomicMax(A.stat_err, (unsigned long long)__double_as_longlong(err));
   }
+  // Certificate (in units of the scaled rows x = theta * s).  Every vertex
+  // outside the pool has a pool key at least the pool's largest, so its
+  // computed d2~ >= a_P^2.  A vertex with |x_v| > |x_q| + s d_k is farther
+  // than d_k by the triangle inequality; only the others ("near" rows)
+  // need a bound.  In general the computed d2~ = |b_q|^2 + |b_v|^2 -
+  // 2 <b_q, b_v> over the bfloat16 rows b errs from |b_q - b_v|^2 by at
+  // most delta = 2^-15 (|b_q|^2 + |b_v|^2) (about 132 FP32 roundings of
+  // those magnitudes, with margin), and |b - x| <= r per row (r_q computed
+  // here; r_v <= E for every row, and <= 2^-8 |x_v| <= 2^-8 (|x_q| + s d_k)
+  // for a near row).  Rows of counts are integral in bfloat16 (a count
+  // below 256 stays itself, a larger one rounds to an even integer), so
+  // when b_q is integral too and |b_q|^2 + |b_v|^2 < 2^24 the FP32
+  // evaluation is exact (delta = 0).  When moreover |x_q| + s d_k < 255,
+  // every near row has coordinates below 255, which bfloat16 keeps exactly
+  // (x is count * (1 +- 2^-23)), so r_v <= 2^-22 (|x_q| + s d_k).  If
+  // sqrt(a_P^2 - delta) - r_q - r_v > s d_k, no outside vertex can enter
+  // the top k, ties included.  In that last case with d_k = 0 the k results
+  // are rows equal to the query's, each with d2~ = 0 in the pool in id
+  // order, so it is certified too.  Otherwise the query is recomputed
+  // exactly: every row within its k-th exact pair (d_k, id) is a candidate.
+  double nq2 = 0.0, rq2 = 0.0;
+  bool q_int = true;
+  const float sf = (float)A.scale;
+  for (int j = lane; j < A.D; j += kWave) {
+    nq2 = fma((double)tq[j], (double)tq[j], nq2);
+    const float b = (float)(__bf16)(tq[j] * sf);
+    const double r = (double)b - (double)(tq[j] * sf);
+    rq2 = fma(r, r, rq2);
+    q_int = q_int && b == floorf(b);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    nq2 += __shfl_xor(nq2, off, kWave);
+    rq2 += __shfl_xor(rq2, off, kWave);
+  }
+  q_int = __ballot(!q_int) == 0ull;
+  if (lane == 0) {
+    const bool full = A.pool_ids[qi * P + P - 1] >= 0;
+    bool ok = !full || m < k;
+    if (!ok && !A.force) {
+      const double s = A.scale, dk = s * sqrt(d[k - 1]);
+      const double xq = s * sqrt(nq2), M = s * (double)A.db_max[0], E = (double)A.db_max[1];
+      const double reach = xq + dk;
+      const bool small = q_int && reach < 255.0;
+      if (small && d[k - 1] == 0.0) {
+        ok = true;
+      } else {
+        const double bq = xq * (1.0 + 1.0 / 256.0);
+        const double bv = fmin(M, reach) * (1.0 + 1.0 / 256.0);
+        // integral rows whose norms and the sum stay below 2^24 are
+        // evaluated exactly in FP32
+        const bool exact = q_int && bq * bq + bv * bv < 16777216.0;
+        const double delta = exact ? 0.0 : 3.0517578125e-05 * (bq * bq + bv * bv);
+        const double rv = small ? 2.384185791015625e-07 * reach : fmin(E, reach / 128.0);
+        const double a2 = (double)A.pool_d2[qi * P + P - 1];
+        // r was measured against the FP32 product theta * s, which is within
+        // 2^-24 of the exact scaled row
+        const double lower = sqrt(fmax(a2 - delta, 0.0)) - sqrt(rq2) * (1.0 + 1e-6) - rv -
+                             1.2e-7 * (xq + bv);
+        ok = lower > dk * (1.0 + 1e-9);
+      }
+    }
+    if (!ok) {
+      const unsigned long long at = atomicAdd(A.fb_n, 1ull);
+      A.fb_list[at] = (int32_t)qi;
+      A.fb_tau_d[at] = d[k - 1];
+      A.fb_tau_v[at] = v[k - 1];
+    }
+  }
 }
 
 }  // namespace
@@ -513,11 +621,23 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
       c->d_theta, c->n, D, (float)c->R, static_cast<__bf16*>(pp->b_bf16.p),
       static_cast<float*>(pp->b_norm.p));
   HIPTRY(hipGetLastError(), "bf16 rows");
+  TRY(ctx_ensure(c, pp->b_dbmax, 64, "row bounds"));
+  HIPTRY(hipMemsetAsync(pp->b_dbmax.p, 0, 64, s), "row bounds");
+  k_row_bounds<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+      c->d_theta, c->n, D, (float)c->R, static_cast<unsigned int*>(pp->b_dbmax.p));
+  HIPTRY(hipGetLastError(), "row bounds");
   pp->bf16_D = D;
   return PANTHER_OK;
 }
 
 namespace panther {
+
+size_t knn_range_bytes(int64_t nr);
+int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* qtheta,
+                         bool exclude_self, const int32_t* queries, const int32_t* rows,
+                         int64_t nr, const double* tau_d, const int32_t* tau_v, int32_t k,
+                         int num_cus, void* work, unsigned long long* ov_n_dev,
+                         int32_t* out_ids, double* out_dist, hipStream_t s, uint32_t cap);
 
 // Pool pass + rerank over the database context c.  qtheta (null: c's own
 // features) holds the queries' feature rows when they come from another
@@ -593,18 +713,56 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
     HIPTRY(hipGetLastError(), "pp merge");
   }
   unsigned long long* st = static_cast<unsigned long long*>(lane->b_stats.p);
-  RerankArgs ra{c->d_theta, qtheta ? qtheta : c->d_theta, D, dq, nq, P, k, pool_ids, pool_d2,
-                1.0f / (scale * scale), d_ids, d_dist, st, st + 1, st + 2};
+  TRY(ctx_ensure(c, lane->b_fb, (2 * sizeof(int32_t) + sizeof(double)) * (size_t)nq,
+                 "uncertified queries"));
+  int32_t* fb_list = static_cast<int32_t*>(lane->b_fb.p);
+  double* fb_tau_d = reinterpret_cast<double*>(fb_list + ((size_t)nq + 1) / 2 * 2);
+  int32_t* fb_tau_v = reinterpret_cast<int32_t*>(fb_tau_d + nq);
+  RerankArgs ra{};
+  ra.theta = c->d_theta;
+  ra.db_max = static_cast<const float*>(pp->b_dbmax.p);
+  ra.scale = (double)scale;
+  ra.fb_list = fb_list;
+  ra.fb_tau_d = fb_tau_d;
+  ra.fb_tau_v = fb_tau_v;
+  ra.fb_n = st + 3;
+  ra.force = c->pp_recompute_all;
+  ra.qtheta = qtheta ? qtheta : c->d_theta;
+  ra.D = D;
+  ra.queries = dq;
+  ra.nq = nq;
+  ra.P = P;
+  ra.k = k;
+  ra.pool_ids = pool_ids;
+  ra.pool_d2 = pool_d2;
+  ra.inv_s2 = 1.0f / (scale * scale);
+  ra.out_ids = d_ids;
+  ra.out_dist = d_dist;
+  ra.stat_hits = st;
+  ra.stat_err = st + 1;
+  ra.stat_ret = st + 2;
   k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, 0, s>>>(ra);
   HIPTRY(hipGetLastError(), "pp rerank");
-  unsigned long long hs[3];
-  HIPTRY(hipMemcpyAsync(hs, st, 24, hipMemcpyDeviceToHost, s), "pp stats");
+  unsigned long long hs[4];
+  HIPTRY(hipMemcpyAsync(hs, st, 32, hipMemcpyDeviceToHost, s), "pp stats");
   HIPTRY(hipStreamSynchronize(s), "pp stats");
+  // queries whose pool boundary is not certified: exact recompute
+  if (hs[3] > 0) {
+    TRY(ctx_ensure(c, lane->b_fbw, knn_range_bytes((int64_t)hs[3]), "exact recompute"));
+    const int e = launch_knn_recompute(c->d_theta, c->n, D, qtheta ? qtheta : c->d_theta, !qtheta,
+                                       dq, fb_list, (int64_t)hs[3], fb_tau_d, fb_tau_v, k,
+                                       c->num_cus, lane->b_fbw.p, st + 4, d_ids, d_dist, s,
+                                       c->pp_recompute_all == 2 ? (uint32_t)(k - 1) : ~0u);
+    HIPTRY((hipError_t)e, "pp exact recompute");
+    HIPTRY(hipStreamSynchronize(s), "pp exact recompute");
+  }
   lane->have_stats = true;
   lane->mean_pre_recall = hs[2] ? (double)hs[0] / (double)hs[2] : 1.0;
   double e;
   std::memcpy(&e, &hs[1], sizeof e);
   lane->max_rel_err = e;
+  lane->stat_nq = nq;
+  lane->stat_fallback = (int64_t)hs[3];
   return PANTHER_OK;
 }
 

@@ -27,6 +27,7 @@ struct PinnedBuf {
 // Panther++ data shared by every lane: bf16 copy of theta and its norms.
 struct PPState {
   DevBuf b_bf16, b_norm, b_iota;
+  DevBuf b_dbmax;  // float: an upper bound on max_v |theta_v| (Euclidean)
   int32_t bf16_D = 0;
 };
 
@@ -35,7 +36,9 @@ struct PPState {
 // over the same read-only graph, paths, index and features.
 struct Lane {
   BatchState* batch = nullptr;
-  DevBuf b_qlen, b_pool, b_out, b_stats, b_q, b_qrows;
+  DevBuf b_qlen, b_pool, b_out, b_stats, b_q, b_qrows, b_fb, b_fbw;
+  int64_t stat_nq = 0;        // queries of the last BF16-form call
+  int64_t stat_fallback = 0;  // of them, recomputed exactly (boundary not certified)
   PinnedBuf h_qlen;  // path-list lengths of the last call's queries
   bool have_stats = false;
   double max_rel_err = 0.0;
@@ -53,6 +56,7 @@ struct panther_ctx {
   int topk_form = 1;  // PANTHER_FORM_BATCHED
   int pp_form = 1;    // PANTHER_PP_BF16
   int pp_pool = 256;
+  int pp_recompute_all = 0;  // test: recompute every full-pool query (2: via brute force)
   int autotune = 1;
   int64_t fail_alloc_after = -1;
   std::mutex alloc_mu;

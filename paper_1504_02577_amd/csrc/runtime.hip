@@ -280,6 +280,10 @@ extern "C" int panther_set_option(panther_ctx* c, const char* key, int64_t value
     if (value != 0 && value != 1) return ctx_fail(c, PANTHER_EINVAL, "timing must be 0 or 1");
     c->timing = (int)value;
     for (int i = 0; i < 5; ++i) c->ev_used[i] = false;
+  } else if (k == "test.pp_recompute_all") {
+    if (value < 0 || value > 2)
+      return ctx_fail(c, PANTHER_EINVAL, "test.pp_recompute_all must be 0, 1 or 2");
+    c->pp_recompute_all = (int)value;
   } else if (k == "test.fail_alloc_after") {
     c->fail_alloc_after = value < 0 ? -1 : value;
   } else if (k == "batch.tier_a" || k == "batch.tier_b" || k == "batch.block" ||
@@ -666,7 +670,7 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
 void free_lane(Lane* lane) {
   free_batch_state(lane);
   for (DevBuf* b : {&lane->b_qlen, &lane->b_pool, &lane->b_out, &lane->b_stats, &lane->b_q,
-                    &lane->b_qrows})
+                    &lane->b_qrows, &lane->b_fb, &lane->b_fbw})
     ctx_release(*b);
   pinned_release(lane->h_qlen);
   lane->have_stats = false;
