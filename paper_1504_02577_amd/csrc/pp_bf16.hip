@@ -38,7 +38,7 @@ constexpr int kDP = 64;        // padded feature width in bfloat16
 constexpr int kQW = 128;       // queries per work-group
 constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
 constexpr int kTiles = kQW / 16;
-constexpr int kCheckEvery = 4;  // chunks between pool compaction checks
+constexpr int kCheckEvery = 8;  // chunks between pool compaction checks
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -48,20 +48,21 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// bf16 rows (scaled by s) and their FP32 norms
+// bf16 rows (scaled by s) and their FP32 norms, for rows 0 .. npad-1:
+// rows n .. npad-1 (the tail of the last chunk) are zero with a NaN norm
 __global__ void __launch_bounds__(kBlock)
-k_bf16_rows(const float* __restrict__ theta, int32_t n, int32_t D, float s,
+k_bf16_rows(const float* __restrict__ theta, int32_t n, int64_t npad, int32_t D, float s,
             __bf16* __restrict__ out, float* __restrict__ norm) {
-  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
-  if (v >= n) return;
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= npad) return;
   float acc = 0.f;
   for (int d = 0; d < kDP; ++d) {
-    const __bf16 b = d < D ? (__bf16)(theta[(int64_t)v * D + d] * s) : (__bf16)0.f;
-    out[(int64_t)v * kDP + d] = b;
+    const __bf16 b = d < D && v < n ? (__bf16)(theta[v * D + d] * s) : (__bf16)0.f;
+    out[v * kDP + d] = b;
     const float f = (float)b;
     acc = fmaf(f, f, acc);
   }
-  norm[v] = acc;
+  norm[v] = v < n ? acc : __builtin_nanf("");
 }
 
 // bf16 rows of the queries' own features (another graph's theta), scaled
@@ -264,7 +265,7 @@ k_pp_pool(PoolArgs A) {
     qn_s[i] = q >= 0 ? (A.q_by_pos ? A.qnorm[q0 + i] : A.norm[q]) : 0.f;
     cnt[i] = 0u;
     tau[i] = ~0ull;
-    tauf_s[i] = INFINITY;
+    tauf_s[i] = q >= 0 ? INFINITY : -1.f;  // a missing query matches nothing
   }
   __syncthreads();
   // query operands: tile m, k-step ks -> 8 bf16 of row (m*16 + l%16)
@@ -284,46 +285,83 @@ k_pp_pool(PoolArgs A) {
       }
     }
   }
-  auto load_b = [&](int64_t cb, bf16x8 (&bb)[2], float& nvv) {
+  // database rows: 16 per wavefront and chunk, row (l%16) as the MFMA's A
+  // operand, so that lane l receives the products of query m*16 + l%16
+  // with rows 4*(l/16) .. 4*(l/16)+3 of its wavefront's 16.  Slices are
+  // whole chunks and the row arrays are padded to whole chunks (zero rows,
+  // NaN norms), so every load is unconditional; a padding row's d2~ is NaN
+  // and passes no test.
+  auto load_b = [&](int64_t cb, bf16x8 (&bb)[2], floatx4& nvv) {
     const int64_t v = cb + wid * 16 + (lane & 15);
-    const bool ok = v < r1;
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      if (ok) {
-        bb[ks] = *reinterpret_cast<const bf16x8*>(A.rows + v * kDP + ks * 32 + 8 * (lane >> 4));
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bb[ks][j] = (__bf16)0.f;
-      }
-    }
-    nvv = ok ? A.norm[v] : 0.f;
+    for (int ks = 0; ks < 2; ++ks)
+      bb[ks] = *reinterpret_cast<const bf16x8*>(A.rows + v * kDP + ks * 32 + 8 * (lane >> 4));
+    nvv = *reinterpret_cast<const floatx4*>(A.norm + cb + wid * 16 + 4 * (lane >> 4));
   };
   bf16x8 b[2], bn[2];
-  float nv = 0.f, nvn = 0.f;
+  floatx4 nv{0.f, 0.f, 0.f, 0.f}, nvn{0.f, 0.f, 0.f, 0.f};
   if (r0 < r1) load_b(r0, b, nv);
+  // Per lane and tile: the norm qn and float threshold t of its query, and
+  // the prefilter bound tm on u = nv - 2 <b_q, b_v> (one rounding, by fma):
+  // d2~ = fl(u + qn) <= t implies u <= fl(t - qn) + 2^-21 (|t| + qn), so
+  // the prefilter drops no row that the exact test would keep.  Kept in
+  // registers; refreshed after every check.
+  float qnr[kTiles], tfr[kTiles], tmr[kTiles];
+  auto refresh = [&]() {
+#pragma unroll
+    for (int m = 0; m < kTiles; ++m) {
+      tfr[m] = tauf_s[m * 16 + (lane & 15)];
+      tmr[m] = (tfr[m] - qnr[m]) + (fabsf(tfr[m]) + qnr[m]) * 4.76837158203125e-7f;
+    }
+  };
+  int32_t qidr[kTiles];  // -1: no query (its threshold -1 passes nothing)
+#pragma unroll
+  for (int m = 0; m < kTiles; ++m) {
+    qnr[m] = qn_s[m * 16 + (lane & 15)];
+    qidr[m] = qid[m * 16 + (lane & 15)];
+  }
+  refresh();
   int chunk_no = 0;
   for (int64_t cb = r0; cb < r1; cb += kChunk) {
-    if (cb + kChunk < r1) load_b(cb + kChunk, bn, nvn);  // prefetch the next chunk
-    const int64_t v = cb + wid * 16 + (lane & 15);
+    // prefetch the next chunk (the last one reloads itself: an
+    // unconditional load lets the wait before the products cover only the
+    // older loads)
+    load_b(cb + kChunk < r1 ? cb + kChunk : cb, bn, nvn);
+    const int64_t vb = cb + wid * 16 + 4 * (lane >> 4);
     floatx4 acc[kTiles];
 #pragma unroll
     for (int m = 0; m < kTiles; ++m) {
       acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][0], b[0], acc[m], 0, 0, 0);
-      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][1], b[1], acc[m], 0, 0, 0);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[0], a[m][0], acc[m], 0, 0, 0);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[1], a[m][1], acc[m], 0, 0, 0);
     }
-    if (v < r1) {
+    // per tile: does any lane's smallest u pass the prefilter?
+    uint64_t tile_hit[kTiles], any_hit = 0ull;
+#pragma unroll
+    for (int m = 0; m < kTiles; ++m) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[m][r] = __builtin_fmaf(-2.f, acc[m][r], nv[r]);  // u
+      const float mn = fminf(fminf(acc[m][0], acc[m][1]), fminf(acc[m][2], acc[m][3]));
+      tile_hit[m] = __ballot(mn <= tmr[m]);
+      any_hit |= tile_hit[m];
+    }
+    if (any_hit != 0ull) {
 #pragma unroll
       for (int m = 0; m < kTiles; ++m) {
+        if (tile_hit[m] == 0ull) continue;
+        const int ql = m * 16 + (lane & 15);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int ql = m * 16 + 4 * (lane >> 4) + r;
-          float d2 = qn_s[ql] + nv - 2.f * acc[m][r];
-          d2 = d2 > 0.f ? d2 : 0.f;
-          if (d2 <= tauf_s[ql]) {  // float prefilter; the exact key test follows
+          const int64_t v = vb + r;
+          // d2~ = fl(u + qn); a negative rounding result counts as 0 (the
+          // test d2 <= t with t >= 0 is the same before and after the clamp)
+          const float raw = acc[m][r] + qnr[m];
+          if (raw <= tfr[m] && (!A.exclude_self || qidr[m] != (int32_t)v)) {
+            const float d2 = raw > 0.f ? raw : 0.f;
             const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)v;
-            if (key < tau[ql] && qid[ql] >= 0 &&
-                (!A.exclude_self || qid[ql] != (int32_t)v)) {
+            // below the threshold's float part the key is below the
+            // threshold; at equality the ids decide
+            if (d2 < tfr[m] || key < tau[ql]) {
               const uint32_t pos = atomicAdd(&cnt[ql], 1u);
               A.buf[((q0 + ql) * A.slices + slice) * cap + pos] = key;
             }
@@ -351,9 +389,16 @@ k_pp_pool(PoolArgs A) {
       __syncthreads();
     }
     // cut back buffers that the next check_every chunks could overflow
-    for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
-      const int c = (int)cnt[ql];
-      if (c > P && c > cap - check_every * kChunk) {
+    // (lane j looks at query wid + 4j; the wave then takes them in turn)
+    constexpr int kPerWave = kQW / (kBlock / kWave);
+    int cj = lane < kPerWave ? (int)cnt[wid + (kBlock / kWave) * lane] : 0;
+    uint64_t todo = __ballot(lane < kPerWave && cj > P && cj > cap - check_every * kChunk);
+    while (todo) {
+      const int j = __ffsll((long long)todo) - 1;
+      todo &= todo - 1ull;
+      const int ql = wid + (kBlock / kWave) * j;
+      const int c = __shfl(cj, j, kWave);
+      {
         uint64_t* g = A.buf + ((q0 + ql) * A.slices + slice) * cap;
         uint64_t* sb = sortmem + (size_t)wid * A.sort_cap;
         for (int i = lane; i < c; i += kWave)
@@ -374,6 +419,7 @@ k_pp_pool(PoolArgs A) {
     }
     __threadfence_block();
     __syncthreads();
+    refresh();
   }
   // final pools of this slice
   for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
@@ -615,10 +661,11 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
   if (!pp || !c->d_theta || c->theta_D != D)
     return ctx_fail(c, PANTHER_ESTATE, "features for D = %d are not computed", D);
   if (pp->bf16_D == D) return PANTHER_OK;
-  TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)c->n * kDP, "bf16 rows"));
-  TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)c->n, "bf16 norms"));
-  k_bf16_rows<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-      c->d_theta, c->n, D, (float)c->R, static_cast<__bf16*>(pp->b_bf16.p),
+  const int64_t npad = ((int64_t)c->n + kChunk - 1) / kChunk * kChunk;
+  TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)npad * kDP, "bf16 rows"));
+  TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)npad, "bf16 norms"));
+  k_bf16_rows<<<(unsigned)((npad + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+      c->d_theta, c->n, npad, D, (float)c->R, static_cast<__bf16*>(pp->b_bf16.p),
       static_cast<float*>(pp->b_norm.p));
   HIPTRY(hipGetLastError(), "bf16 rows");
   TRY(ctx_ensure(c, pp->b_dbmax, 64, "row bounds"));
