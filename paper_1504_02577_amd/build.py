@@ -26,6 +26,10 @@ HIPCC_FLAGS = [
     # IEEE single-precision division and square root
     "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-ffp-contract=off",
+    # matrix-core results in ordinary VGPRs: the pool pass reads every
+    # product with VALU instructions, and accumulation registers would need
+    # a copy each
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]

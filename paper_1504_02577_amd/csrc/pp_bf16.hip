@@ -38,7 +38,8 @@ constexpr int kDP = 64;        // padded feature width in bfloat16
 constexpr int kQW = 128;       // queries per work-group
 constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
 constexpr int kTiles = kQW / 16;
-constexpr int kCheckEvery = 8;  // chunks between pool compaction checks
+constexpr int kTrip = 2;        // chunks per loop trip (ping-pong operands)
+constexpr int kCheckEvery = 8;  // chunks between pool compaction checks (whole trips)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -49,7 +50,7 @@ __device__ __forceinline__ void wsync() {
 }
 
 // bf16 rows (scaled by s) and their FP32 norms, for rows 0 .. npad-1:
-// rows n .. npad-1 (the tail of the last chunk) are zero with a NaN norm
+// rows n .. npad-1 (the tail of the last trip of chunks) are zero with a NaN norm
 __global__ void __launch_bounds__(kBlock)
 k_bf16_rows(const float* __restrict__ theta, int32_t n, int64_t npad, int32_t D, float s,
             __bf16* __restrict__ out, float* __restrict__ norm) {
@@ -224,7 +225,7 @@ struct PoolArgs {
   int32_t P;             // pool size (power of two, <= 1024)
   int32_t cap;           // buffer entries per (query, slice): 2P + kCheckEvery * kChunk
   int32_t slices;        // database slices (grid.y)
-  int32_t rows_per_slice;// multiple of kChunk
+  int32_t rows_per_slice;// multiple of kTrip * kChunk
   int32_t sort_cap;      // per-wave sort buffer entries: next power of two >= cap
   uint64_t* buf;         // [nq][slices][cap] pool buffers
   uint64_t* part;        // [nq][slices][P] sorted slice pools (slices > 1)
@@ -298,9 +299,13 @@ k_pp_pool(PoolArgs A) {
       bb[ks] = *reinterpret_cast<const bf16x8*>(A.rows + v * kDP + ks * 32 + 8 * (lane >> 4));
     nvv = *reinterpret_cast<const floatx4*>(A.norm + cb + wid * 16 + 4 * (lane >> 4));
   };
-  bf16x8 b[2], bn[2];
-  floatx4 nv{0.f, 0.f, 0.f, 0.f}, nvn{0.f, 0.f, 0.f, 0.f};
-  if (r0 < r1) load_b(r0, b, nv);
+  // operands of two chunks in ping-pong registers
+  bf16x8 b0[2], b1[2];
+  floatx4 nv0, nv1;
+  auto next = [&](int64_t t, int64_t cb) { return t < r1 ? t : cb; };
+  // unconditional (an empty slice loads chunk 0), so that the waits in the
+  // loop can leave newer loads in flight
+  load_b(r0 < r1 ? r0 : 0, b0, nv0);
   // Per lane and tile: the norm qn and float threshold t of its query, and
   // the prefilter bound tm on u = nv - 2 <b_q, b_v> (one rounding, by fma):
   // d2~ = fl(u + qn) <= t implies u <= fl(t - qn) + 2^-21 (|t| + qn), so
@@ -321,26 +326,22 @@ k_pp_pool(PoolArgs A) {
     qidr[m] = qid[m * 16 + (lane & 15)];
   }
   refresh();
-  int chunk_no = 0;
-  for (int64_t cb = r0; cb < r1; cb += kChunk) {
-    // prefetch the next chunk (the last one reloads itself: an
-    // unconditional load lets the wait before the products cover only the
-    // older loads)
-    load_b(cb + kChunk < r1 ? cb + kChunk : cb, bn, nvn);
+  // one chunk: products, prefilter, appends
+  auto chunk = [&](const bf16x8 (&bc)[2], const floatx4& nvc, int64_t cb) {
     const int64_t vb = cb + wid * 16 + 4 * (lane >> 4);
     floatx4 acc[kTiles];
 #pragma unroll
     for (int m = 0; m < kTiles; ++m) {
       acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[0], a[m][0], acc[m], 0, 0, 0);
-      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[1], a[m][1], acc[m], 0, 0, 0);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bc[0], a[m][0], acc[m], 0, 0, 0);
+      acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bc[1], a[m][1], acc[m], 0, 0, 0);
     }
     // per tile: does any lane's smallest u pass the prefilter?
     uint64_t tile_hit[kTiles], any_hit = 0ull;
 #pragma unroll
     for (int m = 0; m < kTiles; ++m) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[m][r] = __builtin_fmaf(-2.f, acc[m][r], nv[r]);  // u
+      for (int r = 0; r < 4; ++r) acc[m][r] = __builtin_fmaf(-2.f, acc[m][r], nvc[r]);  // u
       const float mn = fminf(fminf(acc[m][0], acc[m][1]), fminf(acc[m][2], acc[m][3]));
       tile_hit[m] = __ballot(mn <= tmr[m]);
       any_hit |= tile_hit[m];
@@ -369,10 +370,20 @@ k_pp_pool(PoolArgs A) {
         }
       }
     }
-#pragma unroll
-    for (int ks = 0; ks < 2; ++ks) b[ks] = bn[ks];
-    nv = nvn;
-    if (++chunk_no % check_every != 0 && cb + kChunk < r1) continue;
+  };
+  // two chunks per trip, so that the ping-pong needs no register copies
+  // (a copy of a prefetched operand would force a wait); slices are whole
+  // trips and the rows are padded to whole trips, so both chunks are in
+  // bounds (past the last row they are padding).  A prefetch past the
+  // slice reloads a chunk of it instead.
+  int chunk_no = 0;
+  for (int64_t cb = r0; cb < r1; cb += kTrip * kChunk) {
+    load_b(cb + kChunk, b1, nv1);
+    chunk(b0, nv0, cb);
+    load_b(next(cb + 2 * kChunk, cb), b0, nv0);
+    chunk(b1, nv1, cb + kChunk);
+    chunk_no += kTrip;
+    if (chunk_no % check_every != 0 && cb + kTrip * kChunk < r1) continue;
     __threadfence_block();
     __syncthreads();
     // adopt the other slices' bound where it is tighter (one load per query)
@@ -661,7 +672,7 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
   if (!pp || !c->d_theta || c->theta_D != D)
     return ctx_fail(c, PANTHER_ESTATE, "features for D = %d are not computed", D);
   if (pp->bf16_D == D) return PANTHER_OK;
-  const int64_t npad = ((int64_t)c->n + kChunk - 1) / kChunk * kChunk;
+  const int64_t npad = ((int64_t)c->n + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk);
   TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)npad * kDP, "bf16 rows"));
   TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)npad, "bf16 norms"));
   k_bf16_rows<<<(unsigned)((npad + kBlock - 1) / kBlock), kBlock, 0, s>>>(
@@ -710,7 +721,8 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
   S = std::min<int64_t>(S, std::max<int64_t>(1, c->n / 4096));
   S = std::min<int64_t>(S, std::max<int64_t>(1, 262144 / P));  // bounds the merge work
-  const int64_t rps = ((c->n + S - 1) / S + kChunk - 1) / kChunk * kChunk;
+  const int64_t rps =
+      ((c->n + S - 1) / S + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk);
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
   const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;
   const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
