@@ -35,7 +35,8 @@ __global__ void k_iota(int32_t* out, int32_t n) {
 void free_pp_state(panther_ctx* c) {
   c->lane0.have_stats = false;
   if (!c->pp) return;
-  for (DevBuf* b : {&c->pp->b_bf16, &c->pp->b_norm, &c->pp->b_iota, &c->pp->b_dbmax})
+  for (DevBuf* b : {&c->pp->b_bf16, &c->pp->b_norm, &c->pp->b_iota, &c->pp->b_dbmax,
+                    &c->pp->b_sid, &c->pp->b_rank})
     ctx_release(*b);
   delete c->pp;
   c->pp = nullptr;

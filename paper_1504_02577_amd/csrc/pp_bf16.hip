@@ -4,17 +4,25 @@
 // 1. Feature rows are scaled by R (so theta * R is the integer count c) and
 //    rounded to bfloat16, zero-padded to 64 columns; counts up to 256 are
 //    exact in bfloat16, and their products and sums stay exact in the FP32
-//    accumulator.  FP32 row norms come from the same bfloat16 values.
-// 2. Pool pass: a work-group owns 128 queries for the whole scan and
-//    streams every database row in chunks of 64.  Each wavefront computes
-//    128 x 16 dot products per chunk with v_mfma_f32_16x16x32_bf16 (query
-//    operands stay in registers for the whole scan), turns them into
-//    d2~ = |b_q|^2 + |b_v|^2 - 2 <b_q, b_v>, and appends (d2~, v) keys below
-//    the query's threshold to that query's pool buffer in global memory.
-//    After each chunk, buffers that could overflow on the next chunk are
-//    sorted by one wavefront and cut back to the pool size P, which sets the
-//    threshold to the P-th best key.  Keys are (float bits of d2~, id), so
-//    ties break by id exactly as in the exact order.
+//    accumulator.  FP32 row norms come from the same bfloat16 values.  The
+//    rows are stored in ascending order of norm (with each row's original
+//    id), and every call orders its queries by norm too.
+// 2. Pool pass: a work-group owns 128 queries of neighbouring norms and
+//    scans chunks of 64 database rows outward from the chunk where their
+//    median norm falls, alternately upward and downward.  Each wavefront
+//    computes 128 x 16 dot products per chunk with
+//    v_mfma_f32_16x16x32_bf16 (query operands stay in registers), turns
+//    them into d2~ = |b_q|^2 + |b_v|^2 - 2 <b_q, b_v>, and appends (d2~, v)
+//    keys below the query's threshold to that query's pool buffer in global
+//    memory.  Buffers that could overflow are cut back to the pool size P,
+//    which sets the threshold to the P-th best key.  Keys are (float bits
+//    of d2~, original id), so ties break by id exactly as in the exact
+//    order.  The reverse triangle inequality bounds d2~ below by the gap
+//    between the two norms (less the rounding bound below): once a
+//    direction reaches rows whose norms lie outside every query's band
+//    (norm +- threshold radius), it stops -- those rows could not enter
+//    any pool.  The pool is thus the P smallest keys over all rows, the
+//    same set a full scan gives, from a fraction of the rows.
 // 3. Rerank: one wavefront per query recomputes the exact FP64 squared
 //    distance (one fma per coordinate, coordinate order) of every pool
 //    member, sorts by (d2, id) and writes the first k.  It also records how
@@ -24,6 +32,8 @@
 #include <cmath>
 #include <cstring>
 #include <vector>
+
+#include <hipcub/hipcub.hpp>
 
 #include "../../include/panther.h"
 #include "common.h"
@@ -49,21 +59,54 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// bf16 rows (scaled by s) and their FP32 norms, for rows 0 .. npad-1:
-// rows n .. npad-1 (the tail of the last trip of chunks) are zero with a NaN norm
+// FP32 norm of the scaled bfloat16 row of each vertex, as sort keys (the
+// bits of a non-negative float order like the float), with the vertex ids
 __global__ void __launch_bounds__(kBlock)
-k_bf16_rows(const float* __restrict__ theta, int32_t n, int64_t npad, int32_t D, float s,
-            __bf16* __restrict__ out, float* __restrict__ norm) {
-  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (v >= npad) return;
+k_bf16_norm_keys(const float* __restrict__ theta, int32_t n, int32_t D, float s,
+                 uint32_t* __restrict__ keys, int32_t* __restrict__ ids) {
+  const int32_t v = blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  float acc = 0.f;
+  for (int d = 0; d < D; ++d) {
+    const float f = (float)(__bf16)(theta[(int64_t)v * D + d] * s);
+    acc = fmaf(f, f, acc);
+  }
+  keys[v] = __float_as_uint(acc);
+  ids[v] = v;
+}
+
+// bf16 rows (scaled by s) in ascending norm order: position i holds vertex
+// sid[i] with its FP32 norm; rank[v] is v's position.  Positions n .. npad-1
+// (the tail of the last trip of chunks) are zero rows with a NaN norm and
+// id INT32_MAX.
+__global__ void __launch_bounds__(kBlock)
+k_bf16_rows_sorted(const float* __restrict__ theta, int32_t n, int64_t npad, int32_t D, float s,
+                   int32_t* __restrict__ sid, __bf16* __restrict__ out, float* __restrict__ norm,
+                   int32_t* __restrict__ rank) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= npad) return;
+  const int32_t v = i < n ? sid[i] : -1;
   float acc = 0.f;
   for (int d = 0; d < kDP; ++d) {
-    const __bf16 b = d < D && v < n ? (__bf16)(theta[v * D + d] * s) : (__bf16)0.f;
-    out[v * kDP + d] = b;
+    const __bf16 b = d < D && v >= 0 ? (__bf16)(theta[(int64_t)v * D + d] * s) : (__bf16)0.f;
+    out[i * kDP + d] = b;
     const float f = (float)b;
     acc = fmaf(f, f, acc);
   }
-  norm[v] = v < n ? acc : __builtin_nanf("");
+  norm[i] = v >= 0 ? acc : __builtin_nanf("");
+  if (v >= 0) rank[v] = (int32_t)i;
+  else sid[i] = 0x7FFFFFFF;
+}
+
+// sort keys for the queries: norm of each query position's operand
+__global__ void __launch_bounds__(kBlock)
+k_query_norm_keys(const float* __restrict__ norm, const int32_t* __restrict__ rank,
+                  const float* __restrict__ qnorm, const int32_t* __restrict__ queries, int64_t nq,
+                  uint32_t* __restrict__ keys, int32_t* __restrict__ pos) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nq) return;
+  keys[i] = __float_as_uint(qnorm ? qnorm[i] : norm[rank[queries[i]]]);
+  pos[i] = (int32_t)i;
 }
 
 // bf16 rows of the queries' own features (another graph's theta), scaled
@@ -217,69 +260,133 @@ __device__ uint64_t wave_select_cut(uint64_t* a, int c, int P, uint32_t* hist) {
 }
 
 struct PoolArgs {
-  const __bf16* rows;    // [n][64]
-  const float* norm;     // [n]
+  const __bf16* rows;    // [npad][64] database rows in ascending norm order
+  const float* norm;     // [npad] their FP32 norms (NaN past n)
+  const int32_t* sid;    // [npad] original id of each row (INT32_MAX past n)
+  const int32_t* rank;   // [n] position of each original id
   int32_t n;
+  int64_t nchunks;       // chunks of rows (whole trips); chunk nchunks is all padding
   const int32_t* queries;
+  const int32_t* q_order;// query positions in ascending order of operand norm
   int64_t nq;
   int32_t P;             // pool size (power of two, <= 1024)
   int32_t cap;           // buffer entries per (query, slice): 2P + kCheckEvery * kChunk
-  int32_t slices;        // database slices (grid.y)
-  int32_t rows_per_slice;// multiple of kTrip * kChunk
+  int32_t slices;        // work-groups per query tile (grid.y), interleaved over chunks
   int32_t sort_cap;      // per-wave sort buffer entries: next power of two >= cap
-  uint64_t* buf;         // [nq][slices][cap] pool buffers
-  uint64_t* part;        // [nq][slices][P] sorted slice pools (slices > 1)
-  int32_t* pool_ids;     // [nq][P] result when slices == 1, ascending key order, -1 padded
+  uint64_t* buf;         // [nq][slices][cap] pool buffers, by sorted index
+  uint64_t* part;        // [nq][slices][P] slice pools (slices > 1), by sorted index
+  int32_t* pool_ids;     // [nq][P] result by query position, ascending key order, -1 padded
   float* pool_d2;        // [nq][P]
-  // query operands: rows[q] / norm[q] of the database itself, or (cross
+  // query operands: the database's own rows (row rank[q]), or (cross
   // form) qrows[i] / qnorm[i] gathered per query position i
   const __bf16* qrows;
   const float* qnorm;
   int32_t q_by_pos;
   int32_t exclude_self;  // single graph: the query's own row is no candidate
-  // slices > 1: per query, the smallest P-th best key any slice has
-  // reached so far -- an upper bound on the query's P-th best key overall,
-  // so every slice may drop keys at or above it
+  // slices > 1: per query (sorted index), the smallest P-th best key any
+  // slice has reached so far -- an upper bound on the query's P-th best key
+  // overall, so every slice may drop keys at or above it
   unsigned long long* gtau;
 };
 
-// grid (query tiles, database slices)
+// Norm band of one query for the current float threshold t (squared
+// units).  A row whose exact norm x has |x - |b_q|| = g satisfies
+// d2~ >= g^2 - delta with delta <= 2^-15 (|b_q|^2 + x^2) (the rounding
+// bound of d2~), so d2~ > t, and the row cannot enter the pool, once
+// g^2 > (t + 2^-13 |b_q|^2)(1 + 2^-13).  With rho^2 = (t + 2^-12 qn)(1 +
+// 2^-12) that holds for computed norms (FP32 sums of 64 squares, relative
+// error below 2^-17 after the square root) outside
+//   [ (sqrt(qn)(1 - 2^-16) - rho)^2, (sqrt(qn)(1 + 2^-16) + rho)^2 ],
+// widened once more by 2^-12 relative.  lo2 = 0 when the band reaches 0.
+__device__ __forceinline__ void norm_band(float qn, float t, float& lo2, float& hi2) {
+  if (!(t < INFINITY)) {
+    lo2 = 0.f;
+    hi2 = INFINITY;
+    return;
+  }
+  const float rq = sqrtf(qn);
+  const float rho = sqrtf((t + qn * 2.44140625e-4f) * (1.f + 2.44140625e-4f));
+  const float hi = rq * (1.f + 1.52587890625e-5f) + rho;
+  const float lo = rq * (1.f - 1.52587890625e-5f) - rho;
+  hi2 = hi * hi * (1.f + 2.44140625e-4f);
+  lo2 = lo > 0.f ? lo * lo * (1.f - 2.44140625e-4f) : 0.f;
+}
+
+// grid (query tiles, slices)
 __global__ void __launch_bounds__(kBlock)
 k_pp_pool(PoolArgs A) {
   __shared__ uint32_t cnt[kQW];
   __shared__ uint64_t tau[kQW];
   __shared__ float tauf_s[kQW];  // float part of tau, for the prefilter
   __shared__ int32_t qid[kQW];
+  __shared__ int32_t qpos[kQW];
   __shared__ float qn_s[kQW];
+  __shared__ uint32_t s_band[2];  // float bits: band of the whole tile [lo2, hi2]
+  __shared__ int32_t s_dir[2];    // directions still open: up, down
+  __shared__ int64_t s_c0;        // chunk of the tile's median norm
   extern __shared__ __align__(16) uint64_t sortmem[];  // [waves][cap]
   __shared__ uint32_t s_hist[kBlock / kWave][256];     // per-wave radix select
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int64_t q0 = (int64_t)blockIdx.x * kQW;
+  const int64_t q0 = (int64_t)blockIdx.x * kQW;  // sorted index of the tile's first query
   const int slice = blockIdx.y;
+  const int S = A.slices;
   const int P = A.P, cap = A.cap;
   const int check_every = kCheckEvery;
-  const int64_t r0 = (int64_t)slice * A.rows_per_slice;
-  const int64_t r1 = r0 + A.rows_per_slice < A.n ? r0 + A.rows_per_slice : A.n;
+  const int nvalid = (int)(A.nq - q0 < kQW ? A.nq - q0 : kQW);
   for (int i = threadIdx.x; i < kQW; i += kBlock) {
-    const int32_t q = q0 + i < A.nq ? A.queries[q0 + i] : -1;
+    const int32_t pos = i < nvalid ? A.q_order[q0 + i] : -1;
+    const int32_t q = pos >= 0 ? A.queries[pos] : -1;
     qid[i] = q;
-    qn_s[i] = q >= 0 ? (A.q_by_pos ? A.qnorm[q0 + i] : A.norm[q]) : 0.f;
+    qpos[i] = pos;
+    qn_s[i] = q >= 0 ? (A.q_by_pos ? A.qnorm[pos] : A.norm[A.rank[q]]) : 0.f;
     cnt[i] = 0u;
     tau[i] = ~0ull;
     tauf_s[i] = q >= 0 ? INFINITY : -1.f;  // a missing query matches nothing
   }
+  if (threadIdx.x == 0) {
+    s_band[0] = 0u;
+    s_band[1] = __float_as_uint(INFINITY);
+    s_dir[0] = s_dir[1] = 1;
+  }
   __syncthreads();
+  // start chunk: where the median query norm falls among the sorted rows
+  // (a 256-way search for the first row with norm >= target: rows below
+  // lo are below it, and row hi is n or not below it)
+  {
+    const float target = qn_s[(nvalid - 1) / 2];
+    int64_t lo = 0, hi = A.n;
+    while (lo < hi) {
+      const int64_t step = (hi - lo + kBlock - 1) / kBlock;
+      const int64_t idx = lo + (int64_t)threadIdx.x * step;
+      const int below = idx < hi && A.norm[idx] < target;
+      const int nb = __syncthreads_count(below);  // the probes below form a prefix
+      if (nb == 0) {
+        hi = lo;
+      } else {
+        const int64_t last = lo + (int64_t)(nb - 1) * step;  // last probe below
+        lo = last + 1;
+        hi = last + step < hi ? last + step : hi;
+      }
+    }
+    if (threadIdx.x == 0) {
+      int64_t c = lo / kChunk;
+      if (c >= A.nchunks) c = A.nchunks - 1;
+      s_c0 = c;
+    }
+    __syncthreads();
+  }
+  const int64_t c0 = __builtin_amdgcn_readfirstlane((int)s_c0);
   // query operands: tile m, k-step ks -> 8 bf16 of row (m*16 + l%16)
   bf16x8 a[kTiles][2];
 #pragma unroll
   for (int m = 0; m < kTiles; ++m) {
     const int32_t q = qid[m * 16 + (lane & 15)];
-    const int64_t qr = A.q_by_pos ? q0 + m * 16 + (lane & 15) : (int64_t)q;
+    const __bf16* qr = A.q_by_pos ? A.qrows + (int64_t)qpos[m * 16 + (lane & 15)] * kDP
+                                  : A.rows + (int64_t)(q >= 0 ? A.rank[q] : 0) * kDP;
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks) {
       if (q >= 0) {
-        a[m][ks] = *reinterpret_cast<const bf16x8*>(A.qrows + qr * kDP + ks * 32 +
-                                                    8 * (lane >> 4));
+        a[m][ks] = *reinterpret_cast<const bf16x8*>(qr + ks * 32 + 8 * (lane >> 4));
       } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) a[m][ks][j] = (__bf16)0.f;
@@ -288,24 +395,19 @@ k_pp_pool(PoolArgs A) {
   }
   // database rows: 16 per wavefront and chunk, row (l%16) as the MFMA's A
   // operand, so that lane l receives the products of query m*16 + l%16
-  // with rows 4*(l/16) .. 4*(l/16)+3 of its wavefront's 16.  Slices are
-  // whole chunks and the row arrays are padded to whole chunks (zero rows,
-  // NaN norms), so every load is unconditional; a padding row's d2~ is NaN
-  // and passes no test.
-  auto load_b = [&](int64_t cb, bf16x8 (&bb)[2], floatx4& nvv) {
+  // with rows 4*(l/16) .. 4*(l/16)+3 of its wavefront's 16.  The row arrays
+  // are padded to whole trips of chunks plus one chunk (zero rows, NaN
+  // norms), so every load is unconditional; a padding row's d2~ is NaN and
+  // passes no test, and chunk -1 (none) is the all-padding chunk.
+  auto load_b = [&](int64_t c, bf16x8 (&bb)[2], floatx4& nvv, int4& idv) {
+    const int64_t cb = (c >= 0 ? c : A.nchunks) * kChunk;  // -1: the all-padding chunk
     const int64_t v = cb + wid * 16 + (lane & 15);
 #pragma unroll
     for (int ks = 0; ks < 2; ++ks)
       bb[ks] = *reinterpret_cast<const bf16x8*>(A.rows + v * kDP + ks * 32 + 8 * (lane >> 4));
     nvv = *reinterpret_cast<const floatx4*>(A.norm + cb + wid * 16 + 4 * (lane >> 4));
+    idv = *reinterpret_cast<const int4*>(A.sid + cb + wid * 16 + 4 * (lane >> 4));
   };
-  // operands of two chunks in ping-pong registers
-  bf16x8 b0[2], b1[2];
-  floatx4 nv0, nv1;
-  auto next = [&](int64_t t, int64_t cb) { return t < r1 ? t : cb; };
-  // unconditional (an empty slice loads chunk 0), so that the waits in the
-  // loop can leave newer loads in flight
-  load_b(r0 < r1 ? r0 : 0, b0, nv0);
   // Per lane and tile: the norm qn and float threshold t of its query, and
   // the prefilter bound tm on u = nv - 2 <b_q, b_v> (one rounding, by fma):
   // d2~ = fl(u + qn) <= t implies u <= fl(t - qn) + 2^-21 (|t| + qn), so
@@ -327,8 +429,7 @@ k_pp_pool(PoolArgs A) {
   }
   refresh();
   // one chunk: products, prefilter, appends
-  auto chunk = [&](const bf16x8 (&bc)[2], const floatx4& nvc, int64_t cb) {
-    const int64_t vb = cb + wid * 16 + 4 * (lane >> 4);
+  auto chunk = [&](const bf16x8 (&bc)[2], const floatx4& nvc, const int4& idc) {
     floatx4 acc[kTiles];
 #pragma unroll
     for (int m = 0; m < kTiles; ++m) {
@@ -347,43 +448,69 @@ k_pp_pool(PoolArgs A) {
       any_hit |= tile_hit[m];
     }
     if (any_hit != 0ull) {
+      const int32_t ids[4] = {idc.x, idc.y, idc.z, idc.w};
 #pragma unroll
       for (int m = 0; m < kTiles; ++m) {
         if (tile_hit[m] == 0ull) continue;
         const int ql = m * 16 + (lane & 15);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t v = vb + r;
+          const int32_t v = ids[r];
           // d2~ = fl(u + qn); a negative rounding result counts as 0 (the
           // test d2 <= t with t >= 0 is the same before and after the clamp)
           const float raw = acc[m][r] + qnr[m];
-          if (raw <= tfr[m] && (!A.exclude_self || qidr[m] != (int32_t)v)) {
+          if (raw <= tfr[m] && (!A.exclude_self || qidr[m] != v)) {
             const float d2 = raw > 0.f ? raw : 0.f;
             const uint64_t key = ((uint64_t)__float_as_uint(d2) << 32) | (uint32_t)v;
             // below the threshold's float part the key is below the
             // threshold; at equality the ids decide
             if (d2 < tfr[m] || key < tau[ql]) {
               const uint32_t pos = atomicAdd(&cnt[ql], 1u);
-              A.buf[((q0 + ql) * A.slices + slice) * cap + pos] = key;
+              A.buf[((q0 + ql) * S + slice) * cap + pos] = key;
             }
           }
         }
       }
     }
   };
-  // two chunks per trip, so that the ping-pong needs no register copies
-  // (a copy of a prefetched operand would force a wait); slices are whole
-  // trips and the rows are padded to whole trips, so both chunks are in
-  // bounds (past the last row they are padding).  A prefetch past the
-  // slice reloads a chunk of it instead.
+  // Chunk sequence of this slice: upward c0 + slice, c0 + slice + S, ...
+  // and downward c0 - 1 - slice, c0 - 1 - slice - S, ..., alternating while
+  // both directions are open; -1 when none is.  Every wavefront runs the
+  // same (uniform) sequence.
+  int up_on = 1, down_on = 1;
+  int64_t nu = 0, nd = 0;
+  auto next_chunk = [&]() -> int64_t {
+    const int64_t cu = c0 + slice + (int64_t)S * nu;
+    const int64_t cd = c0 - 1 - slice - (int64_t)S * nd;
+    up_on = up_on && cu < A.nchunks;  // a direction past its end stays closed
+    down_on = down_on && cd >= 0;
+    if (up_on && (!down_on || nu <= nd)) {
+      ++nu;
+      return cu;
+    }
+    if (down_on) {
+      ++nd;
+      return cd;
+    }
+    return -1;
+  };
+  // operands of two chunks in ping-pong registers: each trip computes one
+  // while the next loads (no register copies, which would force a wait)
+  bf16x8 b0[2], b1[2];
+  floatx4 nv0, nv1;
+  int4 id0, id1;
+  int64_t c_a = next_chunk();
+  load_b(c_a, b0, nv0, id0);
   int chunk_no = 0;
-  for (int64_t cb = r0; cb < r1; cb += kTrip * kChunk) {
-    load_b(cb + kChunk, b1, nv1);
-    chunk(b0, nv0, cb);
-    load_b(next(cb + 2 * kChunk, cb), b0, nv0);
-    chunk(b1, nv1, cb + kChunk);
+  while (true) {
+    const int64_t c_b = next_chunk();
+    load_b(c_b, b1, nv1, id1);
+    chunk(b0, nv0, id0);
+    c_a = next_chunk();
+    load_b(c_a, b0, nv0, id0);
+    chunk(b1, nv1, id1);
     chunk_no += kTrip;
-    if (chunk_no % check_every != 0 && cb + kTrip * kChunk < r1) continue;
+    if (chunk_no % check_every != 0 && c_a >= 0) continue;
     __threadfence_block();
     __syncthreads();
     // adopt the other slices' bound where it is tighter (one load per query)
@@ -399,79 +526,116 @@ k_pp_pool(PoolArgs A) {
       }
       __syncthreads();
     }
-    // cut back buffers that the next check_every chunks could overflow
+    // cut back buffers that the next check_every chunks could overflow, or
+    // (first cut) any buffer past P while its threshold is still open
     // (lane j looks at query wid + 4j; the wave then takes them in turn)
     constexpr int kPerWave = kQW / (kBlock / kWave);
-    int cj = lane < kPerWave ? (int)cnt[wid + (kBlock / kWave) * lane] : 0;
-    uint64_t todo = __ballot(lane < kPerWave && cj > P && cj > cap - check_every * kChunk);
+    const int qj = wid + (kBlock / kWave) * lane;
+    const int cj = lane < kPerWave ? (int)cnt[qj] : 0;
+    uint64_t todo = __ballot(lane < kPerWave && cj > P &&
+                             (cj > cap - check_every * kChunk || tau[qj] == ~0ull));
     while (todo) {
       const int j = __ffsll((long long)todo) - 1;
       todo &= todo - 1ull;
       const int ql = wid + (kBlock / kWave) * j;
       const int c = __shfl(cj, j, kWave);
-      {
-        uint64_t* g = A.buf + ((q0 + ql) * A.slices + slice) * cap;
-        uint64_t* sb = sortmem + (size_t)wid * A.sort_cap;
-        for (int i = lane; i < c; i += kWave)
-          sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wsync();
-        const uint64_t T = wave_select_cut(sb, c, P, s_hist[wid]);
-        for (int i = lane; i < P; i += kWave) g[i] = sb[i];
-        if (lane == 0) {
-          cnt[ql] = (uint32_t)P;
-          if (T < tau[ql]) {
-            tau[ql] = T;
-            tauf_s[ql] = __uint_as_float((uint32_t)(T >> 32));
-          }
-          if (A.gtau && qid[ql] >= 0) atomicMin(&A.gtau[q0 + ql], (unsigned long long)tau[ql]);
+      uint64_t* g = A.buf + ((q0 + ql) * S + slice) * cap;
+      uint64_t* sb = sortmem + (size_t)wid * A.sort_cap;
+      for (int i = lane; i < c; i += kWave)
+        sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      wsync();
+      const uint64_t T = wave_select_cut(sb, c, P, s_hist[wid]);
+      for (int i = lane; i < P; i += kWave) g[i] = sb[i];
+      if (lane == 0) {
+        cnt[ql] = (uint32_t)P;
+        if (T < tau[ql]) {
+          tau[ql] = T;
+          tauf_s[ql] = __uint_as_float((uint32_t)(T >> 32));
         }
-        wsync();
+        if (A.gtau && qid[ql] >= 0) atomicMin(&A.gtau[q0 + ql], (unsigned long long)tau[ql]);
       }
+      wsync();
     }
     __threadfence_block();
     __syncthreads();
+    // the tile's band: union of its queries' bands (bits of non-negative
+    // floats order like the floats)
+    if (threadIdx.x == 0) {
+      s_band[0] = __float_as_uint(INFINITY);
+      s_band[1] = 0u;
+    }
+    __syncthreads();
+    if (threadIdx.x < nvalid) {
+      float lo2, hi2;
+      norm_band(qn_s[threadIdx.x], tauf_s[threadIdx.x], lo2, hi2);
+      atomicMin(&s_band[0], __float_as_uint(lo2));
+      atomicMax(&s_band[1], __float_as_uint(hi2));
+    }
+    __syncthreads();
+    // close a direction whose next chunk lies wholly outside the band
+    // (norms rise upward: past that chunk every row is outside too)
+    if (threadIdx.x == 0) {
+      const float lo2 = __uint_as_float(s_band[0]), hi2 = __uint_as_float(s_band[1]);
+      int up = up_on, down = down_on;
+      const int64_t cu = c0 + slice + (int64_t)S * nu;
+      if (up && cu < A.nchunks && A.norm[cu * kChunk] > hi2) up = 0;
+      const int64_t cd = c0 - 1 - slice - (int64_t)S * nd;
+      if (down && cd >= 0) {
+        const int64_t last = cd * kChunk + kChunk - 1 < A.n ? cd * kChunk + kChunk - 1 : A.n - 1;
+        if (A.norm[last] < lo2) down = 0;
+      }
+      s_dir[0] = up;
+      s_dir[1] = down;
+    }
+    __syncthreads();
+    up_on = __builtin_amdgcn_readfirstlane(s_dir[0]);
+    down_on = __builtin_amdgcn_readfirstlane(s_dir[1]);
     refresh();
+    if (c_a < 0) break;  // the sequence ran dry (both directions closed)
   }
   // final pools of this slice
   for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
     if (qid[ql] < 0) continue;
     const int c = (int)cnt[ql];
-    uint64_t* g = A.buf + ((q0 + ql) * A.slices + slice) * cap;
+    uint64_t* g = A.buf + ((q0 + ql) * S + slice) * cap;
     uint64_t* sb = sortmem + (size_t)wid * A.sort_cap;
     for (int i = lane; i < c; i += kWave)
       sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     wsync();
     // one slice: the pool in ascending key order; several: the slice's P
     // best in any order (the merge selects across slices)
-    if (A.slices == 1)
+    if (S == 1)
       wave_sort_keys(sb, c);
     else if (c > P)
       (void)wave_select_cut(sb, c, P, s_hist[wid]);
     const int m = c < P ? c : P;
-    if (A.slices == 1) {
+    if (S == 1) {
+      const int64_t pos = qpos[ql];
       for (int i = lane; i < P; i += kWave) {
         const bool ok = i < m;
-        A.pool_ids[(q0 + ql) * P + i] = ok ? (int32_t)(uint32_t)sb[i] : -1;
-        A.pool_d2[(q0 + ql) * P + i] = ok ? __uint_as_float((uint32_t)(sb[i] >> 32)) : INFINITY;
+        A.pool_ids[pos * P + i] = ok ? (int32_t)(uint32_t)sb[i] : -1;
+        A.pool_d2[pos * P + i] = ok ? __uint_as_float((uint32_t)(sb[i] >> 32)) : INFINITY;
       }
     } else {
       // fixed-length slice pools (unordered), padded with the largest key
-      uint64_t* o = A.part + ((q0 + ql) * A.slices + slice) * P;
+      uint64_t* o = A.part + ((q0 + ql) * S + slice) * P;
       for (int i = lane; i < P; i += kWave) o[i] = i < m ? sb[i] : ~0ull;
     }
     wsync();
   }
 }
 
-// One work-group per query: the P smallest keys over all slice pools.
+// One work-group per query (sorted index): the P smallest keys over all
+// slice pools, written to the query's position.
 // Slice pools are P keys long, padded with ~0, which complement to 0: a
 // selected 0 is padding.
 __global__ void __launch_bounds__(kBlock)
 k_pp_merge(PoolArgs A) {
   __shared__ SelectSmem sm;
-  const int64_t qi = blockIdx.x;
+  const int64_t j = blockIdx.x;  // sorted index; the output row is its position
+  const int64_t qi = A.q_order[j];
   const int S = A.slices, P = A.P;
-  const uint64_t* base = A.part + qi * (int64_t)S * P;
+  const uint64_t* base = A.part + j * (int64_t)S * P;
   auto key = [&](int i) { return ~base[i]; };  // larger = better
   const int m = block_select_topk<kBlock>(key, S * P, P, sm);
   for (int i = threadIdx.x; i < P; i += kBlock) {
@@ -664,6 +828,21 @@ k_pp_rerank(RerankArgs A) {
   }
 }
 
+
+// Ascending sort of n (uint32 key, int32 value) pairs with hipCUB; tmp
+// holds the library's scratch.
+int sort_pairs(panther_ctx* c, DevBuf& tmp, const uint32_t* kin, uint32_t* kout,
+               const int32_t* vin, int32_t* vout, int64_t n, hipStream_t s) {
+  if (n <= 0) return PANTHER_OK;
+  size_t bytes = 0;
+  HIPTRY(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, 32, s),
+         "sort scratch size");
+  TRY(ctx_ensure(c, tmp, bytes, "sort scratch"));
+  HIPTRY(hipcub::DeviceRadixSort::SortPairs(tmp.p, bytes, kin, kout, vin, vout, (int)n, 0, 32, s),
+         "sort");
+  return PANTHER_OK;
+}
+
 }  // namespace
 
 int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
@@ -672,13 +851,43 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
   if (!pp || !c->d_theta || c->theta_D != D)
     return ctx_fail(c, PANTHER_ESTATE, "features for D = %d are not computed", D);
   if (pp->bf16_D == D) return PANTHER_OK;
-  const int64_t npad = ((int64_t)c->n + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk);
+  pp->bf16_D = 0;
+  const int64_t n = c->n;
+  // whole trips of chunks, and one all-padding chunk after them
+  const int64_t npad = (n + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk) + kChunk;
   TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)npad * kDP, "bf16 rows"));
   TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)npad, "bf16 norms"));
-  k_bf16_rows<<<(unsigned)((npad + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-      c->d_theta, c->n, npad, D, (float)c->R, static_cast<__bf16*>(pp->b_bf16.p),
-      static_cast<float*>(pp->b_norm.p));
-  HIPTRY(hipGetLastError(), "bf16 rows");
+  TRY(ctx_ensure(c, pp->b_sid, sizeof(int32_t) * (size_t)npad, "bf16 row ids"));
+  TRY(ctx_ensure(c, pp->b_rank, sizeof(int32_t) * (size_t)n, "bf16 row ranks"));
+  // norms as keys, sorted with the ids into (scratch keys, b_sid)
+  DevBuf keys, tmp;
+  int rc = ctx_ensure(c, keys, sizeof(uint32_t) * 2 * (size_t)n + sizeof(int32_t) * (size_t)n,
+                      "norm keys");
+  if (rc == PANTHER_OK) {
+    uint32_t* kin = static_cast<uint32_t*>(keys.p);
+    uint32_t* kout = kin + n;
+    int32_t* vin = reinterpret_cast<int32_t*>(kout + n);
+    k_bf16_norm_keys<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        c->d_theta, c->n, D, (float)c->R, kin, vin);
+    rc = hipGetLastError() == hipSuccess ? PANTHER_OK
+                                         : ctx_fail(c, PANTHER_EDEVICE, "bf16 norm keys");
+    if (rc == PANTHER_OK)
+      rc = sort_pairs(c, tmp, kin, kout, vin, static_cast<int32_t*>(pp->b_sid.p), n, s);
+    if (rc == PANTHER_OK) {
+      k_bf16_rows_sorted<<<(unsigned)((npad + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+          c->d_theta, c->n, npad, D, (float)c->R, static_cast<int32_t*>(pp->b_sid.p),
+          static_cast<__bf16*>(pp->b_bf16.p), static_cast<float*>(pp->b_norm.p),
+          static_cast<int32_t*>(pp->b_rank.p));
+      rc = hipGetLastError() == hipSuccess ? PANTHER_OK
+                                           : ctx_fail(c, PANTHER_EDEVICE, "bf16 rows");
+    }
+    // the scratch is freed only after the kernels that read it are done
+    if (hipStreamSynchronize(s) != hipSuccess && rc == PANTHER_OK)
+      rc = ctx_fail(c, PANTHER_EDEVICE, "bf16 rows");
+  }
+  ctx_release(keys);
+  ctx_release(tmp);
+  TRY(rc);
   TRY(ctx_ensure(c, pp->b_dbmax, 64, "row bounds"));
   HIPTRY(hipMemsetAsync(pp->b_dbmax.p, 0, 64, s), "row bounds");
   k_row_bounds<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
@@ -721,8 +930,6 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
   S = std::min<int64_t>(S, std::max<int64_t>(1, c->n / 4096));
   S = std::min<int64_t>(S, std::max<int64_t>(1, 262144 / P));  // bounds the merge work
-  const int64_t rps =
-      ((c->n + S - 1) / S + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk);
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
   const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;
   const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
@@ -740,10 +947,28 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   HIPTRY(hipMemsetAsync(lane->b_stats.p, 0, 64, s), "pp stats");
   int sort_cap = 2;
   while (sort_cap < cap) sort_cap <<= 1;
-  PoolArgs pa{static_cast<const __bf16*>(pp->b_bf16.p), static_cast<const float*>(pp->b_norm.p),
-              c->n, dq, nq, P, cap, (int32_t)S, (int32_t)rps, sort_cap, buf, part,
-              pool_ids, pool_d2, static_cast<const __bf16*>(pp->b_bf16.p),
-              static_cast<const float*>(pp->b_norm.p), 0, 1, gtau};
+  const int64_t npad =
+      ((int64_t)c->n + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk);
+  PoolArgs pa{};
+  pa.rows = static_cast<const __bf16*>(pp->b_bf16.p);
+  pa.norm = static_cast<const float*>(pp->b_norm.p);
+  pa.sid = static_cast<const int32_t*>(pp->b_sid.p);
+  pa.rank = static_cast<const int32_t*>(pp->b_rank.p);
+  pa.n = c->n;
+  pa.nchunks = npad / kChunk;
+  pa.queries = dq;
+  pa.nq = nq;
+  pa.P = P;
+  pa.cap = cap;
+  pa.slices = (int32_t)S;
+  pa.sort_cap = sort_cap;
+  pa.buf = buf;
+  pa.part = part;
+  pa.pool_ids = pool_ids;
+  pa.pool_d2 = pool_d2;
+  pa.q_by_pos = 0;
+  pa.exclude_self = 1;
+  pa.gtau = gtau;
   if (gtau) {
     k_fill_u64<<<(unsigned)((nq + kBlock - 1) / kBlock), kBlock, 0, s>>>(gtau, nq, ~0ull);
     HIPTRY(hipGetLastError(), "pool bounds");
@@ -760,6 +985,22 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
     pa.qnorm = qn;
     pa.q_by_pos = 1;
     pa.exclude_self = 0;
+  }
+  // query positions in ascending order of operand norm (tiles of similar
+  // norms keep their bands narrow)
+  {
+    const size_t half = ((size_t)nq + 63) / 64 * 64;
+    TRY(ctx_ensure(c, lane->b_qsort, (2 * sizeof(uint32_t) + 2 * sizeof(int32_t)) * half,
+                   "query order"));
+    uint32_t* kin = static_cast<uint32_t*>(lane->b_qsort.p);
+    uint32_t* kout = kin + half;
+    int32_t* vin = reinterpret_cast<int32_t*>(kout + half);
+    int32_t* vout = vin + half;
+    k_query_norm_keys<<<(unsigned)((nq + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        pa.norm, pa.rank, pa.qnorm, dq, nq, kin, vin);
+    HIPTRY(hipGetLastError(), "query order");
+    TRY(sort_pairs(c, lane->b_qsort_tmp, kin, kout, vin, vout, nq, s));
+    pa.q_order = vout;
   }
   const size_t sort_lds = sizeof(uint64_t) * (size_t)sort_cap * (kBlock / kWave);
   HIPTRY(hipFuncSetAttribute((const void*)k_pp_pool, hipFuncAttributeMaxDynamicSharedMemorySize,

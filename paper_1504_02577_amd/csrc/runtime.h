@@ -27,6 +27,7 @@ struct PinnedBuf {
 // Panther++ data shared by every lane: bf16 copy of theta and its norms.
 struct PPState {
   DevBuf b_bf16, b_norm, b_iota;
+  DevBuf b_sid, b_rank;  // BF16 rows in norm order: original id per row, row per id
   DevBuf b_dbmax;  // float: an upper bound on max_v |theta_v| (Euclidean)
   int32_t bf16_D = 0;
 };
@@ -36,7 +37,7 @@ struct PPState {
 // over the same read-only graph, paths, index and features.
 struct Lane {
   BatchState* batch = nullptr;
-  DevBuf b_qlen, b_pool, b_out, b_stats, b_q, b_qrows, b_fb, b_fbw;
+  DevBuf b_qlen, b_pool, b_out, b_stats, b_q, b_qrows, b_fb, b_fbw, b_qsort, b_qsort_tmp;
   int64_t stat_nq = 0;        // queries of the last BF16-form call
   int64_t stat_fallback = 0;  // of them, recomputed exactly (boundary not certified)
   PinnedBuf h_qlen;  // path-list lengths of the last call's queries

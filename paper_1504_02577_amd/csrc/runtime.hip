@@ -670,7 +670,8 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
 void free_lane(Lane* lane) {
   free_batch_state(lane);
   for (DevBuf* b : {&lane->b_qlen, &lane->b_pool, &lane->b_out, &lane->b_stats, &lane->b_q,
-                    &lane->b_qrows, &lane->b_fb, &lane->b_fbw})
+                    &lane->b_qrows, &lane->b_fb, &lane->b_fbw, &lane->b_qsort,
+                    &lane->b_qsort_tmp})
     ctx_release(*b);
   pinned_release(lane->h_qlen);
   lane->have_stats = false;
