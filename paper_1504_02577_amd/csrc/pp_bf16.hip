@@ -75,27 +75,60 @@ k_bf16_norm_keys(const float* __restrict__ theta, int32_t n, int32_t D, float s,
   ids[v] = v;
 }
 
-// bf16 rows (scaled by s) in ascending norm order: position i holds vertex
-// sid[i] with its FP32 norm; rank[v] is v's position.  Positions n .. npad-1
-// (the tail of the last trip of chunks) are zero rows with a NaN norm and
-// id INT32_MAX.
+// Rows of norm 0 are all equal, and a zero row is at d2~ = |b_q|^2 from
+// every query, so only the zero rows of the smallest ids can enter a pool:
+// beyond the first kZeroKeep of them (P <= 1024, plus the query itself),
+// every zero row has at least P zero rows of smaller id, hence of smaller
+// key, and the pool of the rows kept equals the pool of all rows.
+constexpr int64_t kZeroKeep = 1025;
+
 __global__ void __launch_bounds__(kBlock)
-k_bf16_rows_sorted(const float* __restrict__ theta, int32_t n, int64_t npad, int32_t D, float s,
+k_count_zero(const uint32_t* __restrict__ keys, int64_t n, unsigned long long* out) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool z = i < n && keys[i] == 0u;
+  const uint64_t m = __ballot(z);
+  if ((threadIdx.x & (kWave - 1)) == 0 && m) atomicAdd(out, (unsigned long long)__popcll(m));
+}
+
+// bf16 rows (scaled by s) in ascending norm order.  Source position i of
+// the sorted order (vertex order[i]) goes to row i, or i - drop past the
+// kept zero rows [0, zk); the dropped zero rows [zk, zk + drop) keep rank 0
+// (a zero row, the same operand).  sid[row] is the row's vertex, rank[v]
+// its row.
+__global__ void __launch_bounds__(kBlock)
+k_bf16_rows_sorted(const float* __restrict__ theta, int32_t n, int32_t D, float s,
+                   const int32_t* __restrict__ order, int64_t zk, int64_t drop,
                    int32_t* __restrict__ sid, __bf16* __restrict__ out, float* __restrict__ norm,
                    int32_t* __restrict__ rank) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= npad) return;
-  const int32_t v = i < n ? sid[i] : -1;
+  if (i >= n) return;
+  const int32_t v = order[i];
+  if (i >= zk && i < zk + drop) {
+    rank[v] = 0;
+    return;
+  }
+  const int64_t row = i < zk ? i : i - drop;
   float acc = 0.f;
   for (int d = 0; d < kDP; ++d) {
-    const __bf16 b = d < D && v >= 0 ? (__bf16)(theta[(int64_t)v * D + d] * s) : (__bf16)0.f;
-    out[i * kDP + d] = b;
+    const __bf16 b = d < D ? (__bf16)(theta[(int64_t)v * D + d] * s) : (__bf16)0.f;
+    out[row * kDP + d] = b;
     const float f = (float)b;
     acc = fmaf(f, f, acc);
   }
-  norm[i] = v >= 0 ? acc : __builtin_nanf("");
-  if (v >= 0) rank[v] = (int32_t)i;
-  else sid[i] = 0x7FFFFFFF;
+  norm[row] = acc;
+  sid[row] = v;
+  rank[v] = (int32_t)row;
+}
+
+// padding rows [n_rows, npad): zero, NaN norm, id INT32_MAX
+__global__ void __launch_bounds__(kBlock)
+k_bf16_pad_rows(int64_t n_rows, int64_t npad, int32_t* __restrict__ sid, __bf16* __restrict__ out,
+                float* __restrict__ norm) {
+  const int64_t i = n_rows + (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= npad) return;
+  for (int d = 0; d < kDP; ++d) out[i * kDP + d] = (__bf16)0.f;
+  norm[i] = __builtin_nanf("");
+  sid[i] = 0x7FFFFFFF;
 }
 
 // sort keys for the queries: norm of each query position's operand
@@ -263,8 +296,8 @@ struct PoolArgs {
   const __bf16* rows;    // [npad][64] database rows in ascending norm order
   const float* norm;     // [npad] their FP32 norms (NaN past n)
   const int32_t* sid;    // [npad] original id of each row (INT32_MAX past n)
-  const int32_t* rank;   // [n] position of each original id
-  int32_t n;
+  const int32_t* rank;   // [vertices] row of each original id (a zero row if dropped)
+  int32_t n;             // database rows (zero rows past the kept ones dropped)
   int64_t nchunks;       // chunks of rows (whole trips); chunk nchunks is all padding
   const int32_t* queries;
   const int32_t* q_order;// query positions in ascending order of operand norm
@@ -853,33 +886,53 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
   if (pp->bf16_D == D) return PANTHER_OK;
   pp->bf16_D = 0;
   const int64_t n = c->n;
-  // whole trips of chunks, and one all-padding chunk after them
-  const int64_t npad = (n + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk) + kChunk;
-  TRY(ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)npad * kDP, "bf16 rows"));
-  TRY(ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)npad, "bf16 norms"));
-  TRY(ctx_ensure(c, pp->b_sid, sizeof(int32_t) * (size_t)npad, "bf16 row ids"));
-  TRY(ctx_ensure(c, pp->b_rank, sizeof(int32_t) * (size_t)n, "bf16 row ranks"));
-  // norms as keys, sorted with the ids into (scratch keys, b_sid)
+  // norms as keys, sorted with the vertex ids; then the zero rows past
+  // kZeroKeep are dropped and the rest written in that order
   DevBuf keys, tmp;
-  int rc = ctx_ensure(c, keys, sizeof(uint32_t) * 2 * (size_t)n + sizeof(int32_t) * (size_t)n,
+  int64_t rows = n;
+  int rc = ctx_ensure(c, keys, sizeof(uint32_t) * 2 * (size_t)n + sizeof(int32_t) * 2 * (size_t)n + 64,
                       "norm keys");
   if (rc == PANTHER_OK) {
     uint32_t* kin = static_cast<uint32_t*>(keys.p);
     uint32_t* kout = kin + n;
     int32_t* vin = reinterpret_cast<int32_t*>(kout + n);
-    k_bf16_norm_keys<<<(unsigned)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-        c->d_theta, c->n, D, (float)c->R, kin, vin);
+    int32_t* vout = vin + n;
+    unsigned long long* zc = reinterpret_cast<unsigned long long*>(vout + n);  // 16n bytes in
+    const unsigned g = (unsigned)((n + kBlock - 1) / kBlock);
+    k_bf16_norm_keys<<<g, kBlock, 0, s>>>(c->d_theta, c->n, D, (float)c->R, kin, vin);
     rc = hipGetLastError() == hipSuccess ? PANTHER_OK
                                          : ctx_fail(c, PANTHER_EDEVICE, "bf16 norm keys");
-    if (rc == PANTHER_OK)
-      rc = sort_pairs(c, tmp, kin, kout, vin, static_cast<int32_t*>(pp->b_sid.p), n, s);
+    if (rc == PANTHER_OK) rc = sort_pairs(c, tmp, kin, kout, vin, vout, n, s);
+    unsigned long long z = 0;
     if (rc == PANTHER_OK) {
-      k_bf16_rows_sorted<<<(unsigned)((npad + kBlock - 1) / kBlock), kBlock, 0, s>>>(
-          c->d_theta, c->n, npad, D, (float)c->R, static_cast<int32_t*>(pp->b_sid.p),
-          static_cast<__bf16*>(pp->b_bf16.p), static_cast<float*>(pp->b_norm.p),
-          static_cast<int32_t*>(pp->b_rank.p));
-      rc = hipGetLastError() == hipSuccess ? PANTHER_OK
-                                           : ctx_fail(c, PANTHER_EDEVICE, "bf16 rows");
+      if (hipMemsetAsync(zc, 0, sizeof z, s) != hipSuccess) rc = ctx_fail(c, PANTHER_EDEVICE, "zero rows");
+      if (rc == PANTHER_OK) k_count_zero<<<g, kBlock, 0, s>>>(kout, n, zc);
+      if (rc == PANTHER_OK && (hipMemcpyAsync(&z, zc, sizeof z, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                               hipStreamSynchronize(s) != hipSuccess))
+        rc = ctx_fail(c, PANTHER_EDEVICE, "zero rows");
+    }
+    if (rc == PANTHER_OK) {
+      const int64_t zk = std::min<int64_t>((int64_t)z, kZeroKeep);
+      const int64_t drop = (int64_t)z - zk;
+      rows = n - drop;
+      // whole trips of chunks, and one all-padding chunk after them
+      const int64_t npad =
+          (rows + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk) + kChunk;
+      rc = ctx_ensure(c, pp->b_bf16, sizeof(__bf16) * (size_t)npad * kDP, "bf16 rows");
+      if (rc == PANTHER_OK) rc = ctx_ensure(c, pp->b_norm, sizeof(float) * (size_t)npad, "bf16 norms");
+      if (rc == PANTHER_OK) rc = ctx_ensure(c, pp->b_sid, sizeof(int32_t) * (size_t)npad, "bf16 row ids");
+      if (rc == PANTHER_OK) rc = ctx_ensure(c, pp->b_rank, sizeof(int32_t) * (size_t)n, "bf16 row ranks");
+      if (rc == PANTHER_OK) {
+        k_bf16_rows_sorted<<<g, kBlock, 0, s>>>(
+            c->d_theta, c->n, D, (float)c->R, vout, zk, drop, static_cast<int32_t*>(pp->b_sid.p),
+            static_cast<__bf16*>(pp->b_bf16.p), static_cast<float*>(pp->b_norm.p),
+            static_cast<int32_t*>(pp->b_rank.p));
+        k_bf16_pad_rows<<<(unsigned)((npad - rows + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+            rows, npad, static_cast<int32_t*>(pp->b_sid.p), static_cast<__bf16*>(pp->b_bf16.p),
+            static_cast<float*>(pp->b_norm.p));
+        rc = hipGetLastError() == hipSuccess ? PANTHER_OK
+                                             : ctx_fail(c, PANTHER_EDEVICE, "bf16 rows");
+      }
     }
     // the scratch is freed only after the kernels that read it are done
     if (hipStreamSynchronize(s) != hipSuccess && rc == PANTHER_OK)
@@ -888,6 +941,7 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
   ctx_release(keys);
   ctx_release(tmp);
   TRY(rc);
+  pp->bf16_rows = rows;
   TRY(ctx_ensure(c, pp->b_dbmax, 64, "row bounds"));
   HIPTRY(hipMemsetAsync(pp->b_dbmax.p, 0, 64, s), "row bounds");
   k_row_bounds<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
@@ -928,7 +982,7 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   const int64_t tiles = (nq + kQW - 1) / kQW;
   int64_t S = (2 * (int64_t)c->num_cus + tiles - 1) / tiles;
   S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
-  S = std::min<int64_t>(S, std::max<int64_t>(1, c->n / 4096));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, pp->bf16_rows / 4096));
   S = std::min<int64_t>(S, std::max<int64_t>(1, 262144 / P));  // bounds the merge work
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
   const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;
@@ -947,15 +1001,15 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   HIPTRY(hipMemsetAsync(lane->b_stats.p, 0, 64, s), "pp stats");
   int sort_cap = 2;
   while (sort_cap < cap) sort_cap <<= 1;
-  const int64_t npad =
-      ((int64_t)c->n + kTrip * kChunk - 1) / (kTrip * kChunk) * (kTrip * kChunk);
+  const int64_t rows = pp->bf16_rows;
+  const int64_t nchunks = (rows + kTrip * kChunk - 1) / (kTrip * kChunk) * kTrip;
   PoolArgs pa{};
   pa.rows = static_cast<const __bf16*>(pp->b_bf16.p);
   pa.norm = static_cast<const float*>(pp->b_norm.p);
   pa.sid = static_cast<const int32_t*>(pp->b_sid.p);
   pa.rank = static_cast<const int32_t*>(pp->b_rank.p);
-  pa.n = c->n;
-  pa.nchunks = npad / kChunk;
+  pa.n = (int32_t)rows;
+  pa.nchunks = nchunks;
   pa.queries = dq;
   pa.nq = nq;
   pa.P = P;

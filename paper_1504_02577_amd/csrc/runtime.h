@@ -30,6 +30,7 @@ struct PPState {
   DevBuf b_sid, b_rank;  // BF16 rows in norm order: original id per row, row per id
   DevBuf b_dbmax;  // float: an upper bound on max_v |theta_v| (Euclidean)
   int32_t bf16_D = 0;
+  int64_t bf16_rows = 0;  // rows of the norm-ordered BF16 database
 };
 
 // Scratch of one query stream.  The context's own calls use lane 0; the

@@ -107,10 +107,14 @@ def test_knn_rmat14(P, oracle, inputs, rmat, form, pool):
     P.set_option("pp.form", form)
     P.set_option("pp.pool", pool)
     theta = oracle.features(g.n, paths, inv_ptr, inv_pid, 50)
-    # queries from the start set plus some isolated vertices (zero rows)
+    # queries from the start set plus isolated vertices (zero rows) of the
+    # smallest and the largest ids (the BF16 database keeps only the first
+    # zero rows)
     starts = oracle.start_set(g)
     rng = np.random.default_rng(4)
-    iso = np.setdiff1d(np.arange(g.n), starts)[:20]
+    iso_all = np.setdiff1d(np.arange(g.n), starts)
+    assert len(iso_all) > 1100
+    iso = np.concatenate([iso_all[:10], iso_all[-10:]])
     q = np.concatenate([rng.choice(starts, 700, replace=False), iso]).astype(np.int32)
     wi, wd = oracle.knn(theta, q, 20)
     gi, gd = P.pp_topk(q, 50, 20)
