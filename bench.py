@@ -443,8 +443,10 @@ def bench_pp(args):
     fids, fdist = P.pp_topk(sub, D, k)
     fp64_s = time.perf_counter() - t
     agree = float((fids == bf16_ids[:1024]).mean())
-    n_pad = g.n
-    flops = 2.0 * len(q) * n_pad * 64
+    # products actually computed by the pool pass (the norm-band search
+    # skips the rest), each a 64-term bf16 dot product
+    scanned = P.pp_scanned()
+    flops = 2.0 * len(q) * g.n * scanned * 64
     achieved = flops / (pp_ms * 1e-3) / 1e12
     res = {
         "metric": "Panther++ queries/s", "value": len(q) / min(times), "unit": "queries/s",
@@ -456,6 +458,7 @@ def bench_pp(args):
         "features_ms": feat_ms, "pp_kernels_ms": pp_ms,
         "pre_rerank_recall": rec, "bf16_max_rel_err": err,
         "certified_queries": cert_nq - cert_redo, "recomputed_exactly": cert_redo,
+        "pool_scanned_fraction": scanned,
         "fp64_form_queries_per_s": len(sub) / fp64_s,
         "fp64_vs_bf16_id_agreement_1024": agree,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",

@@ -211,12 +211,22 @@ int panther_pp_stats(panther_ctx *ctx, double *max_rel_err,
  * most a bound from the rounding of the bfloat16 rows (2^-8 relative per
  * coordinate) and of the FP32 evaluation; when the pool's largest minus
  * that bound exceeds the k-th exact distance the result is certified
- * exact, otherwise the query is recomputed by the exact FP64 brute force.
- * Either way the returned neighbours equal the FP64 form's.  *queries gets
- * the call's query count, *recomputed how many were recomputed.
+ * exact, otherwise the query is recomputed exactly in FP64 (every row
+ * within its norm band compared with the pool's k-th exact pair).  Either
+ * way the returned neighbours equal the FP64 form's.  *queries gets the
+ * call's query count, *recomputed how many were recomputed.
  * ESTATE if no such call. */
 int panther_pp_certified(panther_ctx *ctx, int64_t *queries,
                          int64_t *recomputed);
+
+/* Pruning of the most recent BF16-form call on this context (the kd-tree's
+ * role in Sec. 3.3): *fraction = (query, row) products its pool pass
+ * computed / (queries * vertices).  The database is scanned in ascending
+ * norm order outward from each query tile, and a direction stops where the
+ * rows' norms leave every query's band (norm +- the radius of its current
+ * P-th candidate, widened by the BF16 rounding bound), so the pool equals
+ * a full scan's.  ESTATE if no such call; EINVAL for a null pointer. */
+int panther_pp_scanned(panther_ctx *ctx, double *fraction);
 
 /* Device time of the stages of the most recent calls, in milliseconds,
  * measured with HIP events on the stream each stage ran on, when the

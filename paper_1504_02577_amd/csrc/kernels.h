@@ -103,4 +103,30 @@ void launch_iota(int32_t* out, int32_t n, hipStream_t s);
 void launch_query_lengths(const uint64_t* inv_ptr, const int32_t* queries, int64_t nq,
                           uint64_t* out, hipStream_t s);
 
+// A norm-ordered copy of a kNN database: rows p < rows in ascending order
+// of their stored squared norm norm_s[p] (units scaled by scale), vertex
+// sid[p]; err bounds the distance between a stored row and scale * theta_v.
+struct KnnBand {
+  const float* norm_s;
+  const int32_t* sid;
+  int64_t rows;
+  double scale;
+  double err;
+};
+
+// Exact recompute of listed queries from a known bound (knn.hip): rows[i]
+// (i < nr) names the output row of query queries[rows[i]], and (tau_d[i],
+// tau_v[i]) is an exact (d2, id) pair that at least k rows reach.  work:
+// device memory of knn_range_bytes(nr) bytes.  band (may be null): scan
+// only each query's norm band of that copy (whose rows must include every
+// candidate).  A list keeps up to min(cap, 4096) candidates; lists that
+// outgrow it are recomputed by the full brute force.
+size_t knn_range_bytes(int64_t nr);
+int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* qtheta,
+                         bool exclude_self, const int32_t* queries, const int32_t* rows,
+                         int64_t nr, const double* tau_d, const int32_t* tau_v, int32_t k,
+                         int num_cus, void* work, unsigned long long* ov_n_dev,
+                         int32_t* out_ids, double* out_dist, hipStream_t s, uint32_t cap,
+                         const KnnBand* band);
+
 }  // namespace panther

@@ -215,6 +215,83 @@ k_knn_range(const float* __restrict__ theta, int32_t n, int32_t D,
 
 constexpr int kSelCap = 4096;
 
+// Norm band of each listed query over a norm-ordered copy of the database
+// (rows of norm^2 norm_s[0 .. rows), ascending, in units scaled by s, each
+// within err of the scaled row s * theta_v).  A row whose exact distance to
+// the query is at most d_k = sqrt(tau_d) has | |s theta_v| - s |theta_q| | <=
+// s d_k, so its stored norm lies in [s(|theta_q| - d_k) - err, s(|theta_q|
+// + d_k) + err], widened here by 2^-15 (|theta_q| + d_k + err) for the FP32
+// rows, 2^-15 relative on the squared norms (FP32 sums) and 10^-9 on d_k
+// (the FP64 distances).  Output: the band's rows [a, b).
+__global__ void __launch_bounds__(kBlock)
+k_knn_band(const float* __restrict__ qtheta, int32_t D, const int32_t* __restrict__ queries,
+           const int32_t* __restrict__ rows, int64_t nr, const double* __restrict__ tau_d,
+           const float* __restrict__ norm_s, int64_t nrows, double scale, double err,
+           int64_t* __restrict__ band) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nr) return;
+  const float* tq = qtheta + (int64_t)queries[rows[i]] * D;
+  double nq2 = 0.0;
+  for (int d = 0; d < D; ++d) nq2 = fma((double)tq[d], (double)tq[d], nq2);
+  const double rq = scale * sqrt(nq2), dk = scale * sqrt(tau_d[i]) * (1.0 + 1e-9);
+  const double slack = (rq + dk + err) * 3.0517578125e-05;  // FP32 rows and norms
+  const double lo = rq - dk - err - slack, hi = rq + dk + err + slack;
+  const float lo2 = lo > 0.0 ? (float)(lo * lo * (1.0 - 3.0517578125e-05)) : -1.f;
+  const float hi2 = (float)(hi * hi * (1.0 + 3.0517578125e-05));
+  // first row with norm >= lo2, first row with norm > hi2
+  int64_t a = 0, b = nrows;
+  while (a < b) {
+    const int64_t m = (a + b) >> 1;
+    if (norm_s[m] < lo2) a = m + 1;
+    else b = m;
+  }
+  int64_t e = a, f = nrows;
+  while (e < f) {
+    const int64_t m = (e + f) >> 1;
+    if (norm_s[m] <= hi2) e = m + 1;
+    else f = m;
+  }
+  band[2 * i] = a;
+  band[2 * i + 1] = e;
+}
+
+// The band form of k_knn_range: work-group (i, g) compares listed query i
+// with rows a_i + g*256 + t, stepping by G*256, of its band (vertex sid[p]).
+__global__ void __launch_bounds__(kBlock)
+k_knn_range_band(const float* __restrict__ theta, int32_t D, const float* __restrict__ qtheta,
+                 int32_t exclude_self, const int32_t* __restrict__ queries,
+                 const int32_t* __restrict__ rows, const double* __restrict__ tau_d,
+                 const int32_t* __restrict__ tau_v, const int64_t* __restrict__ band,
+                 const int32_t* __restrict__ sid, uint32_t cap, double* __restrict__ cand_d,
+                 int32_t* __restrict__ cand_v, unsigned int* __restrict__ cand_n) {
+  extern __shared__ __align__(16) char lds[];
+  double* qv = reinterpret_cast<double*>(lds);  // [D]
+  const int64_t i = blockIdx.x;
+  const int32_t me = queries[rows[i]];
+  for (int d = threadIdx.x; d < D; d += kBlock) qv[d] = (double)qtheta[(int64_t)me * D + d];
+  __syncthreads();
+  const double td = tau_d[i];
+  const int32_t tv = tau_v[i];
+  const int64_t b = band[2 * i + 1];
+  const int64_t stride = (int64_t)gridDim.y * kBlock;
+  for (int64_t p = band[2 * i] + (int64_t)blockIdx.y * kBlock + threadIdx.x; p < b; p += stride) {
+    const int32_t v = sid[p];
+    const float* row = theta + (int64_t)v * D;
+    double acc = 0.0;
+    for (int d = 0; d < D; ++d) {
+      const double delta = qv[d] - (double)row[d];
+      acc = fma(delta, delta, acc);
+    }
+    if ((!exclude_self || v != me) && (acc < td || (acc == td && v <= tv))) {
+      const unsigned pos = atomicAdd(&cand_n[i], 1u);
+      if (pos < cap) {
+        cand_d[i * cap + pos] = acc;
+        cand_v[i * cap + pos] = v;
+      }
+    }
+  }
+}
+
 // One work-group per listed query: sort its candidates by (d2, id) and
 // write the first k to output row rows[i].  A list that overflowed is left
 // alone and its index is appended to ov_list.
@@ -274,7 +351,7 @@ int launch_knn_fp64(const float* theta, int32_t n, int32_t D, const float* qthet
 
 size_t knn_range_bytes(int64_t nr) {
   return (sizeof(double) + sizeof(int32_t)) * (size_t)nr * kSelCap + sizeof(unsigned) * nr +
-         sizeof(int32_t) * nr + 256;
+         sizeof(int32_t) * nr + 2 * sizeof(int64_t) * nr + 256;
 }
 
 // Exact recompute of listed queries from a known bound: rows[i] (i < nr)
@@ -287,32 +364,51 @@ int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* 
                          bool exclude_self, const int32_t* queries, const int32_t* rows,
                          int64_t nr, const double* tau_d, const int32_t* tau_v, int32_t k,
                          int num_cus, void* work, unsigned long long* ov_n_dev,
-                         int32_t* out_ids, double* out_dist, hipStream_t s, uint32_t cap) {
+                         int32_t* out_ids, double* out_dist, hipStream_t s, uint32_t cap,
+                         const KnnBand* nb) {
   cap = std::min<uint32_t>(cap, kSelCap);
   constexpr int QF = 8;
   if (nr <= 0) return 0;
   char* w = static_cast<char*>(work);
   double* cand_d = reinterpret_cast<double*>(w);
   int32_t* cand_v = reinterpret_cast<int32_t*>(cand_d + (size_t)nr * kSelCap);
-  unsigned* cand_n = reinterpret_cast<unsigned*>(cand_v + (size_t)nr * kSelCap);
+  int64_t* band = reinterpret_cast<int64_t*>(cand_v + (size_t)nr * kSelCap);  // 8-aligned
+  unsigned* cand_n = reinterpret_cast<unsigned*>(band + 2 * nr);
   int32_t* ov_list = reinterpret_cast<int32_t*>(cand_n + nr);
   hipError_t e = hipMemsetAsync(cand_n, 0, sizeof(unsigned) * nr, s);
   if (e != hipSuccess) return (int)e;
   e = hipMemsetAsync(ov_n_dev, 0, sizeof(unsigned long long), s);
   if (e != hipSuccess) return (int)e;
-  const int64_t gx = (nr + QF - 1) / QF;
-  int64_t gy = std::max<int64_t>(1, (4 * (int64_t)num_cus + gx - 1) / gx);
-  gy = std::min<int64_t>(gy, std::max<int64_t>(1, ((int64_t)n + 4 * kBlock - 1) / (4 * kBlock)));
-  const int64_t rpw = ((int64_t)n + gy - 1) / gy;
-  const size_t lds = sizeof(double) * QF * D;
-  e = hipFuncSetAttribute((const void*)k_knn_range<QF>,
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return (int)e;
-  k_knn_range<QF><<<dim3((unsigned)gx, (unsigned)gy), kBlock, lds, s>>>(
-      theta, n, D, qtheta, exclude_self ? 1 : 0, queries, rows, nr, tau_d, tau_v, rpw,
-      cap, cand_d, cand_v, cand_n);
-  e = hipGetLastError();
-  if (e != hipSuccess) return (int)e;
+  if (nb) {
+    // rows in the norm order of a sorted copy, each query within its band
+    k_knn_band<<<(unsigned)((nr + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+        qtheta, D, queries, rows, nr, tau_d, nb->norm_s, nb->rows, nb->scale, nb->err, band);
+    e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(64, (4 * (int64_t)num_cus + nr - 1) / nr));
+    const size_t lds = sizeof(double) * D;
+    k_knn_range_band<<<dim3((unsigned)nr, (unsigned)gy), kBlock, lds, s>>>(
+        theta, D, qtheta, exclude_self ? 1 : 0, queries, rows, tau_d, tau_v, band, nb->sid, cap,
+        cand_d, cand_v, cand_n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+  }
+  if (!nb) {
+    // every row, 8 queries per work-group, rows split into slices
+    const int64_t gx = (nr + QF - 1) / QF;
+    int64_t gy = std::max<int64_t>(1, (4 * (int64_t)num_cus + gx - 1) / gx);
+    gy = std::min<int64_t>(gy, std::max<int64_t>(1, ((int64_t)n + 4 * kBlock - 1) / (4 * kBlock)));
+    const int64_t rpw = ((int64_t)n + gy - 1) / gy;
+    const size_t lds = sizeof(double) * QF * D;
+    e = hipFuncSetAttribute((const void*)k_knn_range<QF>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return (int)e;
+    k_knn_range<QF><<<dim3((unsigned)gx, (unsigned)gy), kBlock, lds, s>>>(
+        theta, n, D, qtheta, exclude_self ? 1 : 0, queries, rows, nr, tau_d, tau_v, rpw,
+        cap, cand_d, cand_v, cand_n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+  }
   k_knn_cand_select<<<(unsigned)nr, kBlock, 0, s>>>(rows, cand_d, cand_v, cand_n, cap, k,
                                                    out_ids, out_dist, ov_list, ov_n_dev);
   e = hipGetLastError();

@@ -241,6 +241,13 @@ extern "C" int panther_pp_certified(panther_ctx* c, int64_t* queries, int64_t* r
   return PANTHER_OK;
 }
 
+extern "C" int panther_pp_scanned(panther_ctx* c, double* fraction) {
+  if (!c || !fraction) return PANTHER_EINVAL;
+  if (!c->lane0.have_stats) return ctx_fail(c, PANTHER_ESTATE, "no BF16 Panther++ call");
+  *fraction = c->lane0.stat_scanned;
+  return PANTHER_OK;
+}
+
 extern "C" int panther_pp_stats(panther_ctx* c, double* max_rel_err, double* mean_pre_recall) {
   if (!c) return PANTHER_EINVAL;
   if (!c->lane0.have_stats) return ctx_fail(c, PANTHER_ESTATE, "no BF16 Panther++ call");

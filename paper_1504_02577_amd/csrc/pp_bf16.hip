@@ -320,6 +320,7 @@ struct PoolArgs {
   // slice has reached so far -- an upper bound on the query's P-th best key
   // overall, so every slice may drop keys at or above it
   unsigned long long* gtau;
+  unsigned long long* stat_products;  // += (query, row) products computed
 };
 
 // Norm band of one query for the current float threshold t (squared
@@ -626,6 +627,8 @@ k_pp_pool(PoolArgs A) {
     refresh();
     if (c_a < 0) break;  // the sequence ran dry (both directions closed)
   }
+  if (threadIdx.x == 0)
+    atomicAdd(A.stat_products, (unsigned long long)((nu + nd) * kChunk * nvalid));
   // final pools of this slice
   for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
     if (qid[ql] < 0) continue;
@@ -802,8 +805,9 @@ k_pp_rerank(RerankArgs A) {
   // here; r_v <= E for every row, and <= 2^-8 |x_v| <= 2^-8 (|x_q| + s d_k)
   // for a near row).  Rows of counts are integral in bfloat16 (a count
   // below 256 stays itself, a larger one rounds to an even integer), so
-  // when b_q is integral too and |b_q|^2 + |b_v|^2 < 2^24 the FP32
-  // evaluation is exact (delta = 0).  When moreover |x_q| + s d_k < 255,
+  // when b_q is integral too and |b_q|^2 + |b_v|^2 < 2^23 the FP32
+  // evaluation is exact (delta = 0: the result |b_q - b_v|^2 and every
+  // partial sum stay integers below 2^24).  When moreover |x_q| + s d_k < 255,
   // every near row has coordinates below 255, which bfloat16 keeps exactly
   // (x is count * (1 +- 2^-23)), so r_v <= 2^-22 (|x_q| + s d_k).  If
   // sqrt(a_P^2 - delta) - r_q - r_v > s d_k, no outside vertex can enter
@@ -839,9 +843,10 @@ k_pp_rerank(RerankArgs A) {
       } else {
         const double bq = xq * (1.0 + 1.0 / 256.0);
         const double bv = fmin(M, reach) * (1.0 + 1.0 / 256.0);
-        // integral rows whose norms and the sum stay below 2^24 are
-        // evaluated exactly in FP32
-        const bool exact = q_int && bq * bq + bv * bv < 16777216.0;
+        // integral rows with |b_q|^2 + |b_v|^2 < 2^23: every partial sum
+        // of the evaluation (in any order) is an integer below 2^24, exact
+        // in FP32
+        const bool exact = q_int && bq * bq + bv * bv < 8388608.0;
         const double delta = exact ? 0.0 : 3.0517578125e-05 * (bq * bq + bv * bv);
         const double rv = small ? 2.384185791015625e-07 * reach : fmin(E, reach / 128.0);
         const double a2 = (double)A.pool_d2[qi * P + P - 1];
@@ -947,18 +952,17 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
   k_row_bounds<<<(unsigned)((c->n + kBlock - 1) / kBlock), kBlock, 0, s>>>(
       c->d_theta, c->n, D, (float)c->R, static_cast<unsigned int*>(pp->b_dbmax.p));
   HIPTRY(hipGetLastError(), "row bounds");
+  float bounds[2];
+  HIPTRY(hipMemcpyAsync(bounds, pp->b_dbmax.p, sizeof bounds, hipMemcpyDeviceToHost, s),
+         "row bounds");
+  HIPTRY(hipStreamSynchronize(s), "row bounds");
+  pp->bf16_err = (double)bounds[1];
   pp->bf16_D = D;
   return PANTHER_OK;
 }
 
 namespace panther {
 
-size_t knn_range_bytes(int64_t nr);
-int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* qtheta,
-                         bool exclude_self, const int32_t* queries, const int32_t* rows,
-                         int64_t nr, const double* tau_d, const int32_t* tau_v, int32_t k,
-                         int num_cus, void* work, unsigned long long* ov_n_dev,
-                         int32_t* out_ids, double* out_dist, hipStream_t s, uint32_t cap);
 
 // Pool pass + rerank over the database context c.  qtheta (null: c's own
 // features) holds the queries' feature rows when they come from another
@@ -1023,6 +1027,7 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   pa.q_by_pos = 0;
   pa.exclude_self = 1;
   pa.gtau = gtau;
+  pa.stat_products = static_cast<unsigned long long*>(lane->b_stats.p) + 5;
   if (gtau) {
     k_fill_u64<<<(unsigned)((nq + kBlock - 1) / kBlock), kBlock, 0, s>>>(gtau, nq, ~0ull);
     HIPTRY(hipGetLastError(), "pool bounds");
@@ -1097,16 +1102,20 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   ra.stat_ret = st + 2;
   k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, 0, s>>>(ra);
   HIPTRY(hipGetLastError(), "pp rerank");
-  unsigned long long hs[4];
-  HIPTRY(hipMemcpyAsync(hs, st, 32, hipMemcpyDeviceToHost, s), "pp stats");
+  unsigned long long hs[6];
+  HIPTRY(hipMemcpyAsync(hs, st, sizeof hs, hipMemcpyDeviceToHost, s), "pp stats");
   HIPTRY(hipStreamSynchronize(s), "pp stats");
   // queries whose pool boundary is not certified: exact recompute
   if (hs[3] > 0) {
     TRY(ctx_ensure(c, lane->b_fbw, knn_range_bytes((int64_t)hs[3]), "exact recompute"));
+    // the norm-ordered BF16 rows bound each query's candidates (a dropped
+    // zero row is never needed: the kept zero rows of smaller id tie it)
+    KnnBand kb{static_cast<const float*>(pp->b_norm.p), static_cast<const int32_t*>(pp->b_sid.p),
+               pp->bf16_rows, (double)scale, pp->bf16_err};
     const int e = launch_knn_recompute(c->d_theta, c->n, D, qtheta ? qtheta : c->d_theta, !qtheta,
                                        dq, fb_list, (int64_t)hs[3], fb_tau_d, fb_tau_v, k,
                                        c->num_cus, lane->b_fbw.p, st + 4, d_ids, d_dist, s,
-                                       c->pp_recompute_all == 2 ? (uint32_t)(k - 1) : ~0u);
+                                       c->pp_recompute_all == 2 ? (uint32_t)(k - 1) : ~0u, &kb);
     HIPTRY((hipError_t)e, "pp exact recompute");
     HIPTRY(hipStreamSynchronize(s), "pp exact recompute");
   }
@@ -1117,6 +1126,7 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   lane->max_rel_err = e;
   lane->stat_nq = nq;
   lane->stat_fallback = (int64_t)hs[3];
+  lane->stat_scanned = (double)hs[5] / ((double)nq * (double)c->n);
   return PANTHER_OK;
 }
 

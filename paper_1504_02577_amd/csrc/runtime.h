@@ -31,6 +31,7 @@ struct PPState {
   DevBuf b_dbmax;  // float: an upper bound on max_v |theta_v| (Euclidean)
   int32_t bf16_D = 0;
   int64_t bf16_rows = 0;  // rows of the norm-ordered BF16 database
+  double bf16_err = 0.0;  // >= max over rows of |bf16 row - theta_v * R|
 };
 
 // Scratch of one query stream.  The context's own calls use lane 0; the
@@ -41,6 +42,7 @@ struct Lane {
   DevBuf b_qlen, b_pool, b_out, b_stats, b_q, b_qrows, b_fb, b_fbw, b_qsort, b_qsort_tmp;
   int64_t stat_nq = 0;        // queries of the last BF16-form call
   int64_t stat_fallback = 0;  // of them, recomputed exactly (boundary not certified)
+  double stat_scanned = 0.0;  // (query, row) products of its pool pass / (queries * vertices)
   PinnedBuf h_qlen;  // path-list lengths of the last call's queries
   bool have_stats = false;
   double max_rel_err = 0.0;

@@ -36,7 +36,7 @@ PANTHER_PP_BF16 = 1
 EXPORTS = [
     "panther_create", "panther_destroy", "panther_last_error", "panther_load_graph",
     "panther_sample_paths", "panther_topk_similar", "panther_topk_all", "panther_pp_topk",
-    "panther_pp_topk_cross", "panther_pp_certified",
+    "panther_pp_topk_cross", "panther_pp_certified", "panther_pp_scanned",
     "panther_sample_size", "panther_set_option", "panther_get_paths", "panther_index_nnz",
     "panther_get_index", "panther_get_features", "panther_pp_stats", "panther_synchronize",
     "panther_stage_times", "panther_server_start", "panther_server_submit",
@@ -97,6 +97,7 @@ def lib():
         "panther_get_features": (ctypes.c_int, [P, i32, P, ctypes.c_int]),
         "panther_pp_stats": (ctypes.c_int, [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
         "panther_pp_certified": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
+        "panther_pp_scanned": (ctypes.c_int, [P, ctypes.POINTER(ctypes.c_double)]),
         "panther_synchronize": (ctypes.c_int, [P]),
         "panther_stage_times": (ctypes.c_int, [P, ctypes.POINTER(dbl)]),
         "panther_server_start": (ctypes.c_int, [P, i64, i32, i32, i32, PP]),
@@ -450,6 +451,14 @@ class Panther:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         self._check(lib().panther_pp_certified(self.h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+
+    def pp_scanned(self):
+        """Fraction of the (query, row) products the last BF16-form pool pass
+        computed (norm-band pruning)."""
+        f = ctypes.c_double()
+        self._check(lib().panther_pp_scanned(self.h, ctypes.byref(f)))
+        return f.value
 
     def stage_times(self):
         """dict of stage -> device milliseconds (option "timing" must be on)."""

@@ -121,7 +121,10 @@ def test_knn_rmat14(P, oracle, inputs, rmat, form, pool):
     check_knn(gi, gd, wi, wd, f"rmat14 form={form} pool={pool}", exact_ids=True)
     if form == 1:
         nq, redo = P.pp_certified()
-        _say(f"  recomputed {redo}/{nq} (pool {pool})")
+        frac = P.pp_scanned()
+        _say(f"  recomputed {redo}/{nq} (pool {pool}), scanned {frac:.3f} of the products")
+        # padding rows of the last chunk count, dropped zero rows do not
+        assert 0.0 < frac <= 1.05
     P.set_option("pp.pool", 256)
 
 
