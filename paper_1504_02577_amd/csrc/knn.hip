@@ -216,13 +216,14 @@ k_knn_range(const float* __restrict__ theta, int32_t n, int32_t D,
 constexpr int kSelCap = 4096;
 
 // Norm band of each listed query over a norm-ordered copy of the database
-// (rows of norm^2 norm_s[0 .. rows), ascending, in units scaled by s, each
-// within err of the scaled row s * theta_v).  A row whose exact distance to
-// the query is at most d_k = sqrt(tau_d) has | |s theta_v| - s |theta_q| | <=
-// s d_k, so its stored norm lies in [s(|theta_q| - d_k) - err, s(|theta_q|
-// + d_k) + err], widened here by 2^-15 (|theta_q| + d_k + err) for the FP32
-// rows, 2^-15 relative on the squared norms (FP32 sums) and 10^-9 on d_k
-// (the FP64 distances).  Output: the band's rows [a, b).
+// (rows of norm^2 norm_s[0 .. rows), ascending, in units scaled by s; a
+// stored row is within min(err, 2^-8 |x|) of its scaled row x = s theta_v,
+// bfloat16 rounding each coordinate within 2^-8 relative).  A row whose
+// exact distance to the query is at most d_k = sqrt(tau_d) has |x| within
+// s d_k of s |theta_q|, so its stored norm lies in that interval widened by
+// the rounding bound at its ends, and here also by 2^-15 (s|theta_q| +
+// s d_k) for the FP32 rows, 2^-15 relative on the squared norms (FP32 sums)
+// and 10^-9 on d_k (the FP64 distances).  Output: the band's rows [a, b).
 __global__ void __launch_bounds__(kBlock)
 k_knn_band(const float* __restrict__ qtheta, int32_t D, const int32_t* __restrict__ queries,
            const int32_t* __restrict__ rows, int64_t nr, const double* __restrict__ tau_d,
@@ -234,8 +235,12 @@ k_knn_band(const float* __restrict__ qtheta, int32_t D, const int32_t* __restric
   double nq2 = 0.0;
   for (int d = 0; d < D; ++d) nq2 = fma((double)tq[d], (double)tq[d], nq2);
   const double rq = scale * sqrt(nq2), dk = scale * sqrt(tau_d[i]) * (1.0 + 1e-9);
-  const double slack = (rq + dk + err) * 3.0517578125e-05;  // FP32 rows and norms
-  const double lo = rq - dk - err - slack, hi = rq + dk + err + slack;
+  // a stored (bfloat16) row is within min(err, 2^-8 |x|) of its row x, and
+  // x - min(err, 2^-8 x), x + min(err, 2^-8 x) both increase with x
+  const double x0 = rq - dk > 0.0 ? rq - dk : 0.0, x1 = rq + dk;
+  const double slack = (rq + dk) * 3.0517578125e-05;  // FP32 rows and norms
+  const double lo = x0 - fmin(err, x0 * 0.00390625) - slack;
+  const double hi = x1 + fmin(err, x1 * 0.00390625) + slack;
   const float lo2 = lo > 0.0 ? (float)(lo * lo * (1.0 - 3.0517578125e-05)) : -1.f;
   const float hi2 = (float)(hi * hi * (1.0 + 3.0517578125e-05));
   // first row with norm >= lo2, first row with norm > hi2

@@ -50,6 +50,7 @@ constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
 constexpr int kTiles = kQW / 16;
 constexpr int kTrip = 2;        // chunks per loop trip (ping-pong operands)
 constexpr int kCheckEvery = 8;  // chunks between pool compaction checks (whole trips)
+constexpr int kBoundChunks = 32;  // chunks of the bound pass before a sliced scan
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -321,6 +322,11 @@ struct PoolArgs {
   // overall, so every slice may drop keys at or above it
   unsigned long long* gtau;
   unsigned long long* stat_products;  // += (query, row) products computed
+  // bound pass: stop after max_chunks chunks and publish, for each full
+  // pool, the key after its P-th to gtau instead of writing pools (at
+  // least P rows have keys below it: a valid exclusive bound)
+  int32_t max_chunks;    // 0: no limit
+  int32_t bound_only;
 };
 
 // Norm band of one query for the current float threshold t (squared
@@ -374,8 +380,15 @@ k_pp_pool(PoolArgs A) {
     qpos[i] = pos;
     qn_s[i] = q >= 0 ? (A.q_by_pos ? A.qnorm[pos] : A.norm[A.rank[q]]) : 0.f;
     cnt[i] = 0u;
-    tau[i] = ~0ull;
-    tauf_s[i] = q >= 0 ? INFINITY : -1.f;  // a missing query matches nothing
+    // start from the shared bound when there is one (a bound pass or
+    // other slices may have set it)
+    const unsigned long long gb =
+        q >= 0 && A.gtau && !A.bound_only
+            ? __hip_atomic_load(&A.gtau[q0 + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+            : ~0ull;
+    tau[i] = gb;
+    tauf_s[i] = q < 0 ? -1.f  // a missing query matches nothing
+                      : (gb == ~0ull ? INFINITY : __uint_as_float((uint32_t)(gb >> 32)));
   }
   if (threadIdx.x == 0) {
     s_band[0] = 0u;
@@ -544,11 +557,12 @@ k_pp_pool(PoolArgs A) {
     load_b(c_a, b0, nv0, id0);
     chunk(b1, nv1, id1);
     chunk_no += kTrip;
-    if (chunk_no % check_every != 0 && c_a >= 0) continue;
+    const bool last = c_a < 0 || (A.max_chunks && chunk_no >= A.max_chunks);
+    if (chunk_no % check_every != 0 && !last) continue;
     __threadfence_block();
     __syncthreads();
     // adopt the other slices' bound where it is tighter (one load per query)
-    if (A.gtau) {
+    if (A.gtau && !A.bound_only) {
       for (int ql = threadIdx.x; ql < kQW; ql += kBlock) {
         if (qid[ql] < 0) continue;
         const unsigned long long gb =
@@ -586,7 +600,10 @@ k_pp_pool(PoolArgs A) {
           tau[ql] = T;
           tauf_s[ql] = __uint_as_float((uint32_t)(T >> 32));
         }
-        if (A.gtau && qid[ql] >= 0) atomicMin(&A.gtau[q0 + ql], (unsigned long long)tau[ql]);
+        // (a slice keeps its P keys <= tau, so the others may drop keys >=
+        // tau; the bound pass keeps nothing and publishes only at its end)
+        if (A.gtau && !A.bound_only && qid[ql] >= 0)
+          atomicMin(&A.gtau[q0 + ql], (unsigned long long)tau[ql]);
       }
       wsync();
     }
@@ -625,10 +642,27 @@ k_pp_pool(PoolArgs A) {
     up_on = __builtin_amdgcn_readfirstlane(s_dir[0]);
     down_on = __builtin_amdgcn_readfirstlane(s_dir[1]);
     refresh();
-    if (c_a < 0) break;  // the sequence ran dry (both directions closed)
+    if (last) break;  // the sequence ran dry (both directions closed), or the budget
   }
   if (threadIdx.x == 0)
     atomicAdd(A.stat_products, (unsigned long long)((nu + nd) * kChunk * nvalid));
+  if (A.bound_only) {
+    for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
+      const int c = (int)cnt[ql];
+      if (qid[ql] < 0 || c < P) continue;
+      uint64_t* g = A.buf + ((q0 + ql) * S + slice) * cap;
+      uint64_t* sb = sortmem + (size_t)wid * A.sort_cap;
+      for (int i = lane; i < c; i += kWave)
+        sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      wsync();
+      // this pass keeps no pool, so the slices must keep keys equal to T
+      // too: publish the next key, T + 1 (ids stay below 2^31)
+      const uint64_t T = wave_select_cut(sb, c, P, s_hist[wid]);
+      if (lane == 0) atomicMin(&A.gtau[q0 + ql], (unsigned long long)(T + 1ull));
+      wsync();
+    }
+    return;
+  }
   // final pools of this slice
   for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
     if (qid[ql] < 0) continue;
@@ -682,6 +716,11 @@ k_pp_merge(PoolArgs A) {
   }
 }
 
+__host__ __device__ constexpr size_t rerank_lds_per_wave(int P, int D) {
+  return (sizeof(double) + sizeof(int32_t) + sizeof(float)) * (size_t)P +
+         sizeof(float) * (size_t)kWave * (size_t)(D + 1);
+}
+
 struct RerankArgs {
   const float* theta;    // [n][D] database rows
   const float* db_max;   // [0] >= max_v |theta_v|, [1] >= max_v of a row's bf16 rounding error
@@ -709,34 +748,45 @@ struct RerankArgs {
 // one wavefront per query
 __global__ void __launch_bounds__(kBlock)
 k_pp_rerank(RerankArgs A) {
-  __shared__ double sd[kBlock / kWave][1024];
-  __shared__ int32_t sv[kBlock / kWave][1024];
-  __shared__ float sa[kBlock / kWave][1024];
+  // per wavefront: d[P], v[P], ap[P], then a [64][D+1] tile of staged rows
+  extern __shared__ __align__(16) char rr_lds[];
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + wid;
   if (qi >= A.nq) return;
   const int32_t q = A.queries[qi];
-  const float* tq = A.qtheta + (int64_t)q * A.D;
-  const int P = A.P;
-  double* d = sd[wid];
-  int32_t* v = sv[wid];
-  float* ap = sa[wid];
-  for (int i = lane; i < P; i += kWave) {
-    const int32_t c = A.pool_ids[qi * P + i];
-    double s = INFINITY;
-    if (c >= 0) {
-      const float* tv = A.theta + (int64_t)c * A.D;
-      s = 0.0;
-      for (int j = 0; j < A.D; ++j) {
-        const double delta = (double)tq[j] - (double)tv[j];
-        s = fma(delta, delta, s);
-      }
+  const int P = A.P, D = A.D, DS = A.D + 1;
+  const float* tq = A.qtheta + (int64_t)q * D;
+  char* mine = rr_lds + (size_t)wid * rerank_lds_per_wave(P, D);
+  double* d = reinterpret_cast<double*>(mine);
+  int32_t* v = reinterpret_cast<int32_t*>(d + P);
+  float* ap = reinterpret_cast<float*>(v + P);
+  float* tile = ap + P;
+  // 64 pool members at a time: their rows are staged by whole-row loads
+  // (one row per instruction, D <= 64 lanes), then each lane runs the
+  // exact chain for its member from LDS
+  for (int b0 = 0; b0 < P; b0 += kWave) {
+    const int i = b0 + lane;
+    const int32_t c = i < P ? A.pool_ids[qi * P + i] : -1;
+    for (int r = 0; r < kWave; ++r) {
+      const int32_t cr = __shfl(c, r, kWave);
+      if (cr >= 0 && lane < D) tile[r * DS + lane] = A.theta[(int64_t)cr * D + lane];
     }
-    d[i] = s;
-    v[i] = c >= 0 ? c : 0x7FFFFFFF;
-    ap[i] = A.pool_d2[qi * P + i];
+    wsync();
+    if (i < P) {
+      double s = INFINITY;
+      if (c >= 0) {
+        s = 0.0;
+        for (int j = 0; j < D; ++j) {
+          const double delta = (double)tq[j] - (double)tile[lane * DS + j];
+          s = fma(delta, delta, s);
+        }
+      }
+      d[i] = s;
+      v[i] = c >= 0 ? c : 0x7FFFFFFF;
+      ap[i] = A.pool_d2[qi * P + i];
+    }
+    wsync();
   }
-  wsync();
   // pre-rerank top-k ids are pool entries 0..k-1 (pool is in key order)
   // count valid entries
   int valid = 0;
@@ -1065,6 +1115,18 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   HIPTRY(hipFuncSetAttribute((const void*)k_pp_pool, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)sort_lds),
          "pp pool attribute");
+  if (S > 1) {
+    // bound pass: one work-group per tile scans the kBoundChunks chunks
+    // nearest its median norm and publishes each query's P-th key, so that
+    // the slices start from a tight bound instead of each filling its own
+    // pool from the first rows
+    PoolArgs pb = pa;
+    pb.slices = 1;
+    pb.max_chunks = kBoundChunks;
+    pb.bound_only = 1;
+    k_pp_pool<<<dim3((unsigned)tiles, 1u), kBlock, sort_lds, s>>>(pb);
+    HIPTRY(hipGetLastError(), "pp pool bound");
+  }
   k_pp_pool<<<dim3((unsigned)tiles, (unsigned)S), kBlock, sort_lds, s>>>(pa);
   HIPTRY(hipGetLastError(), "pp pool");
   if (S > 1) {
@@ -1100,7 +1162,11 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   ra.stat_hits = st;
   ra.stat_err = st + 1;
   ra.stat_ret = st + 2;
-  k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, 0, s>>>(ra);
+  const size_t rr_lds = (kBlock / kWave) * rerank_lds_per_wave(P, D);
+  HIPTRY(hipFuncSetAttribute((const void*)k_pp_rerank, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)rr_lds),
+         "pp rerank attribute");
+  k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, rr_lds, s>>>(ra);
   HIPTRY(hipGetLastError(), "pp rerank");
   unsigned long long hs[6];
   HIPTRY(hipMemcpyAsync(hs, st, sizeof hs, hipMemcpyDeviceToHost, s), "pp stats");
