@@ -7,10 +7,10 @@
 //    accumulator.  FP32 row norms come from the same bfloat16 values.  The
 //    rows are stored in ascending order of norm (with each row's original
 //    id), and every call orders its queries by norm too.
-// 2. Pool pass: a work-group owns 128 queries of neighbouring norms and
+// 2. Pool pass: a work-group owns 16 or 32 queries of neighbouring norms and
 //    scans chunks of 64 database rows outward from the chunk where their
 //    median norm falls, alternately upward and downward.  Each wavefront
-//    computes 128 x 16 dot products per chunk with
+//    computes its queries' dot products with 16 rows per chunk with
 //    v_mfma_f32_16x16x32_bf16 (query operands stay in registers), turns
 //    them into d2~ = |b_q|^2 + |b_v|^2 - 2 <b_q, b_v>, and appends (d2~, v)
 //    keys below the query's threshold to that query's pool buffer in global
@@ -45,9 +45,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kDP = 64;        // padded feature width in bfloat16
-constexpr int kQW = 128;       // queries per work-group
 constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
-constexpr int kTiles = kQW / 16;
 constexpr int kTrip = 2;        // chunks per loop trip (ping-pong operands)
 constexpr int kCheckEvery = 8;  // chunks between pool compaction checks (whole trips)
 constexpr int kBoundChunks = 32;  // chunks of the bound pass before a sliced scan
@@ -352,28 +350,30 @@ __device__ __forceinline__ void norm_band(float qn, float t, float& lo2, float& 
   lo2 = lo > 0.f ? lo * lo * (1.f - 2.44140625e-4f) : 0.f;
 }
 
-// grid (query tiles, slices)
+// grid (query tiles of QW, slices)
+template <int QW>
 __global__ void __launch_bounds__(kBlock)
 k_pp_pool(PoolArgs A) {
-  __shared__ uint32_t cnt[kQW];
-  __shared__ uint64_t tau[kQW];
-  __shared__ float tauf_s[kQW];  // float part of tau, for the prefilter
-  __shared__ int32_t qid[kQW];
-  __shared__ int32_t qpos[kQW];
-  __shared__ float qn_s[kQW];
+  constexpr int kTiles = QW / 16;  // 16-query MFMA tiles per wavefront
+  __shared__ uint32_t cnt[QW];
+  __shared__ uint64_t tau[QW];
+  __shared__ float tauf_s[QW];  // float part of tau, for the prefilter
+  __shared__ int32_t qid[QW];
+  __shared__ int32_t qpos[QW];
+  __shared__ float qn_s[QW];
   __shared__ uint32_t s_band[2];  // float bits: band of the whole tile [lo2, hi2]
   __shared__ int32_t s_dir[2];    // directions still open: up, down
   __shared__ int64_t s_c0;        // chunk of the tile's median norm
   extern __shared__ __align__(16) uint64_t sortmem[];  // [waves][cap]
   __shared__ uint32_t s_hist[kBlock / kWave][256];     // per-wave radix select
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int64_t q0 = (int64_t)blockIdx.x * kQW;  // sorted index of the tile's first query
+  const int64_t q0 = (int64_t)blockIdx.x * QW;  // sorted index of the tile's first query
   const int slice = blockIdx.y;
   const int S = A.slices;
   const int P = A.P, cap = A.cap;
   const int check_every = kCheckEvery;
-  const int nvalid = (int)(A.nq - q0 < kQW ? A.nq - q0 : kQW);
-  for (int i = threadIdx.x; i < kQW; i += kBlock) {
+  const int nvalid = (int)(A.nq - q0 < QW ? A.nq - q0 : QW);
+  for (int i = threadIdx.x; i < QW; i += kBlock) {
     const int32_t pos = i < nvalid ? A.q_order[q0 + i] : -1;
     const int32_t q = pos >= 0 ? A.queries[pos] : -1;
     qid[i] = q;
@@ -563,7 +563,7 @@ k_pp_pool(PoolArgs A) {
     __syncthreads();
     // adopt the other slices' bound where it is tighter (one load per query)
     if (A.gtau && !A.bound_only) {
-      for (int ql = threadIdx.x; ql < kQW; ql += kBlock) {
+      for (int ql = threadIdx.x; ql < QW; ql += kBlock) {
         if (qid[ql] < 0) continue;
         const unsigned long long gb =
             __hip_atomic_load(&A.gtau[q0 + ql], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -577,7 +577,7 @@ k_pp_pool(PoolArgs A) {
     // cut back buffers that the next check_every chunks could overflow, or
     // (first cut) any buffer past P while its threshold is still open
     // (lane j looks at query wid + 4j; the wave then takes them in turn)
-    constexpr int kPerWave = kQW / (kBlock / kWave);
+    constexpr int kPerWave = QW / (kBlock / kWave);
     const int qj = wid + (kBlock / kWave) * lane;
     const int cj = lane < kPerWave ? (int)cnt[qj] : 0;
     uint64_t todo = __ballot(lane < kPerWave && cj > P &&
@@ -647,7 +647,7 @@ k_pp_pool(PoolArgs A) {
   if (threadIdx.x == 0)
     atomicAdd(A.stat_products, (unsigned long long)((nu + nd) * kChunk * nvalid));
   if (A.bound_only) {
-    for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
+    for (int ql = wid; ql < QW; ql += kBlock / kWave) {
       const int c = (int)cnt[ql];
       if (qid[ql] < 0 || c < P) continue;
       uint64_t* g = A.buf + ((q0 + ql) * S + slice) * cap;
@@ -664,7 +664,7 @@ k_pp_pool(PoolArgs A) {
     return;
   }
   // final pools of this slice
-  for (int ql = wid; ql < kQW; ql += kBlock / kWave) {
+  for (int ql = wid; ql < QW; ql += kBlock / kWave) {
     if (qid[ql] < 0) continue;
     const int c = (int)cnt[ql];
     uint64_t* g = A.buf + ((q0 + ql) * S + slice) * cap;
@@ -716,9 +716,11 @@ k_pp_merge(PoolArgs A) {
   }
 }
 
+// per wavefront: d, v, ap of P entries, then a tile of 64 rows of D + 1
+// floats (also holding up to 256 ids afterwards: k <= 256)
 __host__ __device__ constexpr size_t rerank_lds_per_wave(int P, int D) {
   return (sizeof(double) + sizeof(int32_t) + sizeof(float)) * (size_t)P +
-         sizeof(float) * (size_t)kWave * (size_t)(D + 1);
+         sizeof(float) * (kWave * (D + 1) > 256 ? (size_t)kWave * (size_t)(D + 1) : (size_t)256);
 }
 
 struct RerankArgs {
@@ -819,6 +821,10 @@ k_pp_rerank(RerankArgs A) {
   }
   const int k = A.k;
   const int m = valid < k ? valid : k;
+  // the pool order's first m ids, staged in the (now free) row tile
+  int32_t* first = reinterpret_cast<int32_t*>(tile);
+  for (int i = lane; i < m; i += kWave) first[i] = A.pool_ids[qi * P + i];
+  wsync();
   unsigned hits = 0;
   double err = 0.0;
   for (int j = lane; j < k; j += kWave) {
@@ -827,7 +833,7 @@ k_pp_rerank(RerankArgs A) {
     A.out_dist[qi * k + j] = ok ? sqrt(d[j]) : INFINITY;
     if (ok) {
       // was this id within the first k of the pool order?
-      for (int i = 0; i < m; ++i) hits += (A.pool_ids[qi * P + i] == v[j]) ? 1u : 0u;
+      for (int i = 0; i < m; ++i) hits += (first[i] == v[j]) ? 1u : 0u;
       const double approx = (double)ap[j] * (double)A.inv_s2;
       const double den = d[j] > (double)A.inv_s2 ? d[j] : (double)A.inv_s2;
       const double e = fabs(approx - d[j]) / den;
@@ -1031,9 +1037,13 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   // sort, and room for the kCheckEvery chunks between checks
   const int cap = 2 * P + kCheckEvery * kChunk;
   const float scale = (float)c->R;
-  // split the database into slices when the batch has few query tiles,
-  // so that about two work-groups per CU scan it
-  const int64_t tiles = (nq + kQW - 1) / kQW;
+  // Query tiles: 32 queries per work-group for large batches, 16 for
+  // small ones (a tile scans the union of its queries' norm bands, so
+  // narrower tiles scan fewer rows; wider ones reuse each row more).  The
+  // database is split into slices when the batch has few tiles, so that
+  // about two work-groups per CU scan it.
+  const int qw = nq >= 8192 ? 32 : 16;
+  const int64_t tiles = (nq + qw - 1) / qw;
   int64_t S = (2 * (int64_t)c->num_cus + tiles - 1) / tiles;
   S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
   S = std::min<int64_t>(S, std::max<int64_t>(1, pp->bf16_rows / 4096));
@@ -1112,9 +1122,15 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
     pa.q_order = vout;
   }
   const size_t sort_lds = sizeof(uint64_t) * (size_t)sort_cap * (kBlock / kWave);
-  HIPTRY(hipFuncSetAttribute((const void*)k_pp_pool, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             (int)sort_lds),
+  const void* pool_fn = qw == 32 ? (const void*)k_pp_pool<32> : (const void*)k_pp_pool<16>;
+  HIPTRY(hipFuncSetAttribute(pool_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_lds),
          "pp pool attribute");
+  auto launch_pool = [&](const PoolArgs& args, unsigned gy) {
+    if (qw == 32)
+      k_pp_pool<32><<<dim3((unsigned)tiles, gy), kBlock, sort_lds, s>>>(args);
+    else
+      k_pp_pool<16><<<dim3((unsigned)tiles, gy), kBlock, sort_lds, s>>>(args);
+  };
   if (S > 1) {
     // bound pass: one work-group per tile scans the kBoundChunks chunks
     // nearest its median norm and publishes each query's P-th key, so that
@@ -1124,10 +1140,10 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
     pb.slices = 1;
     pb.max_chunks = kBoundChunks;
     pb.bound_only = 1;
-    k_pp_pool<<<dim3((unsigned)tiles, 1u), kBlock, sort_lds, s>>>(pb);
+    launch_pool(pb, 1u);
     HIPTRY(hipGetLastError(), "pp pool bound");
   }
-  k_pp_pool<<<dim3((unsigned)tiles, (unsigned)S), kBlock, sort_lds, s>>>(pa);
+  launch_pool(pa, (unsigned)S);
   HIPTRY(hipGetLastError(), "pp pool");
   if (S > 1) {
     k_pp_merge<<<(unsigned)nq, kBlock, 0, s>>>(pa);

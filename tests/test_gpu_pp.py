@@ -128,6 +128,23 @@ def test_knn_rmat14(P, oracle, inputs, rmat, form, pool):
     P.set_option("pp.pool", 256)
 
 
+def test_knn_rmat14_large_batch(P, oracle, inputs, rmat):
+    """8,192 queries: the pool pass takes its wide-tile form (32 queries per
+    work-group, one slice); ids equal the oracle's."""
+    g, paths, inv_ptr, inv_pid = rmat
+    _say("case: knn rmat14 large batch")
+    P.load_graph(g)
+    P.sample_paths(5, 400_000, 7)
+    P.set_option("pp.form", 1)
+    theta = oracle.features(g.n, paths, inv_ptr, inv_pid, 50)
+    q = np.random.default_rng(6).choice(g.n, 8192, replace=False).astype(np.int32)
+    wi, wd = oracle.knn(theta, q, 20)
+    gi, gd = P.pp_topk(q, 50, 20)
+    check_knn(gi, gd, wi, wd, "rmat14 large batch", exact_ids=True)
+    nq, redo = P.pp_certified()
+    _say(f"  recomputed {redo}/{nq}, scanned {P.pp_scanned():.3f}")
+
+
 @pytest.mark.parametrize("mode,k", [(1, 20), (1, 200), (2, 20)])
 def test_knn_recompute_paths(P, oracle, inputs, rmat, mode, k):
     """Every full-pool query taken through the exact recompute (mode 1: the
