@@ -740,53 +740,55 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   if (b->tier_b_override >= 0) LB = std::min(LB, (uint64_t)b->tier_b_override);
   // the wave-tier sort buffer holds TA/2 keys and the block selection keeps
   // at most kCand keys without radix narrowing; both are covered by the
-  // load bound T * L <= table / 2
-  std::vector<std::pair<uint64_t, int32_t>> A, B, C;
+  // load bound T * L <= table / 2.  The LDS tiers are ordered by
+  // power-of-two length class, longest first (enough for load balance):
+  // a counting sort over (tier, class) in two passes, written straight
+  // into the pinned upload buffer; hubs go exactly longest-first.
+  auto cls = [](uint64_t L) { return L ? 64 - __builtin_clzll(L) : 0; };
+  size_t cnt[2][65] = {};
+  size_t nC = 0;
   for (int64_t i = 0; i < nq; ++i) {
     const uint64_t L = qlen[i];
-    if (L <= LA)
-      A.push_back({L, (int32_t)i});
-    else if (L <= LB)
-      B.push_back({L, (int32_t)i});
+    if (L > LB)
+      ++nC;
     else
-      C.push_back({L, (int32_t)i});
+      ++cnt[L > LA ? 0 : 1][cls(L)];  // tier 0: work-group (B), 1: wave (A)
   }
-  auto longest_first = [](const std::pair<uint64_t, int32_t>& x,
-                          const std::pair<uint64_t, int32_t>& y) {
-    return x.first != y.first ? x.first > y.first : x.second < y.second;
-  };
-  // hubs exactly longest-first; the LDS tiers by power-of-two length class
-  // (a stable counting sort, O(n)), which is enough for load balance
-  std::sort(C.begin(), C.end(), longest_first);
-  auto by_class = [](std::vector<std::pair<uint64_t, int32_t>>& v) {
-    size_t cnt[65] = {0};
-    auto cls = [](uint64_t L) { return L ? 64 - __builtin_clzll(L) : 0; };
-    for (auto& x : v) ++cnt[cls(x.first)];
-    size_t pos[65];
-    size_t run = 0;
+  size_t pos[2][65], nB = 0, need = 0;
+  for (int t = 0; t < 2; ++t) {
     for (int c2 = 64; c2 >= 0; --c2) {
-      pos[c2] = run;
-      run += cnt[c2];
+      pos[t][c2] = need;
+      need += cnt[t][c2];
     }
-    std::vector<std::pair<uint64_t, int32_t>> o(v.size());
-    for (auto& x : v) o[pos[cls(x.first)]++] = x;
-    v.swap(o);
-  };
-  by_class(B);
-  by_class(A);
-  if (!with_hubs) C.clear();
+    if (t == 0) nB = need;
+  }
   // the pinned staging of the previous plan must have been consumed
   if (b->upload_pending) {
     int st0 = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan");
     if (st0) return st0;
     b->upload_pending = false;
   }
-  int st = plan_hubs(c, b, C, dq, k, d_ids, d_counts, d_len, theta, s, &out->hub);
+  int st;
+  if (need && (st = pinned_ensure(c, b->pin_items, sizeof(int32_t) * need, "batch plan")))
+    return st;
+  int32_t* items = static_cast<int32_t*>(b->pin_items.p);
+  std::vector<std::pair<uint64_t, int32_t>> C;
+  C.reserve(with_hubs ? nC : 0);
+  for (int64_t i = 0; i < nq; ++i) {
+    const uint64_t L = qlen[i];
+    if (L > LB) {
+      if (with_hubs) C.push_back({L, (int32_t)i});
+    } else {
+      items[pos[L > LA ? 0 : 1][cls(L)]++] = (int32_t)i;
+    }
+  }
+  std::sort(C.begin(), C.end(),
+            [](const std::pair<uint64_t, int32_t>& x, const std::pair<uint64_t, int32_t>& y) {
+              return x.first != y.first ? x.first > y.first : x.second < y.second;
+            });
+  st = plan_hubs(c, b, C, dq, k, d_ids, d_counts, d_len, theta, s, &out->hub);
   if (st) return st;
   host_items->clear();
-  for (auto& x : B) host_items->push_back(x.second);
-  for (auto& x : A) host_items->push_back(x.second);
-  const size_t need = host_items->size();
   if ((st = grow(c, b->d_items, b->items_cap, std::max<size_t>(need, 1024), sizeof(int32_t),
                  "batch plan")))
     return st;
@@ -797,8 +799,6 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
     b->d_queue = static_cast<uint32_t*>(p);
   }
   if (need) {
-    if ((st = pinned_ensure(c, b->pin_items, sizeof(int32_t) * need, "batch plan"))) return st;
-    std::memcpy(b->pin_items.p, host_items->data(), sizeof(int32_t) * need);
     st = ctx_hip(c, hipMemcpyAsync(b->d_items, b->pin_items.p, sizeof(int32_t) * need,
                                    hipMemcpyHostToDevice, s),
                  "batch plan upload");
@@ -814,9 +814,9 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   BatchArgs a{};
   a.queries = dq;
   a.itemsB = b->d_items;
-  a.itemsA = b->d_items + B.size();
-  a.nB = (int32_t)B.size();
-  a.nA = (int32_t)A.size();
+  a.itemsA = b->d_items + nB;
+  a.nB = (int32_t)nB;
+  a.nA = (int32_t)(need - nB);
   a.inv_ptr = c->d_inv_ptr;
   a.inv_pid = c->d_inv_pid;
   a.paths = c->d_paths;
