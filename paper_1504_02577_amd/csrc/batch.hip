@@ -18,6 +18,7 @@
 // Counting is exact integer arithmetic and the ranking key (count desc, id
 // asc) is a total order, so the result equals the plain form bit for bit.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cstring>
 #include <cstdio>
@@ -25,6 +26,7 @@
 #include <fstream>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/panther.h"
@@ -744,24 +746,55 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   // power-of-two length class, longest first (enough for load balance):
   // a counting sort over (tier, class) in two passes, written straight
   // into the pinned upload buffer; hubs go exactly longest-first.
+  // Large batches split both passes over host threads (each thread takes a
+  // contiguous range of queries; positions are prefix sums over (tier,
+  // class, thread), so the order is the same as one thread's).
   auto cls = [](uint64_t L) { return L ? 64 - __builtin_clzll(L) : 0; };
-  size_t cnt[2][65] = {};
-  size_t nC = 0;
-  for (int64_t i = 0; i < nq; ++i) {
-    const uint64_t L = qlen[i];
-    if (L > LB)
-      ++nC;
-    else
-      ++cnt[L > LA ? 0 : 1][cls(L)];  // tier 0: work-group (B), 1: wave (A)
-  }
-  size_t pos[2][65], nB = 0, need = 0;
-  for (int t = 0; t < 2; ++t) {
-    for (int c2 = 64; c2 >= 0; --c2) {
-      pos[t][c2] = need;
-      need += cnt[t][c2];
+  const int nth = nq >= (int64_t)1 << 20 ? 8 : 1;
+  std::vector<std::array<size_t, 131>> cnt(nth);  // [tier 0: 0..64, tier 1: 65..129, hubs: 130]
+  auto range = [&](int t, int64_t& lo, int64_t& hi) {
+    lo = nq * t / nth;
+    hi = nq * (t + 1) / nth;
+  };
+  auto count_part = [&](int t) {
+    auto& ct = cnt[t];
+    ct.fill(0);
+    int64_t lo, hi;
+    range(t, lo, hi);
+    for (int64_t i = lo; i < hi; ++i) {
+      const uint64_t L = qlen[i];
+      if (L > LB)
+        ++ct[130];
+      else
+        ++ct[(L > LA ? 0 : 65) + cls(L)];  // tier 0: work-group (B), 1: wave (A)
     }
-    if (t == 0) nB = need;
+  };
+  auto run_parts = [&](auto&& fn) {
+    if (nth == 1) {
+      fn(0);
+      return;
+    }
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) th.emplace_back(fn, t);
+    fn(0);
+    for (auto& x : th) x.join();
+  };
+  run_parts(count_part);
+  // start of each (bucket, thread): buckets in order tier 0 classes 64..0,
+  // tier 1 classes 64..0
+  std::vector<std::array<size_t, 130>> pos(nth);
+  size_t nB = 0, need = 0, nC = 0;
+  for (int tier = 0; tier < 2; ++tier) {
+    for (int c2 = 64; c2 >= 0; --c2) {
+      const int bk = tier * 65 + c2;
+      for (int t = 0; t < nth; ++t) {
+        pos[t][bk] = need;
+        need += cnt[t][bk];
+      }
+    }
+    if (tier == 0) nB = need;
   }
+  for (int t = 0; t < nth; ++t) nC += cnt[t][130];
   // the pinned staging of the previous plan must have been consumed
   if (b->upload_pending) {
     int st0 = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan");
@@ -773,15 +806,27 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
     return st;
   int32_t* items = static_cast<int32_t*>(b->pin_items.p);
   std::vector<std::pair<uint64_t, int32_t>> C;
-  C.reserve(with_hubs ? nC : 0);
-  for (int64_t i = 0; i < nq; ++i) {
-    const uint64_t L = qlen[i];
-    if (L > LB) {
-      if (with_hubs) C.push_back({L, (int32_t)i});
-    } else {
-      items[pos[L > LA ? 0 : 1][cls(L)]++] = (int32_t)i;
-    }
+  if (with_hubs) C.resize(nC);
+  std::vector<size_t> cpos(nth);
+  for (int t = 0, run = 0; t < nth; ++t) {
+    cpos[t] = run;
+    run += (int)cnt[t][130];
   }
+  auto scatter_part = [&](int t) {
+    auto& pt = pos[t];
+    size_t cp = cpos[t];
+    int64_t lo, hi;
+    range(t, lo, hi);
+    for (int64_t i = lo; i < hi; ++i) {
+      const uint64_t L = qlen[i];
+      if (L > LB) {
+        if (with_hubs) C[cp++] = {L, (int32_t)i};
+      } else {
+        items[pt[(L > LA ? 0 : 65) + cls(L)]++] = (int32_t)i;
+      }
+    }
+  };
+  run_parts(scatter_part);
   std::sort(C.begin(), C.end(),
             [](const std::pair<uint64_t, int32_t>& x, const std::pair<uint64_t, int32_t>& y) {
               return x.first != y.first ? x.first > y.first : x.second < y.second;
