@@ -61,7 +61,7 @@ enum { PANTHER_MEM_HOST = 0, PANTHER_MEM_DEVICE = 1 };
 #define PANTHER_FORM_BATCHED 1 /* all queries in one persistent launch */
 /* values of the "pp.form" option */
 #define PANTHER_PP_FP64 0      /* brute-force FP64 distances */
-#define PANTHER_PP_BF16 1      /* BF16 MFMA candidate pool, FP64 rerank */
+#define PANTHER_PP_BF16 1      /* BF16 MFMA candidate pool, FP64 rerank, certified */
 
 /* Creates a context on GPU `device_ordinal`.  *out receives the handle.
  * Errors: EINVAL (bad ordinal / NULL out), EDEVICE. */
@@ -123,9 +123,14 @@ int panther_topk_similar(panther_ctx *ctx, const int32_t *queries, int64_t nq,
  * with one fused multiply-add per coordinate in coordinate order.
  * Layout: out_ids int32[nq][k] (padded with -1), out_dist fp64[nq][k]
  * Euclidean distances (padded with +inf).  The "pp.form" option selects
- * FP64 brute force or the BF16 candidate pool + FP64 rerank.
+ * FP64 brute force or the BF16 form: a matrix-core candidate pool over the
+ * rows in norm order (pruned by each query's norm band), an FP64 rerank,
+ * and a per-query certificate that the pool holds the exact k (else an
+ * exact recompute) -- both forms return the same ids and distances.  The
+ * BF16 form needs D <= 64 and sorts a BF16 copy of theta once per
+ * (paths, D).
  * Errors: ESTATE (no paths), EINVAL (D < 1 or D > 256, k < 1 or k > 256,
- * nq < 0), ERANGE, ENOMEM, EDEVICE. */
+ * nq < 0; D > 64 in the BF16 form), ERANGE, ENOMEM, EDEVICE. */
 int panther_pp_topk(panther_ctx *ctx, const int32_t *queries, int64_t nq,
                     int32_t D, int32_t k, int32_t *out_ids, double *out_dist,
                     int mem, void *stream);
