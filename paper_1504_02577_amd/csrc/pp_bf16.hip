@@ -46,7 +46,7 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kDP = 64;        // padded feature width in bfloat16
 constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
-constexpr int kTrip = 2;        // chunks per loop trip (ping-pong operands)
+constexpr int kTrip = 4;        // chunks per loop trip (register ring of operands)
 constexpr int kCheckEvery = 8;  // chunks between pool compaction checks (whole trips)
 constexpr int kBoundChunks = 32;  // chunks of the bound pass before a sliced scan
 
@@ -541,23 +541,31 @@ k_pp_pool(PoolArgs A) {
     }
     return -1;
   };
-  // operands of two chunks in ping-pong registers: each trip computes one
-  // while the next loads (no register copies, which would force a wait)
-  bf16x8 b0[2], b1[2];
-  floatx4 nv0, nv1;
-  int4 id0, id1;
-  int64_t c_a = next_chunk();
-  load_b(c_a, b0, nv0, id0);
+  // operands of four chunks in a register ring: each chunk's loads are
+  // issued three chunks before its products (a chunk is short next to a
+  // load's latency), and the ring rotates by unrolling, without register
+  // copies (a copy of a prefetched operand would force a wait)
+  bf16x8 b0[2], b1[2], b2[2], b3[2];
+  floatx4 nv0, nv1, nv2, nv3;
+  int4 id0, id1, id2, id3;
+  load_b(next_chunk(), b0, nv0, id0);
+  load_b(next_chunk(), b1, nv1, id1);
+  load_b(next_chunk(), b2, nv2, id2);
   int chunk_no = 0;
   while (true) {
-    const int64_t c_b = next_chunk();
-    load_b(c_b, b1, nv1, id1);
+    load_b(next_chunk(), b3, nv3, id3);
     chunk(b0, nv0, id0);
-    c_a = next_chunk();
-    load_b(c_a, b0, nv0, id0);
+    const int64_t c_next = next_chunk();  // the oldest chunk left in the ring
+    load_b(c_next, b0, nv0, id0);
     chunk(b1, nv1, id1);
+    load_b(next_chunk(), b1, nv1, id1);
+    chunk(b2, nv2, id2);
+    load_b(next_chunk(), b2, nv2, id2);
+    chunk(b3, nv3, id3);
     chunk_no += kTrip;
-    const bool last = c_a < 0 || (A.max_chunks && chunk_no >= A.max_chunks);
+    // once the sequence returns -1 it stays -1: if the oldest chunk left
+    // in the ring is none, so are the two after it
+    const bool last = c_next < 0 || (A.max_chunks && chunk_no >= A.max_chunks);
     if (chunk_no % check_every != 0 && !last) continue;
     __threadfence_block();
     __syncthreads();
