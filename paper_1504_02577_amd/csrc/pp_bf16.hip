@@ -23,9 +23,10 @@
 //    (norm +- threshold radius), it stops -- those rows could not enter
 //    any pool.  The pool is thus the P smallest keys over all rows, the
 //    same set a full scan gives, from a fraction of the rows.
-// 3. Rerank: one wavefront per query recomputes the exact FP64 squared
+// 3. Rerank: one work-group per query recomputes the exact FP64 squared
 //    distance (one fma per coordinate, coordinate order) of every pool
-//    member, sorts by (d2, id) and writes the first k.  It also records how
+//    member (one member per thread), sorts by (d2, id) and writes the
+//    first k.  It also records how
 //    many of the final ids the pool order already had in its first k, and
 //    the relative error of d2~ / R^2 against d2 on the returned neighbours.
 #include <algorithm>
@@ -724,11 +725,9 @@ k_pp_merge(PoolArgs A) {
   }
 }
 
-// per wavefront: d, v, ap of P entries, then a tile of 64 rows of D + 1
-// floats (also holding up to 256 ids afterwards: k <= 256)
-__host__ __device__ constexpr size_t rerank_lds_per_wave(int P, int D) {
-  return (sizeof(double) + sizeof(int32_t) + sizeof(float)) * (size_t)P +
-         sizeof(float) * (kWave * (D + 1) > 256 ? (size_t)kWave * (size_t)(D + 1) : (size_t)256);
+// per query (work-group): d, v, ap of P entries and up to 256 staged ids
+__host__ __device__ constexpr size_t rerank_lds(int P) {
+  return (sizeof(double) + sizeof(int32_t) + sizeof(float)) * (size_t)P + sizeof(int32_t) * 256;
 }
 
 struct RerankArgs {
@@ -758,56 +757,52 @@ struct RerankArgs {
 // one wavefront per query
 __global__ void __launch_bounds__(kBlock)
 k_pp_rerank(RerankArgs A) {
-  // per wavefront: d[P], v[P], ap[P], then a [64][D+1] tile of staged rows
+  // one work-group per query: d[P], v[P], ap[P], first[256]
   extern __shared__ __align__(16) char rr_lds[];
-  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const int64_t qi = (int64_t)blockIdx.x * (kBlock / kWave) + wid;
-  if (qi >= A.nq) return;
+  __shared__ double qv[kDP];
+  __shared__ unsigned int s_valid, s_hits;
+  __shared__ unsigned long long s_err;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t qi = blockIdx.x;
   const int32_t q = A.queries[qi];
-  const int P = A.P, D = A.D, DS = A.D + 1;
+  const int P = A.P, D = A.D;
   const float* tq = A.qtheta + (int64_t)q * D;
-  char* mine = rr_lds + (size_t)wid * rerank_lds_per_wave(P, D);
-  double* d = reinterpret_cast<double*>(mine);
+  double* d = reinterpret_cast<double*>(rr_lds);
   int32_t* v = reinterpret_cast<int32_t*>(d + P);
   float* ap = reinterpret_cast<float*>(v + P);
-  float* tile = ap + P;
-  // 64 pool members at a time: their rows are staged by whole-row loads
-  // (one row per instruction, D <= 64 lanes), then each lane runs the
-  // exact chain for its member from LDS
-  for (int b0 = 0; b0 < P; b0 += kWave) {
-    const int i = b0 + lane;
-    const int32_t c = i < P ? A.pool_ids[qi * P + i] : -1;
-    for (int r = 0; r < kWave; ++r) {
-      const int32_t cr = __shfl(c, r, kWave);
-      if (cr >= 0 && lane < D) tile[r * DS + lane] = A.theta[(int64_t)cr * D + lane];
-    }
-    wsync();
-    if (i < P) {
-      double s = INFINITY;
-      if (c >= 0) {
-        s = 0.0;
-        for (int j = 0; j < D; ++j) {
-          const double delta = (double)tq[j] - (double)tile[lane * DS + j];
-          s = fma(delta, delta, s);
-        }
-      }
-      d[i] = s;
-      v[i] = c >= 0 ? c : 0x7FFFFFFF;
-      ap[i] = A.pool_d2[qi * P + i];
-    }
-    wsync();
+  int32_t* first = reinterpret_cast<int32_t*>(ap + P);
+  if (threadIdx.x < D) qv[threadIdx.x] = (double)tq[threadIdx.x];
+  if (threadIdx.x == 0) {
+    s_valid = 0u;
+    s_hits = 0u;
+    s_err = 0ull;
   }
-  // pre-rerank top-k ids are pool entries 0..k-1 (pool is in key order)
-  // count valid entries
-  int valid = 0;
-  for (int i = lane; i < P; i += kWave) valid += A.pool_ids[qi * P + i] >= 0 ? 1 : 0;
-  for (int off = 32; off > 0; off >>= 1) valid += __shfl_xor(valid, off, kWave);
+  __syncthreads();
+  // every member's row at once (one member per thread, all loads of a
+  // thread's row independent): the exact chain of the oracle
+  unsigned my_valid = 0;
+  for (int i = threadIdx.x; i < P; i += kBlock) {
+    const int32_t c = A.pool_ids[qi * P + i];
+    double sacc = INFINITY;
+    if (c >= 0) {
+      const float* tv = A.theta + (int64_t)c * D;
+      sacc = 0.0;
+      for (int j = 0; j < D; ++j) {
+        const double delta = qv[j] - (double)tv[j];
+        sacc = fma(delta, delta, sacc);
+      }
+      ++my_valid;
+    }
+    d[i] = sacc;
+    v[i] = c >= 0 ? c : 0x7FFFFFFF;
+    ap[i] = A.pool_d2[qi * P + i];
+  }
+  if (my_valid) atomicAdd(&s_valid, my_valid);
+  __syncthreads();
   // sort (d, v) ascending; the approximate values ride along
-  int PP = 2;
-  while (PP < P) PP <<= 1;
-  for (int size = 2; size <= PP; size <<= 1) {
+  for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = lane; i < (PP >> 1); i += kWave) {
+      for (int i = threadIdx.x; i < (P >> 1); i += kBlock) {
         const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
         const int hi = lo + stride;
         const bool asc = (lo & size) == 0;
@@ -824,18 +819,18 @@ k_pp_rerank(RerankArgs A) {
           ap[hi] = t;
         }
       }
-      wsync();
+      __syncthreads();
     }
   }
+  const int valid = (int)s_valid;
   const int k = A.k;
   const int m = valid < k ? valid : k;
-  // the pool order's first m ids, staged in the (now free) row tile
-  int32_t* first = reinterpret_cast<int32_t*>(tile);
-  for (int i = lane; i < m; i += kWave) first[i] = A.pool_ids[qi * P + i];
-  wsync();
+  // the pool order's first m ids (pre-rerank top k: the pool is in key order)
+  for (int i = threadIdx.x; i < m; i += kBlock) first[i] = A.pool_ids[qi * P + i];
+  __syncthreads();
   unsigned hits = 0;
   double err = 0.0;
-  for (int j = lane; j < k; j += kWave) {
+  for (int j = threadIdx.x; j < k; j += kBlock) {
     const bool ok = j < m;
     A.out_ids[qi * k + j] = ok ? v[j] : -1;
     A.out_dist[qi * k + j] = ok ? sqrt(d[j]) : INFINITY;
@@ -848,15 +843,14 @@ k_pp_rerank(RerankArgs A) {
       err = e > err ? e : err;
     }
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    hits += __shfl_xor(hits, off, kWave);
-    const double o = __shfl_xor(err, off, kWave);
-    err = o > err ? o : err;
-  }
+  if (hits) atomicAdd(&s_hits, hits);
+  if (err > 0.0) atomicMax(&s_err, (unsigned long long)__double_as_longlong(err));  // err >= 0
+  __syncthreads();
+  if (threadIdx.x >= kWave) return;  // the first wavefront finishes the query
   if (lane == 0) {
     atomicAdd(A.stat_ret, (unsigned long long)m);
-    atomicAdd(A.stat_hits, (unsigned long long)hits);
-    atomicMax(A.stat_err, (unsigned long long)__double_as_longlong(err));
+    atomicAdd(A.stat_hits, (unsigned long long)s_hits);
+    atomicMax(A.stat_err, s_err);
   }
   // Certificate (in units of the scaled rows x = theta * s).  Every vertex
   // outside the pool has a pool key at least the pool's largest, so its
@@ -1186,11 +1180,11 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   ra.stat_hits = st;
   ra.stat_err = st + 1;
   ra.stat_ret = st + 2;
-  const size_t rr_lds = (kBlock / kWave) * rerank_lds_per_wave(P, D);
+  const size_t rr_lds = rerank_lds(P);
   HIPTRY(hipFuncSetAttribute((const void*)k_pp_rerank, hipFuncAttributeMaxDynamicSharedMemorySize,
                              (int)rr_lds),
          "pp rerank attribute");
-  k_pp_rerank<<<(unsigned)((nq + kBlock / kWave - 1) / (kBlock / kWave)), kBlock, rr_lds, s>>>(ra);
+  k_pp_rerank<<<(unsigned)nq, kBlock, rr_lds, s>>>(ra);
   HIPTRY(hipGetLastError(), "pp rerank");
   unsigned long long hs[6];
   HIPTRY(hipMemcpyAsync(hs, st, sizeof hs, hipMemcpyDeviceToHost, s), "pp stats");
