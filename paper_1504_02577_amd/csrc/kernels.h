@@ -117,10 +117,10 @@ struct KnnBand {
 // Exact recompute of listed queries from a known bound (knn.hip): rows[i]
 // (i < nr) names the output row of query queries[rows[i]], and (tau_d[i],
 // tau_v[i]) is an exact (d2, id) pair that at least k rows reach.  work:
-// device memory of knn_range_bytes(nr) bytes.  band (may be null): scan
-// only each query's norm band of that copy (whose rows must include every
-// candidate).  A list keeps up to min(cap, 4096) candidates; lists that
-// outgrow it are recomputed by the full brute force.
+// device memory of knn_range_bytes(nr) bytes.  band (required): each
+// query scans only its norm band of that copy, whose rows must include
+// every candidate.  A list keeps up to min(cap, 4096) candidates; lists
+// that outgrow it are recomputed by the full brute force.
 size_t knn_range_bytes(int64_t nr);
 int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* qtheta,
                          bool exclude_self, const int32_t* queries, const int32_t* rows,

@@ -152,67 +152,6 @@ k_knn_fp64(const float* __restrict__ theta, int32_t n, int32_t D,
   }
 }
 
-// Exact candidates of queries whose approximate search is not certified.
-// Query i (queries[rows[i]]) keeps every row v whose pair (d2, v) is at most
-// its bound (tau_d[i], tau_v[i]) -- the k-th exact pair among rows already
-// found, so the true top k is a subset.  A work-group takes QF queries and
-// one slice of rows; survivors are appended to the query's list (cap
-// entries; cand_n counts all of them, so a count above cap marks overflow).
-template <int QF>
-__global__ void __launch_bounds__(kBlock)
-k_knn_range(const float* __restrict__ theta, int32_t n, int32_t D,
-            const float* __restrict__ qtheta, int32_t exclude_self,
-            const int32_t* __restrict__ queries, const int32_t* __restrict__ rows, int64_t nr,
-            const double* __restrict__ tau_d, const int32_t* __restrict__ tau_v,
-            int64_t rows_per_wg, uint32_t cap, double* __restrict__ cand_d,
-            int32_t* __restrict__ cand_v, unsigned int* __restrict__ cand_n) {
-  extern __shared__ __align__(16) char lds[];
-  double* qv = reinterpret_cast<double*>(lds);  // [QF][D]
-  __shared__ double td[QF];
-  __shared__ int32_t tv[QF], qid[QF];
-  const int64_t i0 = (int64_t)blockIdx.x * QF;
-  for (int i = threadIdx.x; i < QF; i += kBlock) {
-    const bool ok = i0 + i < nr;
-    qid[i] = ok ? queries[rows[i0 + i]] : -1;
-    td[i] = ok ? tau_d[i0 + i] : -1.0;
-    tv[i] = ok ? tau_v[i0 + i] : -1;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < QF * D; i += kBlock) {
-    const int32_t q = qid[i / D];
-    qv[i] = q >= 0 ? (double)qtheta[(int64_t)q * D + (i % D)] : 0.0;
-  }
-  __syncthreads();
-  const int64_t r0 = (int64_t)blockIdx.y * rows_per_wg;
-  const int64_t r1 = r0 + rows_per_wg < n ? r0 + rows_per_wg : n;
-  for (int64_t v = r0 + threadIdx.x; v < r1; v += kBlock) {
-    double acc[QF];
-#pragma unroll
-    for (int q = 0; q < QF; ++q) acc[q] = 0.0;
-    const float* row = theta + v * D;
-    for (int d = 0; d < D; ++d) {
-      const double x = (double)row[d];
-#pragma unroll
-      for (int q = 0; q < QF; ++q) {
-        const double delta = qv[q * D + d] - x;
-        acc[q] = fma(delta, delta, acc[q]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < QF; ++q) {
-      const int32_t me = qid[q];
-      if (me >= 0 && (!exclude_self || (int32_t)v != me) &&
-          (acc[q] < td[q] || (acc[q] == td[q] && (int32_t)v <= tv[q]))) {
-        const unsigned pos = atomicAdd(&cand_n[i0 + q], 1u);
-        if (pos < cap) {
-          cand_d[(i0 + q) * cap + pos] = acc[q];
-          cand_v[(i0 + q) * cap + pos] = (int32_t)v;
-        }
-      }
-    }
-  }
-}
-
 constexpr int kSelCap = 4096;
 
 // Norm band of each listed query over a norm-ordered copy of the database
@@ -362,9 +301,10 @@ size_t knn_range_bytes(int64_t nr) {
 // Exact recompute of listed queries from a known bound: rows[i] (i < nr)
 // names the output row of query queries[rows[i]], and (tau_d[i], tau_v[i])
 // is an exact (d2, id) pair that at least k rows reach.  work: device
-// memory of knn_range_bytes(nr) bytes.  A list keeps up to
-// min(cap, 4096) candidates; lists that outgrow it are recomputed by the
-// full brute force (one host synchronisation).
+// memory of knn_range_bytes(nr) bytes; nb: the norm-ordered copy whose
+// band of each query is scanned.  A list keeps up to min(cap, 4096)
+// candidates; lists that outgrow it are recomputed by the full brute force
+// (one host synchronisation).
 int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* qtheta,
                          bool exclude_self, const int32_t* queries, const int32_t* rows,
                          int64_t nr, const double* tau_d, const int32_t* tau_v, int32_t k,
@@ -372,8 +312,8 @@ int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* 
                          int32_t* out_ids, double* out_dist, hipStream_t s, uint32_t cap,
                          const KnnBand* nb) {
   cap = std::min<uint32_t>(cap, kSelCap);
-  constexpr int QF = 8;
   if (nr <= 0) return 0;
+  if (!nb) return (int)hipErrorInvalidValue;
   char* w = static_cast<char*>(work);
   double* cand_d = reinterpret_cast<double*>(w);
   int32_t* cand_v = reinterpret_cast<int32_t*>(cand_d + (size_t)nr * kSelCap);
@@ -384,7 +324,7 @@ int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* 
   if (e != hipSuccess) return (int)e;
   e = hipMemsetAsync(ov_n_dev, 0, sizeof(unsigned long long), s);
   if (e != hipSuccess) return (int)e;
-  if (nb) {
+  {
     // rows in the norm order of a sorted copy, each query within its band
     k_knn_band<<<(unsigned)((nr + kBlock - 1) / kBlock), kBlock, 0, s>>>(
         qtheta, D, queries, rows, nr, tau_d, nb->norm_s, nb->rows, nb->scale, nb->err, band);
@@ -395,22 +335,6 @@ int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* 
     k_knn_range_band<<<dim3((unsigned)nr, (unsigned)gy), kBlock, lds, s>>>(
         theta, D, qtheta, exclude_self ? 1 : 0, queries, rows, tau_d, tau_v, band, nb->sid, cap,
         cand_d, cand_v, cand_n);
-    e = hipGetLastError();
-    if (e != hipSuccess) return (int)e;
-  }
-  if (!nb) {
-    // every row, 8 queries per work-group, rows split into slices
-    const int64_t gx = (nr + QF - 1) / QF;
-    int64_t gy = std::max<int64_t>(1, (4 * (int64_t)num_cus + gx - 1) / gx);
-    gy = std::min<int64_t>(gy, std::max<int64_t>(1, ((int64_t)n + 4 * kBlock - 1) / (4 * kBlock)));
-    const int64_t rpw = ((int64_t)n + gy - 1) / gy;
-    const size_t lds = sizeof(double) * QF * D;
-    e = hipFuncSetAttribute((const void*)k_knn_range<QF>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return (int)e;
-    k_knn_range<QF><<<dim3((unsigned)gx, (unsigned)gy), kBlock, lds, s>>>(
-        theta, n, D, qtheta, exclude_self ? 1 : 0, queries, rows, nr, tau_d, tau_v, rpw,
-        cap, cand_d, cand_v, cand_n);
     e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
   }
