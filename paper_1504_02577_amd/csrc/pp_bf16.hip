@@ -48,7 +48,7 @@ constexpr int kBlock = 256;
 constexpr int kDP = 64;        // padded feature width in bfloat16
 constexpr int kChunk = 64;     // database rows per chunk (16 per wavefront)
 constexpr int kTrip = 4;        // chunks per loop trip (register ring of operands)
-constexpr int kCheckEvery = 8;  // chunks between pool compaction checks (whole trips)
+constexpr int kCheckEvery = 16;  // chunks between pool compaction checks (whole trips)
 constexpr int kBoundChunks = 32;  // chunks of the bound pass before a sliced scan
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -305,7 +305,7 @@ struct PoolArgs {
   int32_t P;             // pool size (power of two, <= 1024)
   int32_t cap;           // buffer entries per (query, slice): 2P + kCheckEvery * kChunk
   int32_t slices;        // work-groups per query tile (grid.y), interleaved over chunks
-  int32_t sort_cap;      // per-wave sort buffer entries: next power of two >= cap
+  int32_t sort_cap;      // per-wave buffer entries (>= cap, and >= the sort's P)
   uint64_t* buf;         // [nq][slices][cap] pool buffers, by sorted index
   uint64_t* part;        // [nq][slices][P] slice pools (slices > 1), by sorted index
   int32_t* pool_ids;     // [nq][P] result by query position, ascending key order, -1 padded
@@ -682,11 +682,10 @@ k_pp_pool(PoolArgs A) {
       sb[i] = __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     wsync();
     // one slice: the pool in ascending key order; several: the slice's P
-    // best in any order (the merge selects across slices)
-    if (S == 1)
-      wave_sort_keys(sb, c);
-    else if (c > P)
-      (void)wave_select_cut(sb, c, P, s_hist[wid]);
+    // best in any order (the merge selects across slices).  The P best are
+    // cut first, so the sort needs P (a power of two) entries of buffer.
+    if (c > P) (void)wave_select_cut(sb, c, P, s_hist[wid]);
+    if (S == 1) wave_sort_keys(sb, c < P ? c : P);
     const int m = c < P ? c : P;
     if (S == 1) {
       const int64_t pos = qpos[ql];
@@ -1065,8 +1064,7 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   int32_t* pool_ids = reinterpret_cast<int32_t*>(base + buf_bytes + part_bytes + gtau_bytes);
   float* pool_d2 = reinterpret_cast<float*>(pool_ids + (size_t)nq * P);
   HIPTRY(hipMemsetAsync(lane->b_stats.p, 0, 64, s), "pp stats");
-  int sort_cap = 2;
-  while (sort_cap < cap) sort_cap <<= 1;
+  const int sort_cap = std::max(cap, P);
   const int64_t rows = pp->bf16_rows;
   const int64_t nchunks = (rows + kTrip * kChunk - 1) / (kTrip * kChunk) * kTrip;
   PoolArgs pa{};
