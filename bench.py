@@ -225,11 +225,34 @@ def main():
                      "kernel": "k_walk32", "algorithmic_bytes_per_launch": walk_bytes,
                      "kernel_ms": walk_ms},
     }
+    # achievable HBM bandwidth on this machine: a 2 GiB device-to-device copy
+    # (2 GiB read + 2 GiB written), best of 3, timed with HIP events
+    copy_gbs = measured_copy_gbs()
+    res["roofline"]["measured_copy_GBps"] = copy_gbs
+    res["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs if copy_gbs else None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         res["cpu_baseline"] = cpu_baseline(g, q, T, k, seed, args.cpu_sample or R)
     P.close()
     print(json.dumps(res), flush=True)
+
+
+def measured_copy_gbs():
+    import torch
+
+    x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    best = None
+    for _ in range(4):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    return 2.0 * (1 << 31) / (best * 1e-3) / 1e9
 
 
 def bench_allv(args):
