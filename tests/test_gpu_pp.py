@@ -176,8 +176,20 @@ def test_pp_errors_and_device_buffers(P, oracle, ba):
     import torch
     from paper_1504_02577_amd.panther import PantherError, PANTHER_EINVAL, PANTHER_ERANGE
 
+    from paper_1504_02577_amd.panther import Panther, PANTHER_ESTATE
+
     g, paths, inv_ptr, inv_pid = ba
     _say("case: pp errors and device buffers")
+    fresh = Panther(0)
+    try:  # no BF16 call yet: the statistics calls report ESTATE
+        for call in (fresh.pp_scanned, fresh.pp_certified, fresh.pp_stats):
+            with pytest.raises(PantherError) as e:
+                call()
+            assert e.value.code == PANTHER_ESTATE
+    finally:
+        fresh.close()
+    with pytest.raises(PantherError):
+        P.set_option("test.pp_recompute_all", 3)
     P.load_graph(g)
     P.sample_paths(5, 100_000, 1)
     P.set_option("pp.form", 1)
