@@ -94,10 +94,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ uint32_t ld_agent_u32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Gathers the rows of P_q [a, a+L) with `nthr` threads (thread id `t`),
 // calling f(v) for every distinct vertex v != q of every row.
 template <int S, typename F>

@@ -198,11 +198,6 @@ __global__ void k_fill_u64(unsigned long long* a, int64_t n, unsigned long long 
   if (i < n) a[i] = v;
 }
 
-__device__ __forceinline__ uint64_t pool_key(float d2, int32_t v) {
-  const float c = d2 > 0.f ? d2 : 0.f;
-  return ((uint64_t)__float_as_uint(c) << 32) | (uint32_t)v;
-}
-
 // ascending bitonic sort of cnt keys (padded with ~0) by one wavefront
 __device__ void wave_sort_keys(uint64_t* a, int cnt) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -625,7 +620,7 @@ k_pp_pool(PoolArgs A) {
       s_band[1] = 0u;
     }
     __syncthreads();
-    if (threadIdx.x < nvalid) {
+    if ((int)threadIdx.x < nvalid) {
       float lo2, hi2;
       norm_band(qn_s[threadIdx.x], tauf_s[threadIdx.x], lo2, hi2);
       atomicMin(&s_band[0], __float_as_uint(lo2));
@@ -770,7 +765,7 @@ k_pp_rerank(RerankArgs A) {
   int32_t* v = reinterpret_cast<int32_t*>(d + P);
   float* ap = reinterpret_cast<float*>(v + P);
   int32_t* first = reinterpret_cast<int32_t*>(ap + P);
-  if (threadIdx.x < D) qv[threadIdx.x] = (double)tq[threadIdx.x];
+  if ((int)threadIdx.x < D) qv[threadIdx.x] = (double)tq[threadIdx.x];
   if (threadIdx.x == 0) {
     s_valid = 0u;
     s_hits = 0u;
