@@ -330,7 +330,11 @@ int launch_knn_recompute(const float* theta, int32_t n, int32_t D, const float* 
         qtheta, D, queries, rows, nr, tau_d, nb->norm_s, nb->rows, nb->scale, nb->err, band);
     e = hipGetLastError();
     if (e != hipSuccess) return (int)e;
-    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(64, (4 * (int64_t)num_cus + nr - 1) / nr));
+    // at least 64 work-groups per query (up to 256 for a few queries):
+    // bands differ by orders of magnitude (a hub's spans most rows), and
+    // the work-groups of a narrow band find nothing to do and end at once
+    const int64_t gy = std::max<int64_t>(
+        64, std::min<int64_t>(256, (4 * (int64_t)num_cus + nr - 1) / nr));
     const size_t lds = sizeof(double) * D;
     k_knn_range_band<<<dim3((unsigned)nr, (unsigned)gy), kBlock, lds, s>>>(
         theta, D, qtheta, exclude_self ? 1 : 0, queries, rows, tau_d, tau_v, band, nb->sid, cap,
