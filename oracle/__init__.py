@@ -66,6 +66,10 @@ def lib():
         L.or_dist2.restype = dbl
         L.or_knn.argtypes = [i32, i32, P, P, i64, i32, P, P]
         L.or_knn_cross.argtypes = [i32, i64, P, i32, P, i32, P, P]
+        L.or_stream_counts.argtypes = [i32, i64, P, P, P, i32, i64, u64, ctypes.c_int, P, i32,
+                                       P, P]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_get_threads.restype = ctypes.c_int
         L.or_sample_size.argtypes = [dbl, dbl, dbl, i32]
         L.or_sample_size.restype = i64
         _lib = L
@@ -153,6 +157,35 @@ def walk_pids(g, T: int, seed: int, pids, start_all: bool = False) -> np.ndarray
     return out
 
 
+def stream_counts(g, T: int, R: int, seed: int, queries, start_all: bool = False):
+    """List lengths |P_v| for every v and dense counts c(q, v) for each query,
+    streamed over all R paths without storing them (small graphs only:
+    one n-array per query).  Returns (list_len uint64[n], counts uint32[nq][n])."""
+    rp = _c(g.row_ptr, np.int32)
+    col = _c(g.col, np.int32)
+    w = _c(g.w, np.uint32)
+    q = _c(queries, np.int32)
+    ln = np.zeros(g.n, np.uint64)
+    cnt = np.zeros((max(q.shape[0], 1), g.n), np.uint32)
+    _check(lib().or_stream_counts(g.n, g.m, _p(rp), _p(col), _p(w), T, R, seed, int(start_all),
+                                  _p(q), q.shape[0], _p(ln), _p(cnt)), "stream_counts")
+    return ln, cnt[:q.shape[0]]
+
+
+def topk_from_counts(counts, q: int, k: int):
+    """Top-k of one query from its dense counts: the vertices v != q with
+    c > 0, ordered by (c descending, id ascending), padded with (-1, 0)."""
+    c = np.asarray(counts).astype(np.int64).copy()
+    c[q] = 0
+    cand = np.nonzero(c)[0]
+    order = np.lexsort((cand, -c[cand]))[:k]
+    ids = np.full(k, -1, np.int32)
+    cnt = np.zeros(k, np.uint32)
+    ids[:order.size] = cand[order]
+    cnt[:order.size] = c[cand[order]]
+    return ids, cnt, int(order.size)
+
+
 def index(n: int, paths: np.ndarray):
     paths = _c(paths, np.int32)
     R, T1 = paths.shape
@@ -224,6 +257,15 @@ def knn_cross(theta_q, theta_db, k: int):
     _check(lib().or_knn_cross(D, nq, _p(tq), tdb.shape[0], _p(tdb), k, _p(ids), _p(dist)),
            "knn_cross")
     return ids, dist
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops (timing only)."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
 
 
 def sample_size(eps: float, c: float, delta: float, T: int) -> int:

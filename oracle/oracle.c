@@ -500,3 +500,99 @@ int or_walk_pids(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *co
   free(W); free(pfx); free(starts);
   return ns > 0 ? OR_OK : OR_EINVAL;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Counts of Algorithm 1 and the list lengths of the inverted index         */
+/* (Sec. 3.1) computed by streaming over every sampled path, storing        */
+/* neither the paths nor the index, for runs whose index is too large to    */
+/* hold (more than 2^32 entries).  Path pid is drawn exactly as in or_walk. */
+/*   list_len[v]      = |P_v|, the number of paths whose vertex set has v;  */
+/*   counts[i * n + v] = c(queries[i], v) = |P_q intersect P_v| for v != q, */
+/*                       and 0 for v == q.                                  */
+/* Memory: one dense n-counter array per query (and per thread), so this   */
+/* is meant for small graphs.                                               */
+/* ------------------------------------------------------------------------ */
+int or_stream_counts(int32_t n, int64_t m, const int32_t *row_ptr, const int32_t *col,
+                     const uint32_t *w, int32_t T, int64_t R, uint64_t seed,
+                     int start_all, const int32_t *queries, int32_t nq,
+                     uint64_t *list_len, uint32_t *counts) {
+  if (T < 1 || R < 1 || nq < 0) return OR_EINVAL;
+  uint64_t *W = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+  uint64_t *pfx = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m > 0 ? m : 1));
+  int32_t *starts = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+  if (!W || !pfx || !starts) {
+    free(W); free(pfx); free(starts);
+    return OR_ENOMEM;
+  }
+  or_row_weights(n, row_ptr, w, W);
+  or_row_prefix(n, row_ptr, w, pfx);
+  int32_t ns = or_start_set(n, W, start_all, starts);
+  if (ns == 0) {
+    free(W); free(pfx); free(starts);
+    return OR_EINVAL;
+  }
+  memset(list_len, 0, sizeof(uint64_t) * (size_t)n);
+  memset(counts, 0, sizeof(uint32_t) * (size_t)nq * (size_t)n);
+  int status = OR_OK;
+#pragma omp parallel
+  {
+    uint64_t *my_len = (uint64_t *)calloc((size_t)n, sizeof(uint64_t));
+    uint32_t *my_cnt = (uint32_t *)calloc((size_t)nq * (size_t)n + 1, sizeof(uint32_t));
+    int32_t *p = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    if (!my_len || !my_cnt || !p) {
+#pragma omp atomic write
+      status = OR_ENOMEM;
+    } else {
+#pragma omp for schedule(static)
+      for (int64_t pid = 0; pid < R; ++pid) {
+        int32_t v = starts[or_scale(or_draw(seed, (uint64_t)pid, 0u), (uint64_t)ns)];
+        p[0] = v;
+        for (int32_t t = 1; t <= T; ++t) {
+          int64_t e = or_pick_edge(row_ptr, pfx, W, v, or_draw(seed, (uint64_t)pid, (uint32_t)t));
+          if (e >= 0) v = col[e];
+          p[t] = v;
+        }
+        /* the path's vertex set: first occurrences only */
+        for (int32_t i = 0; i <= T; ++i)
+          if (or_first_occurrence(p, i)) my_len[p[i]] += 1;
+        for (int32_t qi = 0; qi < nq; ++qi) {
+          int32_t q = queries[qi], has = 0;
+          for (int32_t i = 0; i <= T; ++i) has |= p[i] == q;
+          if (!has) continue;
+          uint32_t *c = my_cnt + (size_t)qi * (size_t)n;
+          for (int32_t i = 0; i <= T; ++i)
+            if (p[i] != q && or_first_occurrence(p, i)) c[p[i]] += 1;
+        }
+      }
+#pragma omp critical
+      {
+        for (int32_t v = 0; v < n; ++v) list_len[v] += my_len[v];
+        for (size_t i = 0; i < (size_t)nq * (size_t)n; ++i) counts[i] += my_cnt[i];
+      }
+    }
+    free(my_len); free(my_cnt); free(p);
+  }
+  free(W); free(pfx); free(starts);
+  return status;
+}
+
+/* Thread count of the OpenMP loops above (timing of the CPU baseline only;
+ * results do not depend on it). */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+void or_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
+int or_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
