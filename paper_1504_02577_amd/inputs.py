@@ -45,23 +45,55 @@ class Graph:
 
 def _csr_from_undirected(n: int, u: np.ndarray, v: np.ndarray, w: np.ndarray,
                          name: str) -> Graph:
-    """Symmetrise a list of undirected edges (u != v, unique pairs) into CSR."""
-    rows = np.concatenate([u, v]).astype(np.int64)
-    cols = np.concatenate([v, u]).astype(np.int64)
-    ws = np.concatenate([w, w]).astype(np.uint32)
-    key = rows * np.int64(n) + cols
-    order = np.argsort(key, kind="stable")
-    del key
-    rows = rows[order]
-    cols = cols[order].astype(np.int32)
-    ws = ws[order]
-    del order
-    counts = np.bincount(rows, minlength=n)
-    del rows
+    """Symmetrise a list of undirected edges (u != v, unique pairs) into CSR.
+
+    Every directed (row, col) pair is distinct, so sorting by the key
+    row * n + col orders the entries uniquely (rows ascending, neighbours
+    ascending).  When the key fits 48 bits and the weights 16 bits, the
+    weight rides in the low bits of one sorted 64-bit word; otherwise an
+    argsort carries it."""
+    u = np.asarray(u, dtype=np.int64)
+    v = np.asarray(v, dtype=np.int64)
+    w = np.asarray(w, dtype=np.uint32)
+    m = 2 * u.shape[0]
+    if m >= 2 ** 31:
+        raise ValueError("graph too large for int32 CSR")
+    wmax = int(w.max()) if w.size else 0
+    if n <= (1 << 24) and wmax < (1 << 16):
+        key = np.empty(m, dtype=np.uint64)
+        h = u.shape[0]
+        np.multiply(u, n, out=key[:h], casting="unsafe")
+        key[:h] += v.astype(np.uint64)
+        np.multiply(v, n, out=key[h:], casting="unsafe")
+        key[h:] += u.astype(np.uint64)
+        key <<= np.uint64(16)
+        wk = w.astype(np.uint64)
+        key[:h] |= wk
+        key[h:] |= wk
+        del wk
+        key.sort()
+        ws = (key & np.uint64(0xFFFF)).astype(np.uint32)
+        key >>= np.uint64(16)
+        rows = key // np.uint64(n)
+        cols = (key - rows * np.uint64(n)).astype(np.int32)
+        del key
+        counts = np.bincount(rows.astype(np.int64), minlength=n)
+        del rows
+    else:
+        rows = np.concatenate([u, v])
+        cols = np.concatenate([v, u])
+        ws = np.concatenate([w, w])
+        key = rows * np.int64(n) + cols
+        order = np.argsort(key)  # keys are distinct: any sort gives this order
+        del key
+        rows = rows[order]
+        cols = cols[order].astype(np.int32)
+        ws = ws[order]
+        del order
+        counts = np.bincount(rows, minlength=n)
+        del rows
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(counts, out=row_ptr[1:])
-    if row_ptr[-1] >= 2 ** 31:
-        raise ValueError("graph too large for int32 CSR")
     return Graph(n=n, row_ptr=row_ptr.astype(np.int32), col=cols, w=ws,
                  name=name)
 
@@ -111,18 +143,39 @@ def rmat_graph(scale: int, edge_factor: int = 16, a: float = 0.57,
     abc = np.float32(a + b + c)
     fa = np.float32(a)
     chunk = 1 << 24
-    for lo in range(0, n_edges, chunk):
-        hi = min(n_edges, lo + chunk)
-        s = np.zeros(hi - lo, dtype=np.uint32)
-        d = np.zeros(hi - lo, dtype=np.uint32)
-        for _ in range(scale):
-            r = rng.random(hi - lo, dtype=np.float32)
-            row_bit = (r >= ab).astype(np.uint32)
-            col_bit = (((r >= fa) & (r < ab)) | (r >= abc)).astype(np.uint32)
-            s = (s << np.uint32(1)) | row_bit
-            d = (d << np.uint32(1)) | col_bit
-        src[lo:hi] = s
-        dst[lo:hi] = d
+
+    def assemble(s, d, levels):
+        # quadrant of each level, most significant bit first: row bit =
+        # (r >= a+b); column bit = (a <= r < a+b) or (r >= a+b+c)
+        b1 = np.empty(s.shape[0], dtype=bool)
+        b2 = np.empty(s.shape[0], dtype=bool)
+        for r in levels:
+            np.left_shift(s, 1, out=s)
+            np.greater_equal(r, ab, out=b1)
+            np.bitwise_or(s, b1, out=s, casting="unsafe")
+            np.greater_equal(r, fa, out=b2)
+            np.logical_not(b1, out=b1)
+            np.logical_and(b2, b1, out=b2)
+            np.greater_equal(r, abc, out=b1)
+            np.logical_or(b2, b1, out=b2)
+            np.left_shift(d, 1, out=d)
+            np.bitwise_or(d, b2, out=d, casting="unsafe")
+
+    # the draws stay in one sequential stream (chunk by chunk, level by
+    # level); the bit assembly of each chunk runs on a worker thread
+    import concurrent.futures as cf
+
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        pending = []
+        for lo in range(0, n_edges, chunk):
+            hi = min(n_edges, lo + chunk)
+            levels = [rng.random(hi - lo, dtype=np.float32) for _ in range(scale)]
+            pending.append(ex.submit(assemble, src[lo:hi], dst[lo:hi], levels))
+            del levels
+            if len(pending) >= 4:
+                pending.pop(0).result()
+        for f in pending:
+            f.result()
     lo_v = np.minimum(src, dst).astype(np.uint64)
     hi_v = np.maximum(src, dst).astype(np.uint64)
     del src, dst
