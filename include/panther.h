@@ -55,6 +55,7 @@ enum { PANTHER_MEM_HOST = 0, PANTHER_MEM_DEVICE = 1 };
 
 /* load_graph flags */
 #define PANTHER_START_ALL_VERTICES 1u /* start uniformly over all of V */
+#define PANTHER_CHECK_SYMMETRIC 2u    /* reject a CSR that is not undirected */
 
 /* values of the "topk.form" option */
 #define PANTHER_FORM_PLAIN 0   /* one query per kernel launch */
@@ -81,10 +82,17 @@ const char *panther_last_error(const panther_ctx *ctx);
  * rows.  Prepares the transition step of Eq. 3: per-row inclusive weight
  * prefixes and the start set {v : sum of row weights > 0} (or all of V
  * with PANTHER_START_ALL_VERTICES, where a walk on a weightless vertex
- * stays put).  Replaces any previous graph and drops paths, index and
- * features.
- * Errors: EINVAL (n < 1, m < 0, m >= 2^31, malformed CSR, empty start
- * set, row weight sum >= 2^63), ENOMEM, EDEVICE. */
+ * stays put).  With PANTHER_CHECK_SYMMETRIC the CSR must describe an
+ * undirected graph (Definition 1: every edge {v, u} of weight w is stored
+ * as v->u in row v and u->v in row u with the same weight; parallel entries
+ * must match in number; a self-loop is its own reverse); rows with
+ * ascending columns are searched by bisection, other rows scanned, so the
+ * check costs O(m log d) on sorted input.  Without the flag the rows are
+ * walked as given.  Replaces any previous graph and drops paths, index and
+ * features; a rejected graph leaves the context without a graph.
+ * Errors: EINVAL (n < 1, m < 0, m >= 2^31, malformed CSR, an asymmetric CSR
+ * under PANTHER_CHECK_SYMMETRIC, unknown flags, empty start set, row weight
+ * sum >= 2^63), ENOMEM, EDEVICE. */
 int panther_load_graph(panther_ctx *ctx, int32_t n, int64_t m,
                        const int32_t *row_ptr, const int32_t *col,
                        const uint32_t *w, int mem, uint32_t flags);
@@ -151,7 +159,10 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * LDS-derived default; longer lists go to the split hub pipeline),
  * "batch.hub_bits" (largest log2 bucket count per hub query, 0..12, -1 =
  * 12; smaller values make buckets overflow their LDS table and take the
- * sub-range path, for tests), "test.pp_recompute_all" (0..2, default 0;
+ * sub-range path, for tests), "test.hub_budget" (bytes of hub staging per
+ * chunk of the batched form, 0 = automatic: min(8 GiB, free / 4), at least
+ * 256 MiB; a small value splits the hub queries into many chunks, for
+ * tests), "test.pp_recompute_all" (0..2, default 0;
  * 1: the BF16 form recomputes every query whose pool is full by the exact
  * path, certified or not; 2: also overflows every candidate list so that
  * the full brute force runs; for tests), "test.fail_alloc_after" (the next n device allocations

@@ -17,13 +17,17 @@
 //      enqueued on the same stream ahead of the persistent kernel.
 // Counting is exact integer arithmetic and the ranking key (count desc, id
 // asc) is a total order, so the result equals the plain form bit for bit.
+#include <fcntl.h>
+#include <sys/file.h>
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <array>
 #include <chrono>
 #include <cstring>
 #include <cstdio>
 #include <cstdlib>
-#include <fstream>
 #include <sstream>
 #include <string>
 #include <thread>
@@ -273,9 +277,11 @@ struct BatchConfig {
 struct Plan {
   BatchArgs args{};
   bool run_kernel = false;
+  int stride = 0;  // path row stride: selects the kernel specialisations
   std::vector<HubArgs> hub;
   bool operator==(const Plan& o) const {
-    if (run_kernel != o.run_kernel || hub.size() != o.hub.size()) return false;
+    if (run_kernel != o.run_kernel || stride != o.stride || hub.size() != o.hub.size())
+      return false;
     if (std::memcmp(&args, &o.args, sizeof(args)) != 0) return false;
     for (size_t i = 0; i < hub.size(); ++i)
       if (std::memcmp(&hub[i], &o.hub[i], sizeof(HubArgs)) != 0) return false;
@@ -328,6 +334,7 @@ struct BatchState {
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   size_t hub_budget = 0;  // staging budget in bytes, fixed at first use
+  size_t hub_budget_forced = 0;  // option test.hub_budget (0 = automatic)
   // configuration
   bool tuned = false;
   BatchConfig cfg;
@@ -366,9 +373,18 @@ void copy_batch_options(panther_ctx* c, Lane* dst) {
   b->tier_a_override = a->tier_a_override;
   b->tier_b_override = a->tier_b_override;
   b->hub_bits_max = a->hub_bits_max;
+  b->hub_budget_forced = a->hub_budget_forced;
   b->tuned = false;
   b->no_tune = true;
   b->no_fork = true;
+}
+
+void forget_batch_graph(Lane* lane) {
+  BatchState* b = lane->batch;
+  if (!b) return;
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  b->last_valid = false;
 }
 
 void free_batch_state(Lane* lane) {
@@ -406,6 +422,9 @@ int set_batch_option(panther_ctx* c, const std::string& key, int64_t value) {
   } else if (key == "batch.hub_bits") {
     if (value < -1 || value > 12) return ctx_fail(c, PANTHER_EINVAL, "batch.hub_bits in -1..12");
     b->hub_bits_max = value < 0 ? 12 : (int)value;
+  } else if (key == "test.hub_budget") {
+    if (value < 0) return ctx_fail(c, PANTHER_EINVAL, "test.hub_budget must be >= 0");
+    b->hub_budget_forced = (size_t)value;
   } else if (key == "batch.wgs_per_cu") {
     if (value < 0 || value > 2) return ctx_fail(c, PANTHER_EINVAL, "batch.wgs_per_cu in 0..2");
     b->forced_wgs = (int)value;
@@ -445,33 +464,52 @@ std::string tune_cache_path() {
   return std::string(h ? h : "/tmp") + "/.cache/panther_tune.txt";
 }
 
+// The cache is a text file of "key block wgs_per_cu" lines (last match
+// wins).  Readers take a shared and writers an exclusive flock(2) on it, so
+// lanes and processes that tune at once never interleave a line.  Every
+// failure (no home, read-only disk) leaves tuning to run again next time.
 bool tune_lookup(const std::string& key, BatchConfig* cfg) {
-  std::ifstream f(tune_cache_path());
-  std::string line;
+  const int fd = open(tune_cache_path().c_str(), O_RDONLY | O_CLOEXEC);
+  if (fd < 0) return false;
   bool found = false;
-  while (std::getline(f, line)) {
-    std::istringstream is(line);
-    std::string k;
-    int blk, wgs;
-    if (is >> k >> blk >> wgs && k == key) {
-      cfg->block = blk;
-      cfg->wgs_per_cu = wgs;
-      found = true;
+  if (flock(fd, LOCK_SH) == 0) {
+    std::string text;
+    char buf[4096];
+    ssize_t r;
+    while ((r = read(fd, buf, sizeof buf)) > 0) text.append(buf, (size_t)r);
+    std::istringstream lines(text);
+    std::string line;
+    while (std::getline(lines, line)) {
+      std::istringstream is(line);
+      std::string k;
+      int blk, wgs;
+      if (is >> k >> blk >> wgs && k == key) {
+        cfg->block = blk;
+        cfg->wgs_per_cu = wgs;
+        found = true;
+      }
     }
+    (void)flock(fd, LOCK_UN);
   }
+  close(fd);
   return found;
 }
 
 void tune_store(const std::string& key, const BatchConfig& cfg) {
   const std::string path = tune_cache_path();
-  const size_t slash = path.rfind('/');
-  if (slash != std::string::npos) {
-    std::string dir = path.substr(0, slash);
-    std::string cmd = "mkdir -p '" + dir + "' 2>/dev/null";
-    (void)!system(cmd.c_str());
+  // create the parent directories one component at a time (no shell)
+  for (size_t pos = path.find('/', 1); pos != std::string::npos; pos = path.find('/', pos + 1))
+    (void)mkdir(path.substr(0, pos).c_str(), 0755);
+  const int fd = open(path.c_str(), O_WRONLY | O_CREAT | O_APPEND | O_CLOEXEC, 0644);
+  if (fd < 0) return;
+  if (flock(fd, LOCK_EX) == 0) {
+    char line[512];
+    const int len = snprintf(line, sizeof line, "%s %d %d\n", key.c_str(), cfg.block,
+                             cfg.wgs_per_cu);
+    if (len > 0 && len < (int)sizeof line) (void)!write(fd, line, (size_t)len);
+    (void)flock(fd, LOCK_UN);
   }
-  std::ofstream f(path, std::ios::app);
-  if (f) f << key << " " << cfg.block << " " << cfg.wgs_per_cu << "\n";
+  close(fd);
 }
 
 }  // namespace
@@ -600,7 +638,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     b->hub_budget = std::max<size_t>(std::min((size_t)8 << 30, free_b / 4), (size_t)1 << 28);
   }
   // staging bytes per occurrence slot: row order, bucket order
-  const size_t budget = b->hub_budget;
+  const size_t budget = b->hub_budget_forced ? b->hub_budget_forced : b->hub_budget;
   uint64_t occ_limit = std::max<uint64_t>(budget / 8, T * C.front().first);
   occ_limit = std::min<uint64_t>(occ_limit, (uint64_t)1 << 31);
   if (T * C.front().first > occ_limit)
@@ -873,6 +911,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   a.fR = (float)c->R;
   out->args = a;
   out->run_kernel = need > 0;
+  out->stride = c->stride;
   return PANTHER_OK;
 }
 

@@ -20,6 +20,11 @@ struct VRec {
 // column out of range.
 void launch_validate(const int32_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
                      uint32_t* err, hipStream_t s);
+// Symmetry (column ids already validated): sets bit 2 of *err when some
+// entry v->u of weight w has no matching u->v of weight w (multiplicities
+// compared).  sorted: n bytes of scratch.
+void launch_check_symmetric(const int32_t* row_ptr, const int32_t* col, const uint32_t* w,
+                            int32_t n, uint8_t* sorted, uint32_t* err, hipStream_t s);
 // Row sums into vrec; rows longer than 256 entries go to big_rows.
 void launch_rowsum(const int32_t* row_ptr, const uint32_t* w, int32_t n, VRec* vrec,
                    uint64_t* max_w, int32_t* big_rows, uint32_t* n_big, hipStream_t s);

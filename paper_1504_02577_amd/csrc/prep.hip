@@ -25,6 +25,74 @@ k_validate(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
   if (e) atomicOr(err, e);
 }
 
+// Symmetry check of an undirected CSR (Sec. 2, Definition 1: E holds
+// unordered pairs, so the entry v->u of weight w is stored in both rows).
+// Pass 1 marks the rows whose columns ascend; pass 2 takes one wavefront
+// per row and, for every entry (v, u, w), compares how many entries of row v
+// read (u, w) with how many of row u read (v, w) -- multi-edges must match
+// in number.  Ascending rows are searched by bisection, others scanned.
+__global__ void __launch_bounds__(kBlock)
+k_rows_sorted(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col, int32_t n,
+              uint8_t* __restrict__ sorted) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+    bool ok = true;
+    for (int32_t e = a + 1 + lane; e < b; e += kWave) ok = ok && col[e - 1] <= col[e];
+    const bool all = __ballot(!ok) == 0ull;
+    if (lane == 0) sorted[v] = all ? 1 : 0;
+  }
+}
+
+// Entries of row r equal to (t, wt).
+__device__ __forceinline__ uint32_t row_matches(const int32_t* __restrict__ row_ptr,
+                                                const int32_t* __restrict__ col,
+                                                const uint32_t* __restrict__ w,
+                                                const uint8_t* __restrict__ sorted, int32_t r,
+                                                int32_t t, uint32_t wt) {
+  int32_t lo = row_ptr[r];
+  const int32_t hi = row_ptr[r + 1];
+  uint32_t c = 0;
+  if (sorted[r]) {
+    int32_t h = hi;
+    while (lo < h) {  // first entry with col >= t
+      const int32_t mid = lo + ((h - lo) >> 1);
+      if (col[mid] < t)
+        lo = mid + 1;
+      else
+        h = mid;
+    }
+    for (int32_t e = lo; e < hi && col[e] == t; ++e) c += w[e] == wt ? 1u : 0u;
+  } else {
+    for (int32_t e = lo; e < hi; ++e) c += (col[e] == t && w[e] == wt) ? 1u : 0u;
+  }
+  return c;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_check_symmetric(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+                  const uint32_t* __restrict__ w, const uint8_t* __restrict__ sorted, int32_t n,
+                  uint32_t* err) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int64_t nwaves = (int64_t)gridDim.x * (kBlock / kWave);
+  bool bad = false;
+  for (int64_t v = wave; v < n; v += nwaves) {
+    const int32_t a = row_ptr[v], b = row_ptr[v + 1];
+    for (int32_t e = a + lane; e < b; e += kWave) {
+      const int32_t u = col[e];
+      const uint32_t wt = w[e];
+      if (u == (int32_t)v) continue;  // a self-loop is its own reverse
+      if (row_matches(row_ptr, col, w, sorted, (int32_t)v, u, wt) !=
+          row_matches(row_ptr, col, w, sorted, u, (int32_t)v, wt))
+        bad = true;
+    }
+  }
+  if (__ballot(bad) != 0ull && lane == 0) atomicOr(err, 4u);
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_rowsum(const int32_t* __restrict__ row_ptr, const uint32_t* __restrict__ w, int32_t n,
          VRec* __restrict__ vrec, unsigned long long* max_w, int32_t* big_rows,
@@ -315,6 +383,13 @@ void launch_validate(const int32_t* row_ptr, const int32_t* col, int32_t n, int6
                      uint32_t* err, hipStream_t s) {
   const int64_t work = m > n ? m : n;
   k_validate<<<grid_for(work, kBlock * 8, 65536), kBlock, 0, s>>>(row_ptr, col, n, m, err);
+}
+
+void launch_check_symmetric(const int32_t* row_ptr, const int32_t* col, const uint32_t* w,
+                            int32_t n, uint8_t* sorted, uint32_t* err, hipStream_t s) {
+  const unsigned g = grid_for(n, kBlock / kWave, 65536);
+  k_rows_sorted<<<g, kBlock, 0, s>>>(row_ptr, col, n, sorted);
+  k_check_symmetric<<<g, kBlock, 0, s>>>(row_ptr, col, w, sorted, n, err);
 }
 
 void launch_rowsum(const int32_t* row_ptr, const uint32_t* w, int32_t n, VRec* vrec,

@@ -150,6 +150,8 @@ int set_batch_option(panther_ctx* c, const std::string& key, int64_t value);
 // copies the forced batch options of lane 0 to another lane
 void copy_batch_options(panther_ctx* c, Lane* dst);
 void free_batch_state(Lane* lane);
+// drops the lane's captured graph and its repeat detection (new paths)
+void forget_batch_graph(Lane* lane);
 void free_lane(Lane* lane);
 
 // Panther++ (pp.hip, knn.hip, pp_bf16.hip)

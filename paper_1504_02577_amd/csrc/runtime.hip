@@ -115,6 +115,7 @@ static void free_features(panther_ctx* c) {
 // `release` is set (a new graph, or destroy).
 static void free_paths(panther_ctx* c, bool release) {
   free_features(c);
+  forget_batch_graph(&c->lane0);
   c->d_paths = nullptr;
   c->d_inv_ptr = nullptr;
   c->d_inv_pid = nullptr;
@@ -287,7 +288,7 @@ extern "C" int panther_set_option(panther_ctx* c, const char* key, int64_t value
   } else if (k == "test.fail_alloc_after") {
     c->fail_alloc_after = value < 0 ? -1 : value;
   } else if (k == "batch.tier_a" || k == "batch.tier_b" || k == "batch.block" ||
-             k == "batch.wgs_per_cu" || k == "batch.hub_bits") {
+             k == "batch.wgs_per_cu" || k == "batch.hub_bits" || k == "test.hub_budget") {
     return set_batch_option(c, k, value);
   } else {
     return ctx_fail(c, PANTHER_EINVAL, "unknown option '%s'", key);
@@ -324,7 +325,8 @@ extern "C" int panther_load_graph(panther_ctx* c, int32_t n, int64_t m, const in
     return ctx_fail(c, PANTHER_EINVAL, "null CSR pointer");
   if (mem != PANTHER_MEM_HOST && mem != PANTHER_MEM_DEVICE)
     return ctx_fail(c, PANTHER_EINVAL, "mem must be PANTHER_MEM_HOST or PANTHER_MEM_DEVICE");
-  if (flags & ~PANTHER_START_ALL_VERTICES) return ctx_fail(c, PANTHER_EINVAL, "unknown flags");
+  if (flags & ~(PANTHER_START_ALL_VERTICES | PANTHER_CHECK_SYMMETRIC))
+    return ctx_fail(c, PANTHER_EINVAL, "unknown flags");
   hipStream_t s = c->stream;
   int32_t ends[2];
   if (mem == PANTHER_MEM_HOST) {
@@ -383,6 +385,20 @@ extern "C" int panther_load_graph(panther_ctx* c, int32_t n, int64_t m, const in
   if (hctl[0] & 2u) {
     free_graph(c);
     return ctx_fail(c, PANTHER_EINVAL, "column id out of range");
+  }
+  if (flags & PANTHER_CHECK_SYMMETRIC) {
+    TRY(ctx_alloc(c, &p, (size_t)n, "row order flags"));
+    tmp.add(p);
+    launch_check_symmetric(d_rp, d_col, d_w, n, static_cast<uint8_t*>(p), ctl, s);
+    HIPTRY(hipGetLastError(), "symmetry check");
+    HIPTRY(hipMemcpyAsync(hctl, ctl, 16, hipMemcpyDeviceToHost, s), "symmetry check");
+    HIPTRY(hipStreamSynchronize(s), "symmetry check");
+    if (hctl[0] & 4u) {
+      free_graph(c);
+      return ctx_fail(c, PANTHER_EINVAL,
+                      "CSR is not symmetric: an entry v->u of weight w lacks a matching u->v "
+                      "of weight w");
+    }
   }
   TRY(ctx_alloc(c, &p, sizeof(VRec) * (size_t)n, "vertex records"));
   c->d_vrec = static_cast<VRec*>(p);

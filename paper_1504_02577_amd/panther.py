@@ -28,6 +28,7 @@ PANTHER_EDEVICE = -5
 PANTHER_MEM_HOST = 0
 PANTHER_MEM_DEVICE = 1
 PANTHER_START_ALL_VERTICES = 1
+PANTHER_CHECK_SYMMETRIC = 2
 PANTHER_FORM_PLAIN = 0
 PANTHER_FORM_BATCHED = 1
 PANTHER_PP_FP64 = 0
