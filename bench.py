@@ -4,14 +4,16 @@ One step = one pass of the whole hot path over the workload: sample R
 weighted random paths of length T (walk kernel), build the vertex-to-path
 index, and answer every query's top-k in the batched form.  Inputs are
 resident in device memory before the timed region starts.  The headline
-value is path-steps/s (R * T per step).  Also reported: batched vs plain
-top-k queries/s (with a bit-exactness check between the two), per-stage
-device times, the walk kernel's roofline figure and the oracle timed on the
-host cores on a bounded sample of the same workload.
+value is path-steps/s (R * T per step) on R-MAT scale 24 (T=5, R=10^8, 10^5
+degree-weighted queries, k=50), the largest configuration that is one GPU's
+whole job.  Also reported: batched vs plain top-k queries/s (with a
+bit-exactness check between the two), per-stage device times and their
+fractions of the HBM roofline by algorithmic bytes, the dominant kernel's
+roofline object, and the oracle timed on the host cores on a bounded sample
+of the same workload.
 
 Other workloads (one JSON line each, not the headline):
-  --workload rmat24     batched vs plain top-k, 10^5 degree-weighted queries,
-                        R = 10^8 (the heavy-tailed batching case)
+  --workload rmat20     the same step at R-MAT scale 20 (R = 10^7, 10^4 queries)
   --workload rmat22_pp  Panther++: features (D=50) and 65,536 kNN queries
                         (k=20) in the BF16 matrix-core form, FP64 form timed
                         on a 1,024-query subset
@@ -30,12 +32,13 @@ Other workloads (one JSON line each, not the headline):
                         degree-weighted queries, k=10, D=50, and how often a
                         vertex's twin is in its top-10
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat20]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload rmat24]
 """
 import argparse
 import json
 import math
 import os
+import platform
 import sys
 import time
 
@@ -51,43 +54,97 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def walk_algorithmic_bytes(R, T):
-    """Bytes the walk must move per launch: per step one 64-byte guide
-    record (three candidate edges with their targets' records) and the
-    4-byte vertex written; per path the 16-byte start record and the 4-byte
-    start written."""
-    return R * (T * (64 + 4) + 20)
+def walk_algorithmic_bytes(P, g, T):
+    """Bytes the walk must move per launch (Algorithm 3 with the inverse-CDF
+    step of Eq. 3), from the sampled paths: per step leaving vertex v, its
+    row bounds (8 B), ceil(log2 d_v) probes of 4-byte weight prefixes, the
+    chosen column (4 B) and the vertex written (4 B); per path, the start-set
+    entry read (4 B) and the start written (4 B)."""
+    import torch
+
+    deg = torch.from_numpy(np.diff(g.row_ptr.astype(np.int64))).cuda()
+    # ceil(log2 d) for d >= 1 (0 for d = 1): bit length of d - 1
+    probes = torch.zeros_like(deg)
+    x = (deg - 1).clamp(min=0)
+    while bool((x > 0).any()):
+        probes += (x > 0).to(torch.int64)
+        x >>= 1
+    paths = P.paths_device()
+    R = paths.shape[0]
+    total_probes = 0
+    for t in range(T):
+        total_probes += int(probes[paths[:, t].to(torch.int64)].sum().item())
+    del paths
+    return R * T * 16 + 4 * total_probes + R * 8, total_probes / (R * T)
 
 
-def measured_traffic(kernel):
+def index_algorithmic_bytes(R, T, nnz, n):
+    """Read every path row (4 B per vertex), write every list entry (4 B)
+    and the list offsets (8 B per vertex)."""
+    return 4 * R * (T + 1) + 4 * nnz + 8 * (n + 1)
+
+
+def count_algorithmic_bytes(lens, k):
+    """Per query: its two list offsets (16 B), per listed path its id (4 B)
+    and its 24-byte row (6 vertices), and k (id, count) pairs written."""
+    return int(16 * len(lens) + 28 * int(np.sum(lens)) + 8 * k * len(lens))
+
+
+def measured_traffic(kernel, workload):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed since the counters were taken."""
     import hashlib
 
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel]
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[kernel][workload]
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
         if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
             return None
         return rec["hbm_bytes_per_launch"]
-    except (OSError, KeyError, ValueError):
+    except (OSError, KeyError, ValueError, TypeError):
         return None
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(g, queries, T, k, seed, R_sample):
+    """The oracle on a bounded sample of the workload: R_sample paths walked
+    and indexed on one thread, then all queries answered on that index with
+    every host thread.  Value in path-steps/s of the sample."""
     import oracle
 
     oracle.build()
+    all_threads = oracle.get_threads()
+    oracle.set_threads(1)
     t0 = time.perf_counter()
     paths = oracle.walk(g, T, R_sample, seed)
+    t_walk = time.perf_counter() - t0
+    t0 = time.perf_counter()
     inv_ptr, inv_pid = oracle.index(g.n, paths)
+    t_index = time.perf_counter() - t0
+    oracle.set_threads(all_threads)
+    t0 = time.perf_counter()
     oracle.topk(g.n, paths, inv_ptr, inv_pid, queries, k)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": R_sample * T / dt, "unit": "path-steps/s", "cores": cores,
+    t_q = time.perf_counter() - t0
+    dt = t_walk + t_index + t_q
+    return {"value": R_sample * T / dt, "unit": "path-steps/s", "cores": all_threads,
             "kind": "oracle",
-            "sample": (f"oracle walk of {R_sample} paths (T={T}) + index + top-{k} of all "
-                       f"{len(queries)} queries on that index, {dt:.2f} s")}
+            "sample": (f"oracle on {R_sample} of the workload's paths (same graph, seed, T): "
+                       f"walk {t_walk:.2f} s and index {t_index:.2f} s on 1 thread, then top-{k} "
+                       f"of all {len(queries)} queries on that index {t_q:.2f} s on "
+                       f"{all_threads} threads; total {dt:.2f} s"),
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread": {"walk_path_steps_per_s": R_sample * T / t_walk,
+                              "index_entries_per_s": len(inv_pid) / t_index},
+            "all_threads": {"queries_per_s": len(queries) / t_q, "threads": all_threads}}
 
 
 def main():
@@ -95,8 +152,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="rmat20")
+    ap.add_argument("--workload", default="rmat24")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain-form comparison (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (HBM counter calibration)")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
@@ -105,7 +164,7 @@ def main():
     ap.add_argument("--allv-graph", default="rmat20")
     ap.add_argument("--allv-k", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=0,
-                    help="paths in the oracle sample (0 = the full R of the workload)")
+                    help="paths in the oracle sample (0 = R/50)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: multi-GPU sharding is designed, not built; "
@@ -183,18 +242,38 @@ def main():
     P.topk(dq, k, out=out, stream=stream)
     torch.cuda.synchronize()
     tb = time.perf_counter() - tb
-    P.set_option("topk.form", 0)
-    tp = time.perf_counter()
-    P.topk(dq, k, out=out, stream=stream)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - tp
-    plain = tuple(t.cpu().numpy() for t in out)
-    exact = all((a == b).all() for a, b in zip(batched, plain))
-    P.set_option("topk.form", 1)
+    tp, exact = None, None
+    if not args.no_plain:
+        P.set_option("topk.form", 0)
+        tp = time.perf_counter()
+        P.topk(dq, k, out=out, stream=stream)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - tp
+        plain = tuple(t.cpu().numpy() for t in out)
+        exact = all((a == b).all() for a, b in zip(batched, plain))
+        P.set_option("topk.form", 1)
 
+    # algorithmic bytes of each stage and their fractions of the HBM peak
     walk_ms = float(np.mean(stage["walk"]))
-    walk_bytes = walk_algorithmic_bytes(R, T)
-    achieved = walk_bytes / (walk_ms * 1e-3) / 1e9
+    index_ms = float(np.mean(stage["index"]))
+    topk_ms = float(np.mean(stage["topk"]))
+    walk_bytes, mean_probes = walk_algorithmic_bytes(P, g, T)
+    nnz = P.nnz()
+    ptr, _ = P.index_device(g.n)
+    lens = (ptr[1:] - ptr[:-1]).cpu().numpy()[q]
+    del ptr, _
+    idx_bytes = index_algorithmic_bytes(R, T, nnz, g.n)
+    cnt_bytes = count_algorithmic_bytes(lens, k)
+
+    def frac(b, ms):
+        gbs = b / (ms * 1e-3) / 1e9
+        return {"ms": ms, "algorithmic_bytes": int(b), "GBps": gbs, "frac": gbs / HBM_PEAK_GBS}
+
+    stages = {"walk": frac(walk_bytes, walk_ms), "index": frac(idx_bytes, index_ms),
+              "count_topk": frac(cnt_bytes, topk_ms)}
+    stages["walk"]["mean_probes_per_step"] = mean_probes
+    stages["count_topk"]["sum_list_rows"] = int(np.sum(lens))
+    achieved = stages["walk"]["GBps"]
 
     res = {
         "metric": "path-steps/s",
@@ -211,29 +290,31 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: R-MAT scale {int(math.log2(g.n))}, "
                                f"{g.m} CSR entries, lognormal weights, T={T}, R={R}, "
-                               f"{nq} queries, k={k}",
+                               f"{nq} queries ({p['queries'][0]}), k={k}",
                    "parallelism": "single GPU"},
         "stage_ms": {kk: float(np.mean(v)) for kk, v in stage.items()},
+        "stages": stages,
         "topk_batched_qps": nq / tb,
-        "topk_plain_qps": nq / tp,
-        "batched_vs_plain": tp / tb,
-        "batched_equals_plain": bool(exact),
+        "topk_plain_qps": nq / tp if tp else None,
+        "batched_vs_plain": tp / tb if tp else None,
+        "batched_equals_plain": exact,
+        # the longest single launch of a step is the walk (k_walk32, one
+        # launch); the top-k stage is several shorter hub launches
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic("k_walk32")
-                                 if args.workload == "rmat20" else None),
-                     "kernel": "k_walk32", "algorithmic_bytes_per_launch": walk_bytes,
+                     "traffic": measured_traffic("k_walk32", args.workload),
+                     "kernel": "k_walk32", "algorithmic_bytes_per_launch": int(walk_bytes),
                      "kernel_ms": walk_ms},
     }
     # achievable HBM bandwidth on this machine: a 2 GiB device-to-device copy
-    # (2 GiB read + 2 GiB written), best of 3, timed with HIP events
+    # (2 GiB read + 2 GiB written), best of 4, timed with HIP events
     copy_gbs = measured_copy_gbs()
     res["roofline"]["measured_copy_GBps"] = copy_gbs
     res["roofline"]["frac_of_measured_copy"] = achieved / copy_gbs if copy_gbs else None
+    P.close()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        res["cpu_baseline"] = cpu_baseline(g, q, T, k, seed, args.cpu_sample or R)
-    P.close()
+        res["cpu_baseline"] = cpu_baseline(g, q, T, k, seed, args.cpu_sample or R // 50)
     print(json.dumps(res), flush=True)
 
 
