@@ -5,6 +5,7 @@ configuration bench.py times (batched form) plus the plain form.  Every
 path, every index list and every top-k row is compared bit for bit with
 the oracle."""
 import os
+import sys
 
 import numpy as np
 import pytest
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 def full(oracle, inputs):
     os.environ.setdefault("PANTHER_INPUT_CACHE", "/tmp/panther_inputs")
     g, q, p = inputs.workload("rmat20")
-    print(f"case: rmat20 full size n={g.n} m={g.m} R={p['R']}", flush=True)
+    print(f"case: rmat20 full size n={g.n} m={g.m} R={p['R']}", file=sys.__stderr__, flush=True)
     paths = oracle.walk(g, p["T"], p["R"], p["seed"])
     inv_ptr, inv_pid = oracle.index(g.n, paths)
     want = oracle.topk(g.n, paths, inv_ptr, inv_pid, q, p["k"])

@@ -210,17 +210,24 @@ def test_errors_leave_context_usable(P, oracle, inputs, ba_state):
     fresh.close()
 
 
-@pytest.mark.parametrize("block,wgs,ta,tb,hb", [
-    (512, 1, -1, -1, -1), (256, 1, -1, -1, -1), (512, 2, -1, -1, -1), (256, 2, -1, -1, -1),
-    (512, 1, 0, 0, -1),     # every non-empty list goes to the split hub pipeline
-    (256, 1, 4, 0, -1),     # wave tier + hub pipeline
-    (512, 2, 1, 60, -1),    # all three tiers, small tables
-    (512, 1, 0, 0, 0),      # one bucket per hub: large ones overflow the LDS table
-    (512, 1, -1, 60, 1),    # two buckets per hub, overflow and sub-range splits
+@pytest.mark.parametrize("block,wgs,ta,tb,hb,budget", [
+    (512, 1, -1, -1, -1, 0), (256, 1, -1, -1, -1, 0), (512, 2, -1, -1, -1, 0),
+    (256, 2, -1, -1, -1, 0),
+    (512, 1, 0, 0, -1, 0),     # every non-empty list goes to the split hub pipeline
+    (256, 1, 4, 0, -1, 0),     # wave tier + hub pipeline
+    (512, 2, 1, 60, -1, 0),    # all three tiers, small tables
+    (512, 1, 0, 0, 0, 0),      # one bucket per hub: large ones overflow the LDS table
+    (512, 1, -1, 60, 1, 0),    # two buckets per hub, overflow and sub-range splits
+    # a staging budget of 64 KiB splits the hub queries into many chunks
+    # (each at least the longest list's T * L slots), as at R-MAT 24
+    (512, 1, 0, 0, -1, 1 << 16),
+    (512, 1, -1, 60, 1, 1 << 16),
+    (256, 2, 4, 0, 0, 1 << 16),
 ])
-def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb, hb):
+def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb, hb, budget):
     g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
-    _say(f"case: batched tiers block={block} wgs={wgs} ta={ta} tb={tb} hub_bits={hb}")
+    _say(f"case: batched tiers block={block} wgs={wgs} ta={ta} tb={tb} hub_bits={hb} "
+         f"hub_budget={budget}")
     P.load_graph(g)
     P.sample_paths(T, R, seed)
     P.set_option("topk.form", 1)
@@ -229,15 +236,16 @@ def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb, hb)
     P.set_option("batch.tier_a", ta)
     P.set_option("batch.tier_b", tb)
     P.set_option("batch.hub_bits", hb)
+    P.set_option("test.hub_budget", budget)
     try:
         qs = np.concatenate([inputs.queries_by_degree(g, 1500, 11),
                              np.arange(0, g.n, 97, dtype=np.int32)])
         for k in (1, 50, 300):
             want = oracle.topk(g.n, paths, inv_ptr, inv_pid, qs, k)
-            _check_topk(P.topk(qs, k), want, f"tiers {block}/{wgs}/{ta}/{tb}/{hb} k={k}")
+            _check_topk(P.topk(qs, k), want, f"tiers {block}/{wgs}/{ta}/{tb}/{hb}/{budget} k={k}")
     finally:
         for key, v in (("batch.block", 0), ("batch.wgs_per_cu", 0), ("batch.tier_a", -1),
-                       ("batch.tier_b", -1), ("batch.hub_bits", -1)):
+                       ("batch.tier_b", -1), ("batch.hub_bits", -1), ("test.hub_budget", 0)):
             P.set_option(key, v)
 
 
@@ -289,3 +297,89 @@ def test_batched_graph_replays(P, oracle, inputs, rmat14):
         _check_topk(tuple(t.cpu().numpy() for t in out), want, f"replay {rep}")
         x = (x * 1.0001).sin()  # unrelated eager work between replays
         torch.cuda.synchronize()
+
+
+def test_check_symmetric_flag(P, inputs, ba_state):
+    """PANTHER_CHECK_SYMMETRIC (Definition 1: undirected edges, stored in
+    both rows with one weight): asymmetric entries, mismatched weights and
+    unmatched parallel entries are rejected with EINVAL before anything is
+    loaded; symmetric input passes, also with rows not in column order."""
+    from paper_1504_02577_amd.panther import (PANTHER_CHECK_SYMMETRIC, PANTHER_EINVAL,
+                                              PANTHER_ESTATE, PantherError)
+
+    g, T, R, seed, paths, inv_ptr, inv_pid = ba_state
+    _say("case: symmetric check")
+    P.load_graph(g, flags=PANTHER_CHECK_SYMMETRIC)  # the BA graph is symmetric
+    P.sample_paths(T, 1000, seed)
+
+    def rejected(gg):
+        with pytest.raises(PantherError) as e:
+            P.load_graph(gg, flags=PANTHER_CHECK_SYMMETRIC)
+        assert e.value.code == PANTHER_EINVAL, e.value
+        with pytest.raises(PantherError) as e2:  # nothing loaded
+            P.sample_paths(T, 10, seed)
+        assert e2.value.code == PANTHER_ESTATE
+
+    # one weight changed on one side only
+    bad = inputs.Graph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=g.w.copy())
+    bad.w[123] += 1
+    rejected(bad)
+    # a directed edge: 0 -> 1 only
+    d = inputs.Graph(n=3, row_ptr=np.array([0, 1, 1, 1], np.int32),
+                     col=np.array([1], np.int32), w=np.array([5], np.uint32))
+    rejected(d)
+    # parallel entries: two 0->1 of weight 2, one 1->0
+    mm = inputs.Graph(n=2, row_ptr=np.array([0, 2, 3], np.int32),
+                      col=np.array([1, 1, 0], np.int32), w=np.array([2, 2, 2], np.uint32))
+    rejected(mm)
+    # the same with both copies on the other side passes; so do unsorted
+    # rows and a self-loop
+    ok = inputs.Graph(n=3, row_ptr=np.array([0, 3, 5, 6], np.int32),
+                      col=np.array([2, 1, 1, 0, 0, 0], np.int32),
+                      w=np.array([7, 2, 2, 2, 2, 7], np.uint32))
+    P.load_graph(ok, flags=PANTHER_CHECK_SYMMETRIC)
+    loop = inputs.Graph(n=2, row_ptr=np.array([0, 2, 3], np.int32),
+                        col=np.array([0, 1, 0], np.int32), w=np.array([4, 3, 3], np.uint32))
+    P.load_graph(loop, flags=PANTHER_CHECK_SYMMETRIC)
+    # without the flag a directed CSR is walked as given
+    P.load_graph(d)
+    P.sample_paths(2, 100, 1)
+    assert (P.paths()[:, 0] == 0).all() and (P.paths()[:, 1:] == 1).all()
+
+
+def test_resample_with_new_stride_after_capture(P, oracle, inputs, rmat14):
+    """A captured batched launch must not be replayed over paths of another
+    row stride: T = 9 (stride 16) twice on device buffers captures the
+    launch; after sampling T = 5 (stride 8) the same call must use the
+    stride-8 kernels."""
+    import torch
+
+    g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
+    _say("case: resample with a new stride after graph capture")
+    P.load_graph(g)
+    P.set_option("topk.form", 1)
+    qs = inputs.queries_uniform(g, 600, 31)
+    dq = torch.from_numpy(qs).cuda()
+    k = 20
+    out = (torch.empty((len(qs), k), dtype=torch.int32, device="cuda"),
+           torch.empty((len(qs), k), dtype=torch.uint32, device="cuda"),
+           torch.empty(len(qs), dtype=torch.int32, device="cuda"))
+    stream = torch.cuda.current_stream().cuda_stream
+    R9 = 60_000
+    paths9 = oracle.walk(g, 9, R9, seed)
+    p9, i9 = oracle.index(g.n, paths9)
+    want9 = oracle.topk(g.n, paths9, p9, i9, qs, k)
+    P.sample_paths(9, R9, seed)
+    for _ in range(3):
+        P.topk(dq, k, out=out, stream=stream)
+        torch.cuda.synchronize()
+        _check_topk(tuple(t.cpu().numpy() for t in out), want9, "T=9")
+    R5 = 90_000  # fewer path bytes than the T=9 run: the buffers are reused
+    paths5 = oracle.walk(g, 5, R5, seed)
+    p5, i5 = oracle.index(g.n, paths5)
+    want5 = oracle.topk(g.n, paths5, p5, i5, qs, k)
+    P.sample_paths(5, R5, seed)
+    for _ in range(3):
+        P.topk(dq, k, out=out, stream=stream)
+        torch.cuda.synchronize()
+        _check_topk(tuple(t.cpu().numpy() for t in out), want5, "T=5 after T=9")

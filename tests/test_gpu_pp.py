@@ -6,8 +6,7 @@ FP64 form must return the same ids with the same squared distances.  The
 BF16 form (matrix-core candidate pool + FP64 rerank) certifies each query's
 pool boundary against a bound on the BF16 error and recomputes uncertified
 queries exactly, so it too must return the oracle's ids, with distances
-within 1e-9 relative (here: equal, since the rerank is the oracle's FMA
-chain).
+bit-identical distances (the rerank is the oracle's FMA chain).
 """
 import numpy as np
 import pytest
@@ -47,7 +46,20 @@ def rmat(oracle, inputs):
 
 
 def check_knn(got_ids, got_d, want_ids, want_d, tag, exact_ids=False):
+    """exact_ids: ids equal and distances bit-identical (the FP64 form and
+    the BF16 form's rerank evaluate the oracle's FMA chain and IEEE square
+    root); otherwise distances within REL and ids equal outside ties."""
     assert got_ids.shape == want_ids.shape
+    if exact_ids:
+        gi, wi = np.asarray(got_ids), np.asarray(want_ids)
+        bad = np.nonzero((gi != wi).any(1))[0]
+        assert bad.size == 0, (tag, "ids differ in rows", bad[:5])
+        gd = np.ascontiguousarray(got_d, np.float64).view(np.uint64)
+        wd = np.ascontiguousarray(want_d, np.float64).view(np.uint64)
+        bad = np.nonzero((gd != wd).any(1))[0]
+        assert bad.size == 0, (tag, "distances differ in rows", bad[:5],
+                               np.asarray(got_d)[bad[0]][:4], np.asarray(want_d)[bad[0]][:4])
+        return
     for i in range(want_ids.shape[0]):
         wi, wd, gi, gd = want_ids[i], want_d[i], got_ids[i], got_d[i]
         fin = np.isfinite(wd)
