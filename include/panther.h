@@ -282,10 +282,17 @@ typedef struct panther_result {
 /* Starts serving on a context that has paths (and, for Panther++ requests,
  * computes the D-dimensional features first; D = 0 disables Panther++).
  * `lanes` (1..8) work streams run batches concurrently; a batch holds at
- * most max_batch requests; a request is admitted only while the in-flight
- * estimate (its outputs, plus its candidate pool for Panther++) stays within
- * mem_budget_bytes.  While the server runs, the context must not be used by
- * other calls.  Errors: ESTATE (no paths), EINVAL, ENOMEM, EDEVICE. */
+ * most max_batch requests.  Memory admission: each lane may hold
+ * mem_budget_bytes / lanes of device scratch.  Requests join a lane's batch,
+ * oldest first, while the batch's device memory fits that share: its rows
+ * and query ids, for a Panther request of path-list length |P_q| the
+ * batched form's staging of a hub query (about 8 * T * |P_q| bytes plus its
+ * buckets and winners), and the candidate pools of a Panther++ call of that
+ * many queries -- the sizes the kernels allocate.  A lane whose kept scratch
+ * plus the next batch's need would pass its share frees its scratch first,
+ * so the lanes together hold at most mem_budget_bytes.  While the server
+ * runs, the context must not be used by other calls.
+ * Errors: ESTATE (no paths), EINVAL, ENOMEM, EDEVICE. */
 int panther_server_start(panther_ctx *ctx, int64_t mem_budget_bytes,
                          int32_t max_batch, int32_t lanes, int32_t D,
                          panther_server **out);
@@ -293,7 +300,7 @@ int panther_server_start(panther_ctx *ctx, int64_t mem_budget_bytes,
 /* Queues a request (thread-safe): kind 0 = Panther top-k of q (k <= 256),
  * kind 1 = Panther++ top-k of q (k <= 256).  Errors: EINVAL, ERANGE (q
  * outside [0, n)), ESTATE (stopping, or kind 1 with D = 0), ENOMEM (the
- * request alone exceeds the budget). */
+ * request alone needs more than one lane's share of the budget). */
 int panther_server_submit(panther_server *srv, int32_t kind, int32_t q,
                           int32_t k, uint64_t tag);
 
@@ -305,6 +312,13 @@ int panther_server_poll(panther_server *srv, panther_result *results,
 /* Latency percentiles and throughput over all completed requests. */
 int panther_server_stats(panther_server *srv, double *p50_ms, double *p99_ms,
                          double *qps, int64_t *completed);
+
+/* Memory admission of the server: *lane_share_bytes = mem_budget_bytes /
+ * lanes, and *peak_lane_bytes = the most device scratch any lane has held
+ * after a batch (never above the share).  Either pointer may be NULL.
+ * Errors: EINVAL (NULL server). */
+int panther_server_memory(panther_server *srv, int64_t *lane_share_bytes,
+                          int64_t *peak_lane_bytes);
 
 /* Finishes every queued request, stops the threads and frees the server;
  * uncollected results are dropped.  Returns EDEVICE if any batch failed. */

@@ -915,6 +915,59 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   return PANTHER_OK;
 }
 
+// Device bytes one query with path list length L adds to a batched call
+// of this lane with k <= kmax (an upper bound: per-chunk buffers are sized
+// by the largest chunk, and every query is counted whole): its plan entry
+// and list length, and for a hub query its staging in row and bucket order,
+// bucket counters and maps, winners and tile maps.
+BatchSizing batched_sizing(panther_ctx* c, Lane* lane) {
+  BatchState* b = state(lane);
+  const Layout lay = layout_for(c, b->tuned ? b->cfg : BatchConfig{});
+  BatchSizing z{};
+  z.T = (uint64_t)c->T;
+  z.LB = (uint64_t)lay.TB / (2 * z.T);
+  if (b->tier_b_override >= 0) z.LB = std::min(z.LB, (uint64_t)b->tier_b_override);
+  z.hub_bits_max = b->hub_bits_max;
+  return z;
+}
+
+size_t batched_query_bytes(const BatchSizing& z, uint64_t L, int32_t kmax) {
+  const uint64_t T = z.T;
+  size_t bytes = sizeof(int32_t) + sizeof(uint64_t);
+  if (L <= z.LB) return bytes;
+  const uint64_t occ = T * L;
+  const int bb = std::min(hub_bucket_bits(occ), z.hub_bits_max);
+  const uint64_t nb = (uint64_t)1 << bb;
+  const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(kmax, kEmitCap) << bb, occ);
+  bytes += 2 * sizeof(int32_t) * occ;                                       // staging
+  bytes += (3 * sizeof(uint32_t) + 2 * sizeof(uint64_t) + sizeof(int32_t)) * nb;  // buckets
+  bytes += scan_temp_bytes((int64_t)nb) + sizeof(uint64_t) * cand + sizeof(uint32_t);
+  bytes += sizeof(HubQuery) + sizeof(HubList) +
+           sizeof(int32_t) * ((size_t)hub_tiles(L) + hub_stiles(L));
+  return bytes;
+}
+
+// Device bytes of a batched call's fixed buffers (plan minimum, queue).
+size_t batched_fixed_bytes() { return sizeof(int32_t) * 1024 + 64 + sizeof(uint32_t) * 16 + 256; }
+
+// Device bytes the lane's query scratch holds now.
+size_t lane_device_bytes(const Lane* lane) {
+  size_t t = 0;
+  for (const DevBuf* d : {&lane->b_qlen, &lane->b_pool, &lane->b_out, &lane->b_stats, &lane->b_q,
+                          &lane->b_qrows, &lane->b_fb, &lane->b_fbw, &lane->b_qsort,
+                          &lane->b_qsort_tmp})
+    t += d->p ? d->cap : 0;
+  const BatchState* b = lane->batch;
+  if (!b) return t;
+  t += sizeof(int32_t) * b->items_cap + (b->d_queue ? 64 : 0);
+  t += sizeof(HubQuery) * b->hq_cap + sizeof(int32_t) * (b->occ_cap + b->occB_cap);
+  t += sizeof(uint32_t) * (b->bkt_cap + b->bkt_fill_cap + b->redo_cap + b->cand_n_cap);
+  t += sizeof(uint64_t) * (b->bkt_start_cap + b->cand_cap + b->bkt_cand0_cap);
+  t += sizeof(HubList) * b->hx_cap + b->scan_cap;
+  t += sizeof(int32_t) * (b->tile_owner_cap + b->stile_owner_cap + b->bkt_owner_cap);
+  return t;
+}
+
 int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* qlen, int64_t nq,
                 int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
                 hipStream_t s) {

@@ -34,7 +34,6 @@
 #include <cstring>
 #include <vector>
 
-#include <hipcub/hipcub.hpp>
 
 #include "../../include/panther.h"
 #include "common.h"
@@ -919,17 +918,53 @@ k_pp_rerank(RerankArgs A) {
 }
 
 
-// Ascending sort of n (uint32 key, int32 value) pairs with hipCUB; tmp
-// holds the library's scratch.
+// Scratch bytes of sort_pairs for n pairs.
+size_t sort_pairs_bytes(int64_t n) {
+  const uint64_t tiles = radix_tiles_pairs((uint64_t)std::max<int64_t>(n, 1));
+  const size_t hist = 256 * (size_t)tiles;
+  return sizeof(uint32_t) * hist + sizeof(uint64_t) * (hist + 1) + scan_temp_bytes((int64_t)hist) +
+         64 + 2 * sizeof(uint32_t) * (size_t)std::max<int64_t>(n, 1) + 4 * 256;
+}
+
+// Ascending, stable sort of n (uint32 key, int32 value) pairs by the same
+// LSD radix passes as the index build (four 8-bit digits); tmp holds the
+// per-tile histograms, their scan, the pair count and a ping-pong copy.
+// kin and vin are only read.
 int sort_pairs(panther_ctx* c, DevBuf& tmp, const uint32_t* kin, uint32_t* kout,
                const int32_t* vin, int32_t* vout, int64_t n, hipStream_t s) {
   if (n <= 0) return PANTHER_OK;
-  size_t bytes = 0;
-  HIPTRY(hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, kin, kout, vin, vout, (int)n, 0, 32, s),
-         "sort scratch size");
-  TRY(ctx_ensure(c, tmp, bytes, "sort scratch"));
-  HIPTRY(hipcub::DeviceRadixSort::SortPairs(tmp.p, bytes, kin, kout, vin, vout, (int)n, 0, 32, s),
-         "sort");
+  const uint64_t tiles = radix_tiles_pairs((uint64_t)n);
+  const size_t hist_n = 256 * (size_t)tiles;
+  TRY(ctx_ensure(c, tmp, sort_pairs_bytes(n), "sort scratch"));
+  char* p = static_cast<char*>(tmp.p);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(p);
+  p += sizeof(uint32_t) * hist_n;
+  p = reinterpret_cast<char*>(((uintptr_t)p + 255) & ~(uintptr_t)255);
+  uint64_t* offs = reinterpret_cast<uint64_t*>(p);
+  p += sizeof(uint64_t) * (hist_n + 1);
+  p = reinterpret_cast<char*>(((uintptr_t)p + 255) & ~(uintptr_t)255);
+  void* scan_tmp = p;
+  p += scan_temp_bytes((int64_t)hist_n);
+  p = reinterpret_cast<char*>(((uintptr_t)p + 255) & ~(uintptr_t)255);
+  uint64_t* count = reinterpret_cast<uint64_t*>(p);
+  p += 64;
+  uint32_t* k1 = reinterpret_cast<uint32_t*>(p);
+  uint32_t* v1 = k1 + n;
+  k_fill_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long*>(count), 1,
+                              (unsigned long long)n);
+  const uint32_t* ki = kin;
+  const uint32_t* vi = reinterpret_cast<const uint32_t*>(vin);
+  for (int pass = 0; pass < 4; ++pass) {
+    // passes alternate between the ping-pong copy and the output
+    uint32_t* ko = pass % 2 == 0 ? k1 : kout;
+    uint32_t* vo = pass % 2 == 0 ? v1 : reinterpret_cast<uint32_t*>(vout);
+    launch_radix_up_pairs(ki, count, (uint64_t)n, 8 * pass, 8, hist, s);
+    launch_scan_u32_to_u64(hist, offs, (int64_t)hist_n, scan_tmp, s);
+    launch_radix_down_pairs(ki, vi, count, (uint64_t)n, 8 * pass, 8, offs, ko, vo, s);
+    ki = ko;
+    vi = vo;
+  }
+  HIPTRY(hipGetLastError(), "sort");
   return PANTHER_OK;
 }
 
@@ -1015,6 +1050,44 @@ int prepare_bf16(panther_ctx* c, int32_t D, hipStream_t s) {
 
 namespace panther {
 
+namespace {
+
+// Candidate-pool geometry of a BF16 call with nq queries.
+struct PoolGeom {
+  int P;          // pool per query
+  int cap;        // buffer entries per (query, slice)
+  int qw;         // queries per work-group tile
+  int64_t tiles;  // query tiles
+  int64_t S;      // database slices per tile
+};
+
+PoolGeom pool_geom(const panther_ctx* c, int64_t nq, int32_t k) {
+  PoolGeom g{};
+  // pool: at least the option and at least 2k (margin for the bfloat16
+  // rounding at the pool boundary), a power of two, at most 1024
+  g.P = 32;
+  while (g.P < c->pp_pool || g.P < 2 * k) g.P <<= 1;
+  if (g.P > 1024) g.P = 1024;
+  // buffer: P kept keys, at least P more before a compaction is worth its
+  // sort, and room for the kCheckEvery chunks between checks
+  g.cap = 2 * g.P + kCheckEvery * kChunk;
+  // Query tiles: 32 queries per work-group for large batches, 16 for
+  // small ones (a tile scans the union of its queries' norm bands, so
+  // narrower tiles scan fewer rows; wider ones reuse each row more).  The
+  // database is split into slices when the batch has few tiles, so that
+  // about two work-groups per CU scan it.
+  g.qw = nq >= 8192 ? 32 : 16;
+  g.tiles = (nq + g.qw - 1) / g.qw;
+  const int64_t rows = c->pp && c->pp->bf16_rows ? c->pp->bf16_rows : (int64_t)c->n;
+  int64_t S = (2 * (int64_t)c->num_cus + g.tiles - 1) / std::max<int64_t>(g.tiles, 1);
+  S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, rows / 4096));
+  S = std::min<int64_t>(S, std::max<int64_t>(1, 262144 / g.P));  // bounds the merge work
+  g.S = S;
+  return g;
+}
+
+}  // namespace
 
 // Pool pass + rerank over the database context c.  qtheta (null: c's own
 // features) holds the queries' feature rows when they come from another
@@ -1024,26 +1097,10 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   PPState* pp = c->pp;
   if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
   if (!pp || pp->bf16_D != D) return ctx_fail(c, PANTHER_ESTATE, "bf16 rows not prepared");
-  // pool: at least the option and at least 2k (margin for the bfloat16
-  // rounding at the pool boundary), a power of two, at most 1024
-  int P = 32;
-  while (P < c->pp_pool || P < 2 * k) P <<= 1;
-  if (P > 1024) P = 1024;
-  // buffer: P kept keys, at least P more before a compaction is worth its
-  // sort, and room for the kCheckEvery chunks between checks
-  const int cap = 2 * P + kCheckEvery * kChunk;
+  const PoolGeom G = pool_geom(c, nq, k);
+  const int P = G.P, cap = G.cap, qw = G.qw;
+  const int64_t tiles = G.tiles, S = G.S;
   const float scale = (float)c->R;
-  // Query tiles: 32 queries per work-group for large batches, 16 for
-  // small ones (a tile scans the union of its queries' norm bands, so
-  // narrower tiles scan fewer rows; wider ones reuse each row more).  The
-  // database is split into slices when the batch has few tiles, so that
-  // about two work-groups per CU scan it.
-  const int qw = nq >= 8192 ? 32 : 16;
-  const int64_t tiles = (nq + qw - 1) / qw;
-  int64_t S = (2 * (int64_t)c->num_cus + tiles - 1) / tiles;
-  S = std::max<int64_t>(1, std::min<int64_t>(S, 256));
-  S = std::min<int64_t>(S, std::max<int64_t>(1, pp->bf16_rows / 4096));
-  S = std::min<int64_t>(S, std::max<int64_t>(1, 262144 / P));  // bounds the merge work
   const size_t buf_bytes = sizeof(uint64_t) * (size_t)nq * S * cap;
   const size_t part_bytes = S > 1 ? sizeof(uint64_t) * (size_t)nq * S * P : 0;
   const size_t ids_bytes = (sizeof(int32_t) + sizeof(float)) * (size_t)nq * P;
@@ -1208,3 +1265,23 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
 }
 
 }  // namespace panther
+
+// Device bytes of the lane scratch a BF16 call of nq queries takes (the
+// FP64 form takes none): pools, statistics, query order and its sort,
+// certificate, exact recompute of every query, cross-graph query rows.
+size_t pp_lane_bytes(const panther_ctx* c, int64_t nq, int32_t k) {
+  if (nq <= 0) return 0;
+  if (c->pp_form == PANTHER_PP_FP64) return 0;
+  const panther::PoolGeom G = panther::pool_geom(c, nq, k);
+  const size_t n = (size_t)nq;
+  size_t b = sizeof(uint64_t) * n * G.S * G.cap + sizeof(uint64_t) * n +
+             (G.S > 1 ? sizeof(uint64_t) * n * G.S * G.P : 0) +
+             (sizeof(int32_t) + sizeof(float)) * n * G.P + 256;
+  b += 64;
+  b += (2 * sizeof(uint32_t) + 2 * sizeof(int32_t)) * ((n + 63) / 64 * 64);
+  b += sort_pairs_bytes(nq);
+  b += (2 * sizeof(int32_t) + sizeof(double)) * n;
+  b += panther::knn_range_bytes(nq);
+  b += (sizeof(uint16_t) * 64 + sizeof(float)) * n;
+  return b;
+}

@@ -153,6 +153,22 @@ void free_batch_state(Lane* lane);
 // drops the lane's captured graph and its repeat detection (new paths)
 void forget_batch_graph(Lane* lane);
 void free_lane(Lane* lane);
+// Memory accounting of the serving loop's admission: the lane's tier and
+// bucket limits (taken while the lane is idle), an upper bound on the device
+// bytes a query with path-list length L adds to a batched call of that lane
+// (k <= kmax), the call's fixed bytes, and what a lane holds now.
+struct BatchSizing {
+  uint64_t T;
+  uint64_t LB;       // longest list counted in one work-group's LDS table
+  int hub_bits_max;  // largest log2 bucket count of a hub query
+};
+BatchSizing batched_sizing(panther_ctx* c, Lane* lane);
+size_t batched_query_bytes(const BatchSizing& z, uint64_t L, int32_t kmax);
+size_t batched_fixed_bytes();
+size_t lane_device_bytes(const Lane* lane);
+// Device bytes of the lane scratch a Panther++ call of nq queries uses
+// (k <= kmax), in the context's current form.
+size_t pp_lane_bytes(const panther_ctx* c, int64_t nq, int32_t kmax);
 
 // Panther++ (pp.hip, knn.hip, pp_bf16.hip)
 void free_pp_state(panther_ctx* c);

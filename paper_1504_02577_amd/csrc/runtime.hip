@@ -615,12 +615,31 @@ extern "C" int panther_get_paths(panther_ctx* c, int32_t* out, int mem) {
   if (!c->has_paths) return ctx_fail(c, PANTHER_ESTATE, "no paths sampled");
   if (!out) return ctx_fail(c, PANTHER_EINVAL, "null output");
   const size_t w = sizeof(int32_t) * (size_t)(c->T + 1);
-  HIPTRY(hipMemcpy2DAsync(out, w, c->d_paths, sizeof(int32_t) * (size_t)c->stride, w,
-                          (size_t)c->R,
-                          mem == PANTHER_MEM_DEVICE ? hipMemcpyDeviceToDevice
-                                                    : hipMemcpyDeviceToHost,
-                          c->stream),
-         "get_paths");
+  const size_t pitch = sizeof(int32_t) * (size_t)c->stride;
+  if (mem == PANTHER_MEM_DEVICE) {
+    HIPTRY(hipMemcpy2DAsync(out, w, c->d_paths, pitch, w, (size_t)c->R, hipMemcpyDeviceToDevice,
+                            c->stream),
+           "get_paths");
+  } else {
+    // rows are packed on the device chunk by chunk (a strided copy straight
+    // to host memory moves one short row at a time), then copied whole
+    const size_t chunk = (size_t)1 << 22;  // rows per chunk
+    void* p;
+    TRY(ctx_alloc(c, &p, w * std::min<size_t>(chunk, (size_t)c->R), "path staging"));
+    Temp tmp;
+    tmp.add(p);
+    for (size_t r0 = 0; r0 < (size_t)c->R; r0 += chunk) {
+      const size_t rows = std::min<size_t>(chunk, (size_t)c->R - r0);
+      HIPTRY(hipMemcpy2DAsync(p, w, c->d_paths + r0 * (size_t)c->stride, pitch, w, rows,
+                              hipMemcpyDeviceToDevice, c->stream),
+             "get_paths");
+      HIPTRY(hipMemcpyAsync(reinterpret_cast<char*>(out) + r0 * w, p, w * rows,
+                            hipMemcpyDeviceToHost, c->stream),
+             "get_paths");
+    }
+    HIPTRY(hipStreamSynchronize(c->stream), "get_paths");
+    return PANTHER_OK;
+  }
   HIPTRY(hipStreamSynchronize(c->stream), "get_paths");
   return PANTHER_OK;
 }

@@ -2,11 +2,18 @@
 // resident paths, index and features.
 //
 // Requests enter a queue (panther_server_submit, any host thread).  A
-// scheduler thread admits them into batches while a lane is free and the
-// in-flight memory estimate stays within the budget, and hands each batch to
-// a lane.  Every lane has its own HIP stream, host worker thread and query
-// scratch, so batches of different lanes run on the device at the same time
-// while later requests keep being admitted.  A batch runs its Panther
+// scheduler thread admits them, oldest first, into a batch for a free lane
+// while the device memory the batch needs fits the lane's share of the
+// budget (budget / lanes), and hands the batch to the lane.  A batch's need
+// is computed with the same sizes the lane's kernels allocate with: for a
+// Panther request, from its path-list length (a hub query's staging grows
+// with T * |P_q|); for the Panther++ requests, the candidate pools of a call
+// of that many queries.  A lane whose held scratch plus the next batch's
+// need would exceed its share frees its scratch first, so the lanes never
+// hold more than the budget between them.  Every lane has its own HIP
+// stream, host worker thread and query scratch, so batches of different
+// lanes run on the device at the same time while later requests keep being
+// admitted.  A batch runs its Panther
 // requests as one batched top-k call with k = the largest k asked (the top-k
 // of a request is the prefix of that list, since the ranking is a total
 // order) and its Panther++ requests as one Panther++ call likewise.
@@ -39,12 +46,15 @@ struct Request {
   int32_t q;
   int32_t k;
   double t_submit;
-  size_t mem;
+  size_t mem;  // Panther: its share of a batched call; Panther++: its outputs
 };
 
 struct Batch {
   std::vector<Request> reqs;
-  size_t mem = 0;
+  size_t mem_panther = 0;  // sum over its Panther requests
+  size_t mem_pp = 0;       // sum over its Panther++ requests' outputs
+  int64_t n_pp = 0;
+  size_t mem = 0;          // device bytes the batch needs on its lane
 };
 
 struct LaneWorker {
@@ -78,7 +88,10 @@ struct panther_server {
   std::mutex mu;
   std::condition_variable cv;        // pending queue / lane availability
   std::deque<Request> pending;
-  size_t inflight_mem = 0;
+  size_t share = 0;                  // device bytes each lane may hold
+  std::vector<uint64_t> list_ptr;    // host copy of the index offsets (|P_q|)
+  BatchSizing sizing{};              // the lanes' tier limits (all lanes alike)
+  std::atomic<int64_t> peak_lane{0};  // most device bytes a lane held
   std::atomic<bool> stopping{false};
   std::mutex done_mu;
   std::condition_variable done_cv;
@@ -89,18 +102,28 @@ struct panther_server {
   std::atomic<int> failures{0};
 };
 
-static size_t request_mem(const panther_server* sv, int kind, int32_t k) {
-  // device bytes a request holds while in flight: its outputs and, for
-  // Panther++, its candidate pool (pool keys, ids and approximate distances)
-  size_t b = (size_t)k * 16 + 64;
-  if (kind == 1) {
-    int P = 32;
-    while (P < sv->c->pp_pool || P < 2 * k) P <<= 1;
-    if (P > 1024) P = 1024;
-    const size_t cap = 2 * (size_t)P + 256;
-    b += cap * 8 + (size_t)P * 8;
-  }
-  return b;
+// Device bytes of a request's query id and output rows on its lane (a
+// batch's rows are as wide as its largest k, at most PANTHER_SERVER_KMAX).
+constexpr size_t kRowBytes =
+    sizeof(int32_t) + PANTHER_SERVER_KMAX * (sizeof(int32_t) + sizeof(double)) + sizeof(int32_t);
+
+static size_t request_mem(const panther_server* sv, int kind, int32_t q) {
+  if (kind == 1) return kRowBytes;
+  const uint64_t L = sv->list_ptr[(size_t)q + 1] - sv->list_ptr[(size_t)q];
+  return kRowBytes + batched_query_bytes(sv->sizing, L, PANTHER_SERVER_KMAX);
+}
+
+// Device bytes a batch needs on a lane: the batched call's fixed buffers,
+// its Panther requests' shares, and the Panther++ call of n_pp queries.
+static size_t batch_mem(const panther_server* sv, size_t mem_panther, size_t mem_pp,
+                        int64_t n_pp) {
+  return batched_fixed_bytes() + mem_panther + mem_pp +
+         pp_lane_bytes(sv->c, n_pp, PANTHER_SERVER_KMAX);
+}
+
+static size_t lane_held(LaneWorker* w) {
+  return lane_device_bytes(&w->lane) + (w->d_q.p ? w->d_q.cap : 0) +
+         (w->d_out.p ? w->d_out.cap : 0);
 }
 
 static void finish(panther_server* sv, const Request& r, const int32_t* ids, const uint32_t* cnt,
@@ -211,10 +234,21 @@ static void lane_main(panther_server* sv, LaneWorker* w) {
       b = std::move(w->batch);
       w->has_batch = false;
     }
+    // buffers only grow within a call: if what the lane keeps plus what this
+    // batch may add could pass the lane's share, start from nothing
+    if (lane_held(w) + b.mem > sv->share) {
+      (void)hipStreamSynchronize(w->stream);
+      free_lane(&w->lane);
+      ctx_release(w->d_q);
+      ctx_release(w->d_out);
+    }
     run_batch(sv, w, b);
+    const int64_t held = (int64_t)lane_held(w);
+    for (int64_t cur = sv->peak_lane.load(); held > cur &&
+                                             !sv->peak_lane.compare_exchange_weak(cur, held);) {
+    }
     {
       std::lock_guard<std::mutex> g(sv->mu);
-      sv->inflight_mem -= b.mem;
       w->busy = false;
     }
     sv->cv.notify_all();
@@ -225,15 +259,13 @@ static void scheduler_main(panther_server* sv) {
   (void)hipSetDevice(sv->c->device);
   while (true) {
     std::unique_lock<std::mutex> lk(sv->mu);
-    // wake when a request can start: a lane is free and the oldest request
-    // fits the memory budget (or nothing is in flight)
+    // wake when a request can start: a lane is free (every request fits a
+    // lane's share on its own, which submit checked)
     sv->cv.wait(lk, [&] {
       if (sv->pending.empty()) return sv->stopping.load();
       bool lane_free = false;
       for (LaneWorker* w : sv->lanes) lane_free = lane_free || !w->busy;
-      if (!lane_free) return false;
-      return sv->inflight_mem == 0 ||
-             sv->inflight_mem + sv->pending.front().mem <= (size_t)sv->budget;
+      return lane_free;
     });
     if (sv->pending.empty() && sv->stopping.load()) return;
     LaneWorker* lane = nullptr;
@@ -243,18 +275,24 @@ static void scheduler_main(panther_server* sv) {
         break;
       }
     if (!lane) continue;
-    // admission: the oldest requests whose memory fits the budget
+    // admission: the oldest requests, in order, while the batch's device
+    // memory fits the lane's share
     Batch b;
     while (!sv->pending.empty() && (int32_t)b.reqs.size() < sv->max_batch) {
       const Request& r = sv->pending.front();
-      if (sv->inflight_mem + b.mem + r.mem > (size_t)sv->budget && !b.reqs.empty()) break;
-      if (sv->inflight_mem + b.mem + r.mem > (size_t)sv->budget && sv->inflight_mem > 0) break;
-      b.mem += r.mem;
+      const size_t mp = b.mem_panther + (r.kind == 0 ? r.mem : 0);
+      const size_t mq = b.mem_pp + (r.kind == 1 ? r.mem : 0);
+      const int64_t npp = b.n_pp + (r.kind == 1 ? 1 : 0);
+      const size_t need = batch_mem(sv, mp, mq, npp);
+      if (need > sv->share && !b.reqs.empty()) break;
+      b.mem_panther = mp;
+      b.mem_pp = mq;
+      b.n_pp = npp;
+      b.mem = need;
       b.reqs.push_back(r);
       sv->pending.pop_front();
     }
-    if (b.reqs.empty()) continue;  // wait for memory to free up
-    sv->inflight_mem += b.mem;
+    if (b.reqs.empty()) continue;
     lane->busy = true;
     lk.unlock();
     {
@@ -285,9 +323,15 @@ extern "C" int panther_server_start(panther_ctx* c, int64_t mem_budget_bytes, in
   panther_server* sv = new panther_server();
   sv->c = c;
   sv->budget = mem_budget_bytes;
+  sv->share = (size_t)mem_budget_bytes / (size_t)lanes;
   sv->max_batch = max_batch;
   sv->D = D;
-  int st = PANTHER_OK;
+  // path-list lengths on the host, for the admission estimate of each
+  // Panther request
+  sv->list_ptr.resize((size_t)c->n + 1);
+  int st = ctx_hip(c, hipMemcpy(sv->list_ptr.data(), c->d_inv_ptr,
+                                sizeof(uint64_t) * ((size_t)c->n + 1), hipMemcpyDeviceToHost),
+                   "server list offsets");
   for (int i = 0; i < lanes && !st; ++i) {
     LaneWorker* w = new LaneWorker();
     sv->lanes.push_back(w);
@@ -311,6 +355,7 @@ extern "C" int panther_server_start(panther_ctx* c, int64_t mem_budget_bytes, in
     delete sv;
     return st;
   }
+  sv->sizing = batched_sizing(c, &sv->lanes[0]->lane);  // all lanes share the options
   for (LaneWorker* w : sv->lanes) w->th = std::thread(lane_main, sv, w);
   sv->scheduler = std::thread(scheduler_main, sv);
   *out = sv;
@@ -324,11 +369,13 @@ extern "C" int panther_server_submit(panther_server* sv, int32_t kind, int32_t q
   if (kind == 1 && sv->D == 0) return PANTHER_ESTATE;
   if (k < 1 || k > PANTHER_SERVER_KMAX || (kind == 1 && k > 256)) return PANTHER_EINVAL;
   if (q < 0 || q >= sv->c->n) return PANTHER_ERANGE;
-  Request r{tag, kind, q, k, now_ms(), request_mem(sv, kind, k)};
+  Request r{tag, kind, q, k, now_ms(), request_mem(sv, kind, q)};
+  // the request must fit a lane's share on its own
+  const size_t alone = batch_mem(sv, kind == 0 ? r.mem : 0, kind == 1 ? r.mem : 0, kind);
   {
     std::lock_guard<std::mutex> g(sv->mu);
     if (sv->stopping) return PANTHER_ESTATE;
-    if (r.mem > (size_t)sv->budget) return PANTHER_ENOMEM;
+    if (alone > sv->share) return PANTHER_ENOMEM;
     sv->pending.push_back(r);
   }
   sv->cv.notify_all();
@@ -374,6 +421,14 @@ extern "C" int panther_server_stats(panther_server* sv, double* p50_ms, double* 
   if (qps) *qps = (t1 > t0 && done > 0) ? (double)done / ((t1 - t0) * 1e-3) : 0.0;
   if (completed) *completed = done;
   return sv->failures.load() ? PANTHER_EDEVICE : PANTHER_OK;
+}
+
+extern "C" int panther_server_memory(panther_server* sv, int64_t* lane_share_bytes,
+                                     int64_t* peak_lane_bytes) {
+  if (!sv) return PANTHER_EINVAL;
+  if (lane_share_bytes) *lane_share_bytes = (int64_t)sv->share;
+  if (peak_lane_bytes) *peak_lane_bytes = sv->peak_lane.load();
+  return PANTHER_OK;
 }
 
 extern "C" int panther_server_stop(panther_server* sv) {

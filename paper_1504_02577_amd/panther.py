@@ -41,7 +41,8 @@ EXPORTS = [
     "panther_sample_size", "panther_set_option", "panther_get_paths", "panther_index_nnz",
     "panther_get_index", "panther_get_features", "panther_pp_stats", "panther_synchronize",
     "panther_stage_times", "panther_server_start", "panther_server_submit",
-    "panther_server_poll", "panther_server_stats", "panther_server_stop",
+    "panther_server_poll", "panther_server_stats", "panther_server_memory",
+    "panther_server_stop",
 ]
 
 PANTHER_SERVER_KMAX = 256
@@ -106,6 +107,7 @@ def lib():
         "panther_server_poll": (ctypes.c_int, [P, ctypes.POINTER(PantherResult), i32, i32]),
         "panther_server_stats": (ctypes.c_int, [P, ctypes.POINTER(dbl), ctypes.POINTER(dbl),
                                                 ctypes.POINTER(dbl), ctypes.POINTER(i64)]),
+        "panther_server_memory": (ctypes.c_int, [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "panther_server_stop": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
@@ -223,6 +225,12 @@ def panther_server_stats(srv):
     return st, a.value, b.value, c.value, n.value
 
 
+def panther_server_memory(srv):
+    share, peak = ctypes.c_int64(), ctypes.c_int64()
+    st = lib().panther_server_memory(srv, ctypes.byref(share), ctypes.byref(peak))
+    return st, share.value, peak.value
+
+
 def panther_server_stop(srv):
     return lib().panther_server_stop(srv)
 
@@ -256,6 +264,10 @@ class Server:
     def stats(self):
         st, p50, p99, qps, done = panther_server_stats(self.h)
         return dict(status=st, p50_ms=p50, p99_ms=p99, qps=qps, completed=done)
+
+    def memory(self):
+        st, share, peak = panther_server_memory(self.h)
+        return dict(status=st, lane_share_bytes=share, peak_lane_bytes=peak)
 
     def stop(self):
         if self.h:

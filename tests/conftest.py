@@ -39,3 +39,22 @@ def ba1k_paths(oracle, ba1k):
     paths = oracle.walk(ba1k, 5, 100_000, 1)
     inv_ptr, inv_pid = oracle.index(ba1k.n, paths)
     return paths, inv_ptr, inv_pid
+
+
+@pytest.fixture(scope="session")
+def progress(request):
+    """say(...) writes a progress line to the terminal at once, past output
+    capture (long stages of the large-workload tests report as each ends)."""
+    tr = request.config.pluginmanager.get_plugin("terminalreporter")
+    capman = request.config.pluginmanager.get_plugin("capturemanager")
+
+    def say(*a):
+        msg = " ".join(str(x) for x in a)
+        if tr is None or capman is None:
+            print(msg, flush=True)
+            return
+        with capman.global_and_fixture_disabled():
+            tr.write_line(msg)
+            tr.flush()
+
+    return say

@@ -69,3 +69,12 @@ def test_product_path_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text, f
+
+
+def test_every_symbol_resolves_at_load(L):
+    """Loading with immediate binding: an undefined symbol in the library
+    (a declaration whose definition landed in another namespace) fails here
+    rather than on first use."""
+    from paper_1504_02577_amd import panther
+
+    ctypes.CDLL(panther.LIB_PATH, mode=os.RTLD_NOW | os.RTLD_LOCAL)

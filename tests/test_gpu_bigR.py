@@ -11,8 +11,6 @@ paths (including the first and last id), every list restricted to three
 windows of path ids (the oracle's index of the window's paths), and the
 top-50 of eight queries, among them the highest ids, whose lists start past
 2^32."""
-import sys
-
 import numpy as np
 import pytest
 
@@ -21,13 +19,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1500)]
 T, R, SEED, K = 5, 850_000_000, 3, 50
 
 
-def _say(*a):
-    # progress of long stages goes to the process's stderr, past pytest's
-    # capture, as each stage ends
-    print(*a, file=sys.__stderr__, flush=True)
-
-
-def test_index_beyond_2_32(oracle, inputs):
+def test_index_beyond_2_32(oracle, inputs, progress):
+    _say = progress
     import time
 
     import torch

@@ -8,33 +8,29 @@ the benchmarked call (all 65,536 queries in one call, device buffers) and a
 1,024-query call; on a seeded sample of 1,024 queries both must return the
 oracle's exact FP64 neighbours (Sec. 3.3): the same ids and bit-identical
 distances.  The FP64 form is checked on 128 of them."""
-import sys
-
 import numpy as np
 import pytest
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(1500)]
 
 
-def _say(*a):
-    # progress of long stages goes to the process's stderr, past pytest's
-    # capture, as each stage ends
-    print(*a, file=sys.__stderr__, flush=True)
-
-
 @pytest.fixture(scope="module")
-def c4(oracle, inputs):
+def c4(oracle, inputs, progress):
+    _say = progress
     import time
 
     t0 = time.time()
+    _say("case: rmat22_pp: generating the inputs")
     g, q, p = inputs.workload("rmat22_pp")
     _say(f"case: rmat22_pp n={g.n} m={g.m} R={p['R']} (inputs {time.time() - t0:.0f} s)")
     t0 = time.time()
     paths = oracle.walk(g, p["T"], p["R"], p["seed"])
     inv_ptr, inv_pid = oracle.index(g.n, paths)
+    _say(f"  oracle walk + index {time.time() - t0:.0f} s")
+    t0 = time.time()
     theta = oracle.features(g.n, paths, inv_ptr, inv_pid, p["D"])
     del paths, inv_pid
-    _say(f"  oracle walk + index + features {time.time() - t0:.0f} s")
+    _say(f"  oracle features {time.time() - t0:.0f} s")
     rng = np.random.default_rng(1024)
     sample = np.sort(rng.choice(len(q), 1024, replace=False))
     t0 = time.time()
@@ -52,7 +48,8 @@ def _exact(gi, gd, wi, wd, tag):
     assert bad.size == 0, f"{tag}: distances differ in {bad.size} rows, first {bad[:5]}"
 
 
-def test_rmat22_features_and_knn(c4):
+def test_rmat22_features_and_knn(c4, progress):
+    _say = progress
     import torch
     from paper_1504_02577_amd.panther import Panther
 
