@@ -170,6 +170,27 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * Errors: EINVAL (unknown key or value out of range). */
 int panther_set_option(panther_ctx *ctx, const char *key, int64_t value);
 
+/* Allocation-free Panther top-k, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation.  Same results as panther_topk_similar (the plain
+ * form's kernels, one launch per query), with the dense per-vertex counters
+ * in a fixed 64 MiB device array that each GPU holds from library load
+ * until the process ends.  Limit: graphs of at most 8,388,600 vertices
+ * (EINVAL above).  queries, out_ids, out_counts and out_len are device
+ * memory (layout as panther_topk_similar); the call only enqueues kernels
+ * on `stream` (NULL = the context's stream) and returns: it allocates
+ * nothing, copies nothing to the host and does not wait.  Because query ids
+ * are not read on the host, an id outside [0, n) does not fail the call: its
+ * row is written as padding (-1, 0) with out_len = -1.  Every call on a GPU
+ * uses that GPU's one array (clearing it first), so calls that overlap on
+ * one GPU -- other contexts, streams or threads -- race and must be
+ * serialised by the caller.
+ * Errors: ESTATE (no paths), EINVAL (k < 1 or k > 1024, nq < 0, NULL
+ * buffers, more than 8,388,600 vertices), EDEVICE. */
+int panther_topk_similar_noalloc(panther_ctx *ctx, const int32_t *queries, int64_t nq,
+                                 int32_t k, int32_t *out_ids, uint32_t *out_counts,
+                                 int32_t *out_len, void *stream);
+
 /* All-vertex top-k (Sec. 4, Table 2's workload): the Panther top-k of
  * every vertex v in [0, n), as if panther_topk_similar were called with
  * queries 0..n-1 in the batched form.  Layout: out_ids int32[n][k],

@@ -99,12 +99,16 @@ struct TopkScratch {
   int32_t* touched;    // [n]
   uint32_t* ctl;       // [4]: touched count, ticket, spare
 };
-void launch_topk_plain(int stride, int32_t q, const uint64_t* inv_ptr, const uint32_t* inv_pid,
-                       const int32_t* paths, uint64_t list_len, TopkScratch sc, int32_t k,
-                       int32_t* out_ids, uint32_t* out_counts, int32_t* out_len,
-                       hipStream_t s);
+// qp: the query id in device memory (an id outside [0, n) yields a padded
+// row with out_len -1); list_len sizes the grid (any value is correct).
+void launch_topk_plain(int stride, const int32_t* qp, int32_t n, const uint64_t* inv_ptr,
+                       const uint32_t* inv_pid, const int32_t* paths, uint64_t list_len,
+                       TopkScratch sc, int32_t k, int32_t* out_ids, uint32_t* out_counts,
+                       int32_t* out_len, hipStream_t s);
 
 void launch_iota(int32_t* out, int32_t n, hipStream_t s);
+// p[0, n) = 0 with a kernel (capturable, unlike a memset node)
+void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s);
 void launch_query_lengths(const uint64_t* inv_ptr, const int32_t* queries, int64_t nq,
                           uint64_t* out, hipStream_t s);
 

@@ -234,6 +234,13 @@ extern "C" int panther_create(int device_ordinal, panther_ctx** out) {
     delete c;
     return PANTHER_EDEVICE;
   }
+  // the cross-stream ordering event exists from the start, so that no query
+  // call (the allocation-free one included) creates driver objects
+  if (hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return PANTHER_EDEVICE;
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device_ordinal) == hipSuccess) {
     c->num_cus = prop.multiProcessorCount;
@@ -826,8 +833,8 @@ extern "C" int panther_topk_similar(panther_ctx* c, const int32_t* queries, int6
   if (c->topk_form == PANTHER_FORM_PLAIN) {
     TopkScratch sc{c->d_cnt, c->d_touched, c->d_ctl};
     for (int64_t i = 0; i < nq; ++i) {
-      launch_topk_plain(c->stride, hq[i], c->d_inv_ptr, c->d_inv_pid, c->d_paths, qlen[i], sc, k,
-                        d_ids + i * k, d_cnt + i * k, d_len + i, s);
+      launch_topk_plain(c->stride, dq + i, c->n, c->d_inv_ptr, c->d_inv_pid, c->d_paths, qlen[i],
+                        sc, k, d_ids + i * k, d_cnt + i * k, d_len + i, s);
     }
     HIPTRY(hipGetLastError(), "topk plain");
   } else {

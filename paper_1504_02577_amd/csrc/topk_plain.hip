@@ -24,15 +24,29 @@ __device__ __forceinline__ int32_t ld_agent(const int32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The query id is read from device memory (*qp).  An id outside [0, n)
+// writes a padded row with out_len = -1 and touches no counter.
 template <int S>
 __global__ void __launch_bounds__(kBlock)
-k_topk_plain(int32_t q, const uint64_t* __restrict__ inv_ptr, const uint32_t* __restrict__ inv_pid,
-             const int32_t* __restrict__ paths, uint32_t* cnt, int32_t* touched, uint32_t* ctl,
-             int32_t k, int32_t* __restrict__ out_ids, uint32_t* __restrict__ out_counts,
+k_topk_plain(const int32_t* __restrict__ qp, int32_t n, const uint64_t* __restrict__ inv_ptr,
+             const uint32_t* __restrict__ inv_pid, const int32_t* __restrict__ paths,
+             uint32_t* cnt, int32_t* touched, uint32_t* ctl, int32_t k,
+             int32_t* __restrict__ out_ids, uint32_t* __restrict__ out_counts,
              int32_t* __restrict__ out_len) {
   __shared__ SelectSmem sm;
   __shared__ uint32_t s_last;
   const int lane = threadIdx.x & (kWave - 1);
+  const int32_t q = *qp;
+  if (q < 0 || q >= n) {
+    if (blockIdx.x == 0) {
+      for (int j = threadIdx.x; j < k; j += kBlock) {
+        out_ids[j] = -1;
+        out_counts[j] = 0u;
+      }
+      if (threadIdx.x == 0) *out_len = -1;
+    }
+    return;
+  }
   const uint64_t a = inv_ptr[q];
   const uint64_t L = inv_ptr[q + 1] - a;
   for (uint64_t base = (uint64_t)blockIdx.x * kBlock; base < L;
@@ -109,6 +123,20 @@ void launch_iota(int32_t* out, int32_t n, hipStream_t s) {
   k_iota_ids<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(out, n);
 }
 
+namespace {
+__global__ void k_zero_u32(uint32_t* p, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * 256;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+}  // namespace
+
+void launch_zero_u32(uint32_t* p, uint64_t n, hipStream_t s) {
+  uint64_t g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  k_zero_u32<<<(unsigned)g, 256, 0, s>>>(p, n);
+}
+
 void launch_query_lengths(const uint64_t* inv_ptr, const int32_t* queries, int64_t nq,
                           uint64_t* out, hipStream_t s) {
   if (nq > 0)
@@ -116,17 +144,17 @@ void launch_query_lengths(const uint64_t* inv_ptr, const int32_t* queries, int64
                                                                             out);
 }
 
-void launch_topk_plain(int stride, int32_t q, const uint64_t* inv_ptr, const uint32_t* inv_pid,
-                       const int32_t* paths, uint64_t list_len, TopkScratch sc, int32_t k,
-                       int32_t* out_ids, uint32_t* out_counts, int32_t* out_len,
-                       hipStream_t s) {
+void launch_topk_plain(int stride, const int32_t* qp, int32_t n, const uint64_t* inv_ptr,
+                       const uint32_t* inv_pid, const int32_t* paths, uint64_t list_len,
+                       TopkScratch sc, int32_t k, int32_t* out_ids, uint32_t* out_counts,
+                       int32_t* out_len, hipStream_t s) {
   uint64_t g = (list_len + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
   if (g > 1024) g = 1024;
   const unsigned grid = (unsigned)g;
-#define PANTHER_LAUNCH(SS)                                                                      \
-  k_topk_plain<SS><<<grid, kBlock, 0, s>>>(q, inv_ptr, inv_pid, paths, sc.cnt, sc.touched,     \
-                                           sc.ctl, k, out_ids, out_counts, out_len)
+#define PANTHER_LAUNCH(SS)                                                                    \
+  k_topk_plain<SS><<<grid, kBlock, 0, s>>>(qp, n, inv_ptr, inv_pid, paths, sc.cnt,            \
+                                           sc.touched, sc.ctl, k, out_ids, out_counts, out_len)
   switch (stride) {
     case 4: PANTHER_LAUNCH(4); break;
     case 8: PANTHER_LAUNCH(8); break;

@@ -36,7 +36,8 @@ PANTHER_PP_BF16 = 1
 
 EXPORTS = [
     "panther_create", "panther_destroy", "panther_last_error", "panther_load_graph",
-    "panther_sample_paths", "panther_topk_similar", "panther_topk_all", "panther_pp_topk",
+    "panther_sample_paths", "panther_topk_similar", "panther_topk_similar_noalloc",
+    "panther_topk_all", "panther_pp_topk",
     "panther_pp_topk_cross", "panther_pp_certified", "panther_pp_scanned",
     "panther_sample_size", "panther_set_option", "panther_get_paths", "panther_index_nnz",
     "panther_get_index", "panther_get_features", "panther_pp_stats", "panther_synchronize",
@@ -88,6 +89,7 @@ def lib():
         "panther_load_graph": (ctypes.c_int, [P, i32, i64, P, P, P, ctypes.c_int, u32]),
         "panther_sample_paths": (ctypes.c_int, [P, i32, i64, u64]),
         "panther_topk_similar": (ctypes.c_int, [P, P, i64, i32, P, P, P, ctypes.c_int, P]),
+        "panther_topk_similar_noalloc": (ctypes.c_int, [P, P, i64, i32, P, P, P, P]),
         "panther_pp_topk": (ctypes.c_int, [P, P, i64, i32, i32, P, P, ctypes.c_int, P]),
         "panther_topk_all": (ctypes.c_int, [P, i32, P, P, P, ctypes.c_int, P]),
         "panther_pp_topk_cross": (ctypes.c_int, [P, P, P, i64, i32, i32, P, P, ctypes.c_int, P]),
@@ -148,6 +150,12 @@ def panther_sample_paths(ctx, T, R, seed):
 def panther_topk_similar(ctx, queries, nq, k, out_ids, out_counts, out_len, mem, stream=None):
     return lib().panther_topk_similar(ctx, queries, nq, k, out_ids, out_counts, out_len, mem,
                                       stream)
+
+
+def panther_topk_similar_noalloc(ctx, queries, nq, k, out_ids, out_counts, out_len,
+                                 stream=None):
+    return lib().panther_topk_similar_noalloc(ctx, queries, nq, k, out_ids, out_counts, out_len,
+                                              stream)
 
 
 def panther_pp_topk_cross(qctx, dbctx, queries, nq, D, k, out_ids, out_dist, mem, stream=None):
