@@ -37,6 +37,16 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kTileItems = 4096;
 constexpr int kChunks = kTileItems / kWave;
 
+// Work-group i of a grid of g runs on XCD i % 8 (round-robin dispatch).
+// Tile order for the down-sweeps: each XCD takes a contiguous range of
+// tiles, so the runs that neighbouring tiles write for one digit (adjacent
+// in the output) meet in the same L2 and leave it as whole lines.
+__device__ __forceinline__ uint64_t xcd_tile(uint32_t i, uint32_t g) {
+  const uint32_t x = i % 8u, j = i / 8u;
+  const uint32_t per = g / 8u, rem = g % 8u;
+  return (uint64_t)x * per + (x < rem ? x : rem) + j;
+}
+
 __device__ __forceinline__ uint32_t digit_of(uint32_t key, int shift, int bits) {
   return (key >> shift) & ((1u << bits) - 1u);
 }
@@ -181,7 +191,8 @@ k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int s
   // the compacted (vertex, path id) pairs are staged in path-id order in
   // the tile region, then moved to registers
   __shared__ RankSmem sm;
-  const uint64_t p0 = (uint64_t)blockIdx.x * ppt;
+  const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint64_t p0 = tile * ppt;
   // thread t takes rows [t * rpt, t * rpt + rpt) of the tile, all loaded
   // before any is used; one block scan orders the pairs by path id
   constexpr int RMAX = S <= 32 ? 32 / S : 1;
@@ -229,7 +240,7 @@ k_radix_down_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int s
     vv[j] = i < n ? sm.u.tile.val[i] : 0u;
   }
   __syncthreads();
-  rank_scatter_regs(k, vv, n, shift, bits, sm, offsets, ntiles, blockIdx.x, key_out, val_out);
+  rank_scatter_regs(k, vv, n, shift, bits, sm, offsets, ntiles, tile, key_out, val_out);
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -262,7 +273,8 @@ k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict
                    uint32_t* __restrict__ val_out) {
   __shared__ RankSmem sm;
   const uint64_t nnz = *nnz_dev;
-  const uint64_t a = (uint64_t)blockIdx.x * kTileItems;
+  const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint64_t a = tile * kTileItems;
   if (a >= nnz) return;  // a tile past the pairs: nothing to move
   const int n = (int)((nnz - a) < (uint64_t)kTileItems ? (nnz - a) : (uint64_t)kTileItems);
   uint32_t k[16], v[16];
@@ -272,7 +284,7 @@ k_radix_down_pairs(const uint32_t* __restrict__ keys, const uint32_t* __restrict
     k[j] = i < n ? keys[a + i] : 0u;
     v[j] = i < n ? vals[a + i] : 0u;
   }
-  rank_scatter_regs(k, v, n, shift, bits, sm, offsets, ntiles, blockIdx.x, key_out, val_out);
+  rank_scatter_regs(k, v, n, shift, bits, sm, offsets, ntiles, tile, key_out, val_out);
 }
 
 __global__ void k_copy_u64(const uint64_t* __restrict__ src, uint64_t* __restrict__ dst) {
