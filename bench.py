@@ -222,6 +222,14 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    tune_file = os.environ.get("PANTHER_TUNE_CACHE") or os.path.join(
+        os.environ.get("HOME", "/tmp"), ".cache", "panther_tune.txt")
+    if os.path.exists(tune_file):
+        with open(tune_file) as f:
+            tuned = [ln.split() for ln in f if ln.startswith(f"gfx950:n{g.n}:T{T}:R{R}:")]
+        if tuned:
+            log("batched configuration (block, wgs/CU, tier B divisor, bucket bias): "
+                + " ".join(tuned[-1][1:]))
     stage = {"walk": [], "index": [], "topk": []}
     t_start = time.perf_counter()
     for _ in range(args.steps):

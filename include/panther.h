@@ -159,7 +159,14 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * LDS-derived default; longer lists go to the split hub pipeline),
  * "batch.hub_bits" (largest log2 bucket count per hub query, 0..12, -1 =
  * 12; smaller values make buckets overflow their LDS table and take the
- * sub-range path, for tests), "test.hub_budget" (bytes of hub staging per
+ * sub-range path, for tests), "batch.tier_b_div" (0 = autotuned, 1, 2: the
+ * work-group tier keeps lists up to its LDS bound divided by this; longer
+ * ones go to the hub pipeline), "batch.bucket_bias" (-1 = autotuned, 0, 1:
+ * a hub query gets 2^bias times the buckets its length asks for).  The
+ * autotuner picks every unforced batch.* choice above per shape class and
+ * keeps it in the text file $PANTHER_TUNE_CACHE (default
+ * $HOME/.cache/panther_tune.txt); forcing any of them turns it off.
+ * "test.hub_budget" (bytes of hub staging per
  * chunk of the batched form, 0 = automatic: min(8 GiB, free / 4), at least
  * 256 MiB; a small value splits the hub queries into many chunks, for
  * tests), "test.pp_recompute_all" (0..2, default 0;

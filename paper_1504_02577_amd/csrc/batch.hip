@@ -270,7 +270,15 @@ KernelFn pick_kernel(int stride) {
 struct BatchConfig {
   int block = 512;      // threads per work-group
   int wgs_per_cu = 1;   // persistent work-groups per CU
+  int tier_b_div = 1;   // tier B keeps lists up to (LDS table bound) / tier_b_div
+  int bucket_bias = 0;  // a hub query gets 2^bias times the buckets its length asks for
 };
+
+// Every value the tuner may pick; results are identical for all of them.
+constexpr int kBlocks[] = {512, 256};
+constexpr int kWgs[] = {1, 2};
+constexpr int kTierBDivs[] = {1, 2};
+constexpr int kBucketBiases[] = {0, 1};
 
 // What one call enqueues: the hub pipeline chunk by chunk, then the
 // persistent kernel over tiers A and B.
@@ -340,6 +348,8 @@ struct BatchState {
   BatchConfig cfg;
   int forced_block = 0;
   int forced_wgs = 0;
+  int forced_div = 0;    // 0: chosen by the tuner
+  int forced_bias = -1;  // -1: chosen by the tuner
   int64_t tier_a_override = -1;
   int64_t tier_b_override = -1;
   int hub_bits_max = 12;
@@ -370,6 +380,8 @@ void copy_batch_options(panther_ctx* c, Lane* dst) {
   BatchState* b = state(dst);
   b->forced_block = a->forced_block;
   b->forced_wgs = a->forced_wgs;
+  b->forced_div = a->forced_div;
+  b->forced_bias = a->forced_bias;
   b->tier_a_override = a->tier_a_override;
   b->tier_b_override = a->tier_b_override;
   b->hub_bits_max = a->hub_bits_max;
@@ -428,6 +440,12 @@ int set_batch_option(panther_ctx* c, const std::string& key, int64_t value) {
   } else if (key == "batch.wgs_per_cu") {
     if (value < 0 || value > 2) return ctx_fail(c, PANTHER_EINVAL, "batch.wgs_per_cu in 0..2");
     b->forced_wgs = (int)value;
+  } else if (key == "batch.tier_b_div") {
+    if (value < 0 || value > 2) return ctx_fail(c, PANTHER_EINVAL, "batch.tier_b_div in 0..2");
+    b->forced_div = (int)value;
+  } else if (key == "batch.bucket_bias") {
+    if (value < -1 || value > 1) return ctx_fail(c, PANTHER_EINVAL, "batch.bucket_bias in -1..1");
+    b->forced_bias = (int)value;
   }
   b->tuned = false;
   return PANTHER_OK;
@@ -457,6 +475,23 @@ Layout layout_for(const panther_ctx* c, const BatchConfig& cfg) {
   return Layout{fixed + region, TA, TB};
 }
 
+// The configurations a lane may run: every tuner choice, with the forced
+// options fixed.
+std::vector<BatchConfig> config_space(const BatchState* b) {
+  std::vector<BatchConfig> v;
+  for (int blk : kBlocks)
+    for (int wgs : kWgs)
+      for (int div : kTierBDivs)
+        for (int bias : kBucketBiases) {
+          if ((b->forced_block && blk != b->forced_block) ||
+              (b->forced_wgs && wgs != b->forced_wgs) || (b->forced_div && div != b->forced_div) ||
+              (b->forced_bias >= 0 && bias != b->forced_bias))
+            continue;
+          v.push_back(BatchConfig{blk, wgs, div, bias});
+        }
+  return v;
+}
+
 std::string tune_cache_path() {
   const char* p = getenv("PANTHER_TUNE_CACHE");
   if (p && *p) return p;
@@ -464,10 +499,12 @@ std::string tune_cache_path() {
   return std::string(h ? h : "/tmp") + "/.cache/panther_tune.txt";
 }
 
-// The cache is a text file of "key block wgs_per_cu" lines (last match
-// wins).  Readers take a shared and writers an exclusive flock(2) on it, so
-// lanes and processes that tune at once never interleave a line.  Every
-// failure (no home, read-only disk) leaves tuning to run again next time.
+// The cache is a text file of "key block wgs_per_cu tier_b_div
+// bucket_bias" lines (last match wins; the last two fields may be missing,
+// and a line with a value outside the tuner's choices is ignored).
+// Readers take a shared and writers an exclusive flock(2) on it, so lanes
+// and processes that tune at once never interleave a line.  Every failure
+// (no home, read-only disk) leaves tuning to run again next time.
 bool tune_lookup(const std::string& key, BatchConfig* cfg) {
   const int fd = open(tune_cache_path().c_str(), O_RDONLY | O_CLOEXEC);
   if (fd < 0) return false;
@@ -482,12 +519,19 @@ bool tune_lookup(const std::string& key, BatchConfig* cfg) {
     while (std::getline(lines, line)) {
       std::istringstream is(line);
       std::string k;
-      int blk, wgs;
-      if (is >> k >> blk >> wgs && k == key) {
-        cfg->block = blk;
-        cfg->wgs_per_cu = wgs;
-        found = true;
+      int blk, wgs, div = 1, bias = 0;
+      if (!(is >> k >> blk >> wgs) || k != key) continue;
+      if (is >> div) {
+        if (!(is >> bias)) continue;
       }
+      auto one_of = [](int v, const int* xs, size_t nx) {
+        return std::find(xs, xs + nx, v) != xs + nx;
+      };
+      if (!one_of(blk, kBlocks, 2) || !one_of(wgs, kWgs, 2) || !one_of(div, kTierBDivs, 2) ||
+          !one_of(bias, kBucketBiases, 2))
+        continue;
+      *cfg = BatchConfig{blk, wgs, div, bias};
+      found = true;
     }
     (void)flock(fd, LOCK_UN);
   }
@@ -504,8 +548,8 @@ void tune_store(const std::string& key, const BatchConfig& cfg) {
   if (fd < 0) return;
   if (flock(fd, LOCK_EX) == 0) {
     char line[512];
-    const int len = snprintf(line, sizeof line, "%s %d %d\n", key.c_str(), cfg.block,
-                             cfg.wgs_per_cu);
+    const int len = snprintf(line, sizeof line, "%s %d %d %d %d\n", key.c_str(), cfg.block,
+                             cfg.wgs_per_cu, cfg.tier_b_div, cfg.bucket_bias);
     if (len > 0 && len < (int)sizeof line) (void)!write(fd, line, (size_t)len);
     (void)flock(fd, LOCK_UN);
   }
@@ -626,7 +670,7 @@ static int launch_batched(panther_ctx* c, BatchState* b, const BatchConfig& cfg,
 // memory budget, and fills the device buffers and per-chunk arguments.
 static int plan_hubs(panther_ctx* c, BatchState* b,
                      const std::vector<std::pair<uint64_t, int32_t>>& C,
-                     const int32_t* dq, int32_t k, int32_t* d_ids, uint32_t* d_counts,
+                     const int32_t* dq, int32_t k, int bias, int32_t* d_ids, uint32_t* d_counts,
                      int32_t* d_len, float* theta, hipStream_t s, std::vector<HubArgs>* out) {
   out->clear();
   b->h_hq.clear();
@@ -666,7 +710,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
   for (const auto& x : C) {
     const uint64_t L = x.first;
     const uint64_t occ = T * L;
-    const int bb = std::min(hub_bucket_bits(occ), b->hub_bits_max);
+    const int bb = std::min(hub_bucket_bits(occ << bias), b->hub_bits_max);
     const uint32_t tiles = hub_tiles(L);
     const uint32_t stiles = hub_stiles(L);
     const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(k, kEmitCap) << bb, occ);
@@ -771,7 +815,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   const Layout lay = layout_for(c, cfg);
   const uint64_t T = (uint64_t)c->T;
   uint64_t LA = (uint64_t)lay.TA / (2 * T);
-  uint64_t LB = (uint64_t)lay.TB / (2 * T);
+  uint64_t LB = (uint64_t)lay.TB / (2 * T) / (uint64_t)cfg.tier_b_div;
   if (b->tier_a_override >= 0) LA = std::min(LA, (uint64_t)b->tier_a_override);
   if (b->tier_b_override >= 0) LB = std::min(LB, (uint64_t)b->tier_b_override);
   // the wave-tier sort buffer holds TA/2 keys and the block selection keeps
@@ -865,7 +909,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
             [](const std::pair<uint64_t, int32_t>& x, const std::pair<uint64_t, int32_t>& y) {
               return x.first != y.first ? x.first > y.first : x.second < y.second;
             });
-  st = plan_hubs(c, b, C, dq, k, d_ids, d_counts, d_len, theta, s, &out->hub);
+  st = plan_hubs(c, b, C, dq, k, cfg.bucket_bias, d_ids, d_counts, d_len, theta, s, &out->hub);
   if (st) return st;
   host_items->clear();
   if ((st = grow(c, b->d_items, b->items_cap, std::max<size_t>(need, 1024), sizeof(int32_t),
@@ -922,10 +966,17 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
 // bucket counters and maps, winners and tile maps.
 BatchSizing batched_sizing(panther_ctx* c, Lane* lane) {
   BatchState* b = state(lane);
-  const Layout lay = layout_for(c, b->tuned ? b->cfg : BatchConfig{});
   BatchSizing z{};
   z.T = (uint64_t)c->T;
-  z.LB = (uint64_t)lay.TB / (2 * z.T);
+  z.LB = ~0ull;
+  z.bucket_bias = 0;
+  // before its first call a lane may still pick any configuration
+  const std::vector<BatchConfig> cs = b->tuned ? std::vector<BatchConfig>{b->cfg} : config_space(b);
+  for (const BatchConfig& cf : cs) {
+    const Layout lay = layout_for(c, cf);
+    z.LB = std::min<uint64_t>(z.LB, (uint64_t)lay.TB / (2 * z.T) / (uint64_t)cf.tier_b_div);
+    z.bucket_bias = std::max(z.bucket_bias, cf.bucket_bias);
+  }
   if (b->tier_b_override >= 0) z.LB = std::min(z.LB, (uint64_t)b->tier_b_override);
   z.hub_bits_max = b->hub_bits_max;
   return z;
@@ -936,7 +987,7 @@ size_t batched_query_bytes(const BatchSizing& z, uint64_t L, int32_t kmax) {
   size_t bytes = sizeof(int32_t) + sizeof(uint64_t);
   if (L <= z.LB) return bytes;
   const uint64_t occ = T * L;
-  const int bb = std::min(hub_bucket_bits(occ), z.hub_bits_max);
+  const int bb = std::min(hub_bucket_bits(occ << z.bucket_bias), z.hub_bits_max);
   const uint64_t nb = (uint64_t)1 << bb;
   const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(kmax, kEmitCap) << bb, occ);
   bytes += 2 * sizeof(int32_t) * occ;                                       // staging
@@ -975,16 +1026,16 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
   std::vector<int32_t> items;
   Plan args;
   // configuration: forced, cached, autotuned, or the default
-  std::vector<BatchConfig> cands;
-  for (int blk : {512, 256})
-    for (int wgs : {1, 2}) cands.push_back(BatchConfig{blk, wgs});
-  if (b->forced_block || b->forced_wgs) {
+  if (b->forced_block || b->forced_wgs || b->forced_div || b->forced_bias >= 0) {
     BatchConfig f;
     if (b->forced_block) f.block = b->forced_block;
     if (b->forced_wgs) f.wgs_per_cu = b->forced_wgs;
+    if (b->forced_div) f.tier_b_div = b->forced_div;
+    if (b->forced_bias >= 0) f.bucket_bias = b->forced_bias;
     b->cfg = f;
     b->tuned = true;
   }
+  const bool forced = b->forced_block || b->forced_wgs || b->forced_div || b->forced_bias >= 0;
   // the tuned choice is kept per shape class: graph and path count, and the
   // batch size and k rounded to powers of two
   int nq_bucket = 0;
@@ -994,7 +1045,7 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
   char key[256];
   snprintf(key, sizeof key, "gfx950:n%d:T%d:R%lld:nq2^%d:k%d:cu%d:f%d", c->n, c->T,
            (long long)c->R, nq_bucket, k_bucket, c->num_cus, theta ? 1 : 0);
-  if (b->tuned && !(b->forced_block || b->forced_wgs) && b->tune_key != key) b->tuned = false;
+  if (b->tuned && !forced && b->tune_key != key) b->tuned = false;
   if (!b->tuned) {
     b->tune_key = key;
     BatchConfig cached;
@@ -1002,32 +1053,70 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
       b->cfg = cached;
       b->tuned = true;
     } else if (c->autotune && !b->no_tune && nq >= 256) {
-      // time every candidate on (a prefix of) this batch -- results are
-      // identical by construction, only speed differs -- and keep the fastest
-      const int64_t m = std::min<int64_t>(nq, 16384);
+      // Results are identical for every configuration by construction; only
+      // speed differs.  Stage 1 times the persistent kernel alone on (a
+      // prefix of) this batch for each (block, work-groups per CU); stage 2,
+      // when the batch has lists near or above the tier B bound, times the
+      // whole call for each (tier B divisor, bucket bias).  Each candidate
+      // runs once to warm up and is then timed twice (the faster counts).
       hipEvent_t e0, e1;
       int st = ctx_hip(c, hipEventCreate(&e0), "autotune");
       if (st) return st;
       st = ctx_hip(c, hipEventCreate(&e1), "autotune");
-      if (st) return st;
+      if (st) {
+        (void)hipEventDestroy(e0);
+        return st;
+      }
+      auto time_cfg = [&](const BatchConfig& cfg, int64_t m, bool hubs, float* ms_out) -> int {
+        int r = plan(c, b, cfg, dq, qlen, m, k, d_ids, d_counts, d_len, theta, s, hubs, &args,
+                     &items);
+        if (r) return r;
+        float best_ms = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+          (void)hipEventRecord(e0, s);
+          if ((r = launch_batched(c, b, cfg, args, s, false))) return r;
+          (void)hipEventRecord(e1, s);
+          if ((r = ctx_hip(c, hipEventSynchronize(e1), "autotune"))) return r;
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) best_ms = std::min(best_ms, ms);
+        }
+        *ms_out = best_ms;
+        return PANTHER_OK;
+      };
+      BatchConfig best_cfg{};
       float best = 1e30f;
-      BatchConfig best_cfg = cands[0];
-      for (const BatchConfig& cfg : cands) {
-        st = plan(c, b, cfg, dq, qlen, m, k, d_ids, d_counts, d_len, theta, s, false, &args,
-                  &items);
-        if (st) break;
-        st = launch_batched(c, b, cfg, args, s, false);  // warm
-        if (st) break;
-        (void)hipEventRecord(e0, s);
-        st = launch_batched(c, b, cfg, args, s, false);
-        if (st) break;
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best) {
-          best = ms;
-          best_cfg = cfg;
+      const int64_t m = std::min<int64_t>(nq, 16384);
+      for (int blk : kBlocks)
+        for (int wgs : kWgs) {
+          const BatchConfig cfg{blk, wgs, 1, 0};
+          float ms = 0.f;
+          if (!st) st = time_cfg(cfg, m, false, &ms);
+          if (!st && ms < best) {
+            best = ms;
+            best_cfg = cfg;
+          }
+        }
+      if (!st) {
+        const Layout lay = layout_for(c, best_cfg);
+        uint64_t LB = (uint64_t)lay.TB / (2 * (uint64_t)c->T);
+        if (b->tier_b_override >= 0) LB = std::min(LB, (uint64_t)b->tier_b_override);
+        const uint64_t lo = LB / (uint64_t)kTierBDivs[1];
+        bool near_hubs = false;
+        for (int64_t i = 0; i < nq && !near_hubs; ++i) near_hubs = qlen[i] > lo;
+        if (near_hubs) {
+          best = 1e30f;
+          const BatchConfig base = best_cfg;
+          for (int div : kTierBDivs)
+            for (int bias : kBucketBiases) {
+              const BatchConfig cfg{base.block, base.wgs_per_cu, div, bias};
+              float ms = 0.f;
+              if (!st) st = time_cfg(cfg, nq, true, &ms);
+              if (!st && ms < best) {
+                best = ms;
+                best_cfg = cfg;
+              }
+            }
         }
       }
       (void)hipEventDestroy(e0);

@@ -161,6 +161,7 @@ struct BatchSizing {
   uint64_t T;
   uint64_t LB;       // longest list counted in one work-group's LDS table
   int hub_bits_max;  // largest log2 bucket count of a hub query
+  int bucket_bias;   // extra log2 buckets per hub query
 };
 BatchSizing batched_sizing(panther_ctx* c, Lane* lane);
 size_t batched_query_bytes(const BatchSizing& z, uint64_t L, int32_t kmax);

@@ -295,7 +295,8 @@ extern "C" int panther_set_option(panther_ctx* c, const char* key, int64_t value
   } else if (k == "test.fail_alloc_after") {
     c->fail_alloc_after = value < 0 ? -1 : value;
   } else if (k == "batch.tier_a" || k == "batch.tier_b" || k == "batch.block" ||
-             k == "batch.wgs_per_cu" || k == "batch.hub_bits" || k == "test.hub_budget") {
+             k == "batch.wgs_per_cu" || k == "batch.hub_bits" || k == "batch.tier_b_div" ||
+             k == "batch.bucket_bias" || k == "test.hub_budget") {
     return set_batch_option(c, k, value);
   } else {
     return ctx_fail(c, PANTHER_EINVAL, "unknown option '%s'", key);

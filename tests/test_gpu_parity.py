@@ -249,6 +249,64 @@ def test_batched_tiers_rmat14(P, oracle, inputs, rmat14, block, wgs, ta, tb, hb,
             P.set_option(key, v)
 
 
+@pytest.mark.parametrize("div,bias", [(2, 0), (1, 1), (2, 1)])
+def test_batched_tuner_choices_rmat14(P, oracle, inputs, rmat14, div, bias):
+    """Each (tier B divisor, bucket bias) the autotuner may pick gives the
+    same lists."""
+    g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
+    _say(f"case: batched tuner choice tier_b_div={div} bucket_bias={bias}")
+    P.load_graph(g)
+    P.sample_paths(T, R, seed)
+    P.set_option("topk.form", 1)
+    P.set_option("batch.tier_b_div", div)
+    P.set_option("batch.bucket_bias", bias)
+    try:
+        qs = np.concatenate([inputs.queries_by_degree(g, 1500, 13),
+                             np.arange(0, g.n, 89, dtype=np.int32)])
+        for k in (1, 50, 300):
+            want = oracle.topk(g.n, paths, inv_ptr, inv_pid, qs, k)
+            _check_topk(P.topk(qs, k), want, f"tuner choice {div}/{bias} k={k}")
+    finally:
+        P.set_option("batch.tier_b_div", 0)
+        P.set_option("batch.bucket_bias", -1)
+
+
+def test_autotune_cache_rmat14(P, oracle, inputs, rmat14, tmp_path, monkeypatch):
+    """The autotuner stores one line per shape class, a later call reuses it,
+    and malformed lines are skipped."""
+    g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
+    _say("case: autotune cache")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PANTHER_TUNE_CACHE", str(cache))
+    P.load_graph(g)
+    P.sample_paths(T, R, seed)
+    P.set_option("topk.form", 1)
+    P.set_option("autotune", 1)
+    P.set_option("batch.block", 0)  # drops the lane's tuned choice
+    qs = np.concatenate([inputs.queries_by_degree(g, 1500, 17),
+                         np.arange(0, g.n, 83, dtype=np.int32)])
+    want = oracle.topk(g.n, paths, inv_ptr, inv_pid, qs, 50)
+    _check_topk(P.topk(qs, 50), want, "autotuned")
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    f = lines[0].split()
+    assert len(f) == 5 and int(f[1]) in (256, 512) and int(f[2]) in (1, 2)
+    assert int(f[3]) in (1, 2) and int(f[4]) in (0, 1)
+    key = f[0]
+    # a stored line (here the short form of earlier caches) is reused: no
+    # new line is appended
+    text = f"{key} 512 9 1 0\n{key} 300 1\n{key} 256 2\n"
+    cache.write_text(text)
+    P.set_option("batch.block", 0)
+    _check_topk(P.topk(qs, 50), want, "cached")
+    assert cache.read_text() == text
+    # only malformed lines: the tuner runs again and appends its choice
+    cache.write_text(f"{key} 512 1 3 0\n{key} 512\n")
+    P.set_option("batch.block", 0)
+    _check_topk(P.topk(qs, 50), want, "retuned")
+    assert len(cache.read_text().splitlines()) == 3
+
+
 @pytest.mark.parametrize("k", [5, 50])
 def test_all_vertex_topk(P, oracle, rmat14, k):
     """panther_topk_all equals the oracle's top-k of every vertex (the
