@@ -223,17 +223,12 @@ __device__ __forceinline__ bool table_add(int32_t* keys, uint32_t* vals, int32_t
   uint32_t h = slot_of(v);
 #pragma unroll 1
   for (int p = 0; p < probes; ++p) {
-    const int32_t cur = *((volatile int32_t*)&keys[h]);
-    if (cur == v) {
+    // one LDS round trip per probe: the swap claims an empty slot, and a
+    // failed swap returns the slot's key
+    const int32_t prev = atomicCAS(&keys[h], -1, v);
+    if (prev == -1 || prev == v) {
       atomicAdd(&vals[h], 1u);
       return true;
-    }
-    if (cur == -1) {
-      const int32_t prev = atomicCAS(&keys[h], -1, v);
-      if (prev == -1 || prev == v) {
-        atomicAdd(&vals[h], 1u);
-        return true;
-      }
     }
     h = (h + 1) & (uint32_t)(kTable - 1);
   }
@@ -241,7 +236,7 @@ __device__ __forceinline__ bool table_add(int32_t* keys, uint32_t* vals, int32_t
 }
 
 // LDS of the count step's common path: the table and a count histogram.
-struct TableSmem {
+struct alignas(16) TableSmem {
   int32_t keys[kTable];
   uint32_t vals[kTable];
   uint32_t ch[256];
@@ -251,7 +246,7 @@ struct TableSmem {
 
 // LDS of the rare path (buckets the common path hands over): the table,
 // the exact block selection and the running best of the sub-ranges.
-struct CountSmem {
+struct alignas(16) CountSmem {
   int32_t keys[kTable];
   uint32_t vals[kTable];  // the two arrays are reused as kTable 64-bit keys
   SelectSmem sel;
@@ -267,9 +262,9 @@ struct CountSmem {
 __device__ bool count_part(const HubArgs& A, int32_t* keys, uint32_t* vals, uint32_t* ctl,
                            uint64_t s, uint64_t e, int bb, int sbits, uint32_t sub) {
   const int probes = bb + sbits >= 32 - kFitBits ? kTable : kProbes;
-  for (int j = threadIdx.x; j < kTable; j += kCountBlock) {
-    keys[j] = -1;
-    vals[j] = 0u;
+  for (int j = threadIdx.x; j < kTable / 4; j += kCountBlock) {
+    reinterpret_cast<int4*>(keys)[j] = make_int4(-1, -1, -1, -1);
+    reinterpret_cast<uint4*>(vals)[j] = make_uint4(0u, 0u, 0u, 0u);
   }
   if (threadIdx.x == 0) {
     ctl[0] = 0u;
@@ -341,11 +336,26 @@ __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t c
     sm.ctl[4] = 0u;  // emit cursor
   }
   __syncthreads();
+  // counts 1..3 (most entries) are summed per wave in three 10-bit fields
+  // (at most kTable / kCountBlock per lane, 512 per wave) and added once
+  // per wave; larger counts go straight to their bin
+  static_assert(kTable / kCountBlock * kWave < 1024, "10-bit fields");
+  uint32_t low = 0u;
   for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
     if (sm.keys[t] >= 0) {
       const uint32_t c = sm.vals[t];
-      atomicAdd(&sm.ch[c < kBins - 1 ? c : kBins - 1], 1u);
+      if (c - 1u < 3u)
+        low += 1u << (10u * (c - 1u));
+      else
+        atomicAdd(&sm.ch[c < kBins - 1 ? c : kBins - 1], 1u);
     }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) low += __shfl_xor(low, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0 && low) {
+    atomicAdd(&sm.ch[1], low & 1023u);
+    atomicAdd(&sm.ch[2], (low >> 10) & 1023u);
+    atomicAdd(&sm.ch[3], low >> 20);
   }
   __syncthreads();
   // descending bins, one per thread: the count above a bin by a block scan
@@ -366,12 +376,18 @@ __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t c
   if (threadIdx.x == 0) sm.ctl[5] = n_emit ? atomicAdd(&A.cand_n[j], n_emit) : 0u;
   __syncthreads();
   uint64_t* dst = A.cand + cand0 + sm.ctl[5];
+  const int lane = threadIdx.x & (kWave - 1);
+  static_assert(kTable % kCountBlock == 0, "uniform emit loop");
   for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
     const int32_t key = sm.keys[t];
-    if (key >= 0) {
-      const uint32_t c = sm.vals[t];
-      if ((c < kBins - 1 ? c : kBins - 1) >= thr) dst[atomicAdd(&sm.ctl[4], 1u)] = rank_key(c, key);
-    }
+    const uint32_t c = key >= 0 ? sm.vals[t] : 0u;
+    const bool em = key >= 0 && (c < kBins - 1 ? c : kBins - 1) >= thr;
+    const uint64_t mask = __ballot(em);
+    if (!mask) continue;
+    uint32_t base = 0u;
+    if (lane == 0) base = atomicAdd(&sm.ctl[4], (uint32_t)__popcll(mask));
+    base = __shfl(base, 0, kWave);
+    if (em) dst[base + __popcll(mask & ((1ull << lane) - 1ull))] = rank_key(c, key);
   }
   return true;
 }
