@@ -166,6 +166,11 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="paths in the oracle sample (0 = R/50)")
     args = ap.parse_args()
+    if args.workload == "serve":
+        # one hardware queue per stream (the context's, the batched form's
+        # second stream, three lanes, torch's): 4 per process would put two
+        # lanes on one queue and serialise them
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
     if args.gpus != 1:
         print("bench.py runs on one GPU only: multi-GPU sharding is designed, not built; "
               "use --gpus 1", file=sys.stderr)
@@ -615,6 +620,7 @@ def bench_serve(args):
     while got < n_req and time.perf_counter() - t0 < arrive[-1] + 60:
         got += len(srv.poll(10000))
     st = srv.stats()
+    mem = srv.memory()
     srv.stop()
     P.close()
     res = {"metric": "p99 ms", "value": st["p99_ms"], "unit": "ms", "n_gpus": 1,
@@ -626,7 +632,8 @@ def bench_serve(args):
                                   "80% Panther / 20% Panther++ (D=50), k in {10,50,200}, "
                                   "3 lanes, max batch 2048"},
            "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "sustained_qps": st["qps"],
-           "offered_qps": args.serve_rate, "completed": st["completed"], "submitted": n_req}
+           "offered_qps": args.serve_rate, "completed": st["completed"], "submitted": n_req,
+           "lane_share_bytes": mem["lane_share_bytes"], "peak_lane_bytes": mem["peak_lane_bytes"]}
     print(json.dumps(res), flush=True)
 
 

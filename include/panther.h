@@ -318,8 +318,12 @@ typedef struct panther_result {
  * buckets and winners), and the candidate pools of a Panther++ call of that
  * many queries -- the sizes the kernels allocate.  A lane whose kept scratch
  * plus the next batch's need would pass its share frees its scratch first,
- * so the lanes together hold at most mem_budget_bytes.  While the server
- * runs, the context must not be used by other calls.
+ * so the lanes together hold at most mem_budget_bytes.  Lanes overlap on
+ * the device only as far as the process has hardware queues: HIP gives a
+ * process GPU_MAX_HW_QUEUES of them (4 by default) and shares them among
+ * its streams, among which are the context's stream, the batched form's
+ * second stream and one per lane.  While the server runs, the context
+ * must not be used by other calls.
  * Errors: ESTATE (no paths), EINVAL, ENOMEM, EDEVICE. */
 int panther_server_start(panther_ctx *ctx, int64_t mem_budget_bytes,
                          int32_t max_batch, int32_t lanes, int32_t D,

@@ -279,6 +279,7 @@ constexpr int kBlocks[] = {512, 256};
 constexpr int kWgs[] = {1, 2};
 constexpr int kTierBDivs[] = {1, 2};
 constexpr int kBucketBiases[] = {0, 1};
+constexpr int64_t kStage2MaxQueries = (int64_t)1 << 18;  // batches the second stage tunes
 
 // What one call enqueues: the hub pipeline chunk by chunk, then the
 // persistent kernel over tiers A and B.
@@ -1085,8 +1086,9 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
       // Results are identical for every configuration by construction; only
       // speed differs.  Stage 1 times the persistent kernel alone on (a
       // prefix of) this batch for each (block, work-groups per CU); stage 2,
-      // when the batch has lists near or above the tier B bound, times the
-      // whole call for each (tier B divisor, bucket bias).  Each candidate
+      // when the batch has lists near or above the tier B bound and at most
+      // kStage2MaxQueries queries, times the whole call for each (tier B
+      // divisor, bucket bias).  Each candidate
       // runs once to warm up and is then timed twice (the faster counts).
       hipEvent_t e0, e1;
       int st = ctx_hip(c, hipEventCreate(&e0), "autotune");
@@ -1131,9 +1133,12 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
         uint64_t LB = (uint64_t)lay.TB / (2 * (uint64_t)c->T);
         if (b->tier_b_override >= 0) LB = std::min(LB, (uint64_t)b->tier_b_override);
         const uint64_t lo = LB / (uint64_t)kTierBDivs[1];
+        // (stage 2 replays the whole call twelve times: not for batches so
+        // large, such as a feature pass over every vertex, that one call
+        // already takes long)
         bool near_hubs = false;
         for (int64_t i = 0; i < nq && !near_hubs; ++i) near_hubs = qlen[i] > lo;
-        if (near_hubs) {
+        if (near_hubs && nq <= kStage2MaxQueries) {
           best = 1e30f;
           const BatchConfig base = best_cfg;
           for (int div : kTierBDivs)
