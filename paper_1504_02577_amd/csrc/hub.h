@@ -9,7 +9,7 @@
 namespace panther {
 
 // Occurrences a bucket is sized for (the LDS table holds twice as many).
-constexpr int kBucketTarget = 2048;
+constexpr int kBucketTarget = 4096;
 // A bucket emits at most max(k, kEmitCap) candidates to the merge.
 constexpr int kEmitCap = 256;
 

@@ -42,9 +42,9 @@ constexpr int kGatherRows = 4;                        // rows per thread
 constexpr int kTileRows = kGatherBlock * kGatherRows;  // rows per gather tile
 constexpr int kSTileRows = 4096;                      // rows per bucketing tile
 constexpr int kMaxBucketBits = 12;
-constexpr int kCountBlock = 512;
+constexpr int kCountBlock = 1024;
 constexpr int kTable = 2 * kBucketTarget;  // LDS hash entries of the count step
-constexpr int kTableBits = 12;
+constexpr int kTableBits = 13;
 constexpr int kProbes = 32;                // bounded probe sequence
 constexpr int kFitBits = kTableBits - 1;   // log2(kTable / 2)
 constexpr uint32_t kRareGrid = 256;        // work-groups of the rare count path
@@ -392,9 +392,13 @@ __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t c
   return true;
 }
 
-// Common path: one work-group per bucket, a small LDS footprint so that
-// several work-groups share a CU.  A bucket whose table overflows, or whose
-// candidate superset exceeds the emit cap, is handed to k_hub_count_rare.
+// Common path: one work-group of 1,024 threads per bucket; its table
+// (64 KB) lets two work-groups share a CU at eight waves per SIMD.  A
+// work-group's life is mostly a few dependent memory round trips (bucket
+// bounds, its slots, the winners' cursor), so buckets are made as large as
+// that occupancy allows: halving them measured slower.  A bucket whose
+// table overflows, or whose candidate superset exceeds the emit cap, is
+// handed to k_hub_count_rare.
 __global__ void __launch_bounds__(kCountBlock) k_hub_count(HubArgs A) {
   __shared__ TableSmem sm;
   const uint32_t g = blockIdx.x;
