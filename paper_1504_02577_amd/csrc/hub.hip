@@ -329,21 +329,38 @@ __device__ int select_exact(const HubArgs& A, CountSmem& sm) {
 // max(k, kEmitCap) entries.
 __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t cand0) {
   constexpr int kBins = 256;  // counts clamped to 255
+  constexpr int kPer = kTable / kCountBlock;  // table slots per thread
+  static_assert(kPer == 8, "two 16-byte loads per array");
   for (int b = threadIdx.x; b < kBins; b += kCountBlock) sm.ch[b] = 0u;
   if (threadIdx.x == 0) {
     sm.ctl[2] = 1u;  // threshold count (when there are fewer than k entries)
     sm.ctl[3] = 0u;  // entries at or above it
     sm.ctl[4] = 0u;  // emit cursor
   }
+  // each thread keeps its eight consecutive slots in registers for both
+  // passes over the table
+  int32_t kk[kPer];
+  uint32_t cc[kPer];
+  {
+    const int4* k4 = reinterpret_cast<const int4*>(sm.keys) + 2 * threadIdx.x;
+    const uint4* c4 = reinterpret_cast<const uint4*>(sm.vals) + 2 * threadIdx.x;
+    const int4 a0 = k4[0], a1 = k4[1];
+    const uint4 b0 = c4[0], b1 = c4[1];
+    kk[0] = a0.x; kk[1] = a0.y; kk[2] = a0.z; kk[3] = a0.w;
+    kk[4] = a1.x; kk[5] = a1.y; kk[6] = a1.z; kk[7] = a1.w;
+    cc[0] = b0.x; cc[1] = b0.y; cc[2] = b0.z; cc[3] = b0.w;
+    cc[4] = b1.x; cc[5] = b1.y; cc[6] = b1.z; cc[7] = b1.w;
+  }
   __syncthreads();
   // counts 1..3 (most entries) are summed per wave in three 10-bit fields
-  // (at most kTable / kCountBlock per lane, 512 per wave) and added once
-  // per wave; larger counts go straight to their bin
-  static_assert(kTable / kCountBlock * kWave < 1024, "10-bit fields");
+  // (at most kPer per lane, 512 per wave) and added once per wave; larger
+  // counts go straight to their bin
+  static_assert(kPer * kWave < 1024, "10-bit fields");
   uint32_t low = 0u;
-  for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
-    if (sm.keys[t] >= 0) {
-      const uint32_t c = sm.vals[t];
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    if (kk[i] >= 0) {
+      const uint32_t c = cc[i];
       if (c - 1u < 3u)
         low += 1u << (10u * (c - 1u));
       else
@@ -374,20 +391,25 @@ __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t c
   const uint32_t cap = (uint32_t)(A.k > kEmitCap ? A.k : kEmitCap);
   if (n_emit > cap) return false;  // uniform: every thread read the same words
   if (threadIdx.x == 0) sm.ctl[5] = n_emit ? atomicAdd(&A.cand_n[j], n_emit) : 0u;
+  // a wave's emitted entries: ballots first, then one cursor add per wave
+  const int lane = threadIdx.x & (kWave - 1);
+  uint64_t mask[kPer];
+  uint32_t wtot = 0u;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    mask[i] = __ballot(kk[i] >= 0 && (cc[i] < kBins - 1 ? cc[i] : kBins - 1) >= thr);
+    wtot += (uint32_t)__popcll(mask[i]);
+  }
+  uint32_t base = 0u;
+  if (lane == 0 && wtot) base = atomicAdd(&sm.ctl[4], wtot);
+  base = __shfl(base, 0, kWave);
   __syncthreads();
   uint64_t* dst = A.cand + cand0 + sm.ctl[5];
-  const int lane = threadIdx.x & (kWave - 1);
-  static_assert(kTable % kCountBlock == 0, "uniform emit loop");
-  for (int t = threadIdx.x; t < kTable; t += kCountBlock) {
-    const int32_t key = sm.keys[t];
-    const uint32_t c = key >= 0 ? sm.vals[t] : 0u;
-    const bool em = key >= 0 && (c < kBins - 1 ? c : kBins - 1) >= thr;
-    const uint64_t mask = __ballot(em);
-    if (!mask) continue;
-    uint32_t base = 0u;
-    if (lane == 0) base = atomicAdd(&sm.ctl[4], (uint32_t)__popcll(mask));
-    base = __shfl(base, 0, kWave);
-    if (em) dst[base + __popcll(mask & ((1ull << lane) - 1ull))] = rank_key(c, key);
+  const uint64_t below = (1ull << lane) - 1ull;
+#pragma unroll
+  for (int i = 0; i < kPer; ++i) {
+    if ((mask[i] >> lane) & 1ull) dst[base + __popcll(mask[i] & below)] = rank_key(cc[i], kk[i]);
+    base += (uint32_t)__popcll(mask[i]);
   }
   return true;
 }
