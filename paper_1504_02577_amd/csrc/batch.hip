@@ -712,17 +712,17 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
   for (const auto& x : C) {
     const uint64_t L = x.first;
     const uint64_t occ = T * L;
-    const int bb = std::min(hub_bucket_bits(occ << bias), b->hub_bits_max);
+    const uint32_t nb = hub_buckets(occ << bias, b->hub_bits_max);
     const uint32_t tiles = hub_tiles(L);
     const uint32_t stiles = hub_stiles(L);
-    const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(k, kEmitCap) << bb, occ);
+    const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(k, kEmitCap) * nb, occ);
     if (cur.nq && (cur.occ + occ > occ_limit || (uint64_t)cur.tiles + tiles > 0x7FFFFFFFu ||
                    (uint64_t)cur.nq + 1 > 0x7FFFFFFFu ||
-                   (uint64_t)cur.bkts + (1u << bb) > 0x7FFFFFFFu))
+                   (uint64_t)cur.bkts + nb > 0x7FFFFFFFu))
       close();
     HubQuery h{};
     h.qi = x.second;
-    h.bb = bb;
+    h.nb = nb;
     h.tile0 = cur.tiles;
     h.stile0 = cur.stiles;
     h.bkt0 = cur.bkts;
@@ -732,7 +732,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     cur.nq += 1;
     cur.tiles += tiles;
     cur.stiles += stiles;
-    cur.bkts += 1u << bb;
+    cur.bkts += nb;
     cur.occ += occ;
     cur.cand += cand;
   }
@@ -1017,9 +1017,8 @@ size_t batched_query_bytes(const BatchSizing& z, uint64_t L, int32_t kmax) {
   size_t bytes = sizeof(int32_t) + sizeof(uint64_t);
   if (L <= z.LB) return bytes;
   const uint64_t occ = T * L;
-  const int bb = std::min(hub_bucket_bits(occ << z.bucket_bias), z.hub_bits_max);
-  const uint64_t nb = (uint64_t)1 << bb;
-  const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(kmax, kEmitCap) << bb, occ);
+  const uint64_t nb = hub_buckets(occ << z.bucket_bias, z.hub_bits_max);
+  const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(kmax, kEmitCap) * nb, occ);
   bytes += 2 * sizeof(int32_t) * occ;                                       // staging
   bytes += (3 * sizeof(uint32_t) + 2 * sizeof(uint64_t) + sizeof(int32_t)) * nb;  // buckets
   bytes += scan_temp_bytes((int64_t)nb) + sizeof(uint64_t) * cand + sizeof(uint32_t);

@@ -10,6 +10,8 @@ namespace panther {
 
 // Occurrences a bucket is sized for (the LDS table holds twice as many).
 constexpr int kBucketTarget = 4096;
+// A hub query has at most 2^kMaxBucketBits buckets.
+constexpr int kMaxBucketBits = 12;
 // A bucket emits at most max(k, kEmitCap) candidates to the merge.
 constexpr int kEmitCap = 256;
 
@@ -17,7 +19,7 @@ constexpr int kEmitCap = 256;
 // ascend with the query's position in the chunk.
 struct HubQuery {
   int32_t qi;       // index of the query in the batch
-  int32_t bb;       // log2 of its bucket count
+  uint32_t nb;      // its bucket count (1 .. 2^kMaxBucketBits)
   uint32_t tile0;   // first gather tile
   uint32_t stile0;  // first bucketing tile
   uint32_t bkt0;    // first bucket
@@ -67,7 +69,9 @@ struct HubArgs {
   float fR;
 };
 
-int hub_bucket_bits(uint64_t occ);
+// Buckets of a hub query with `occ` staging slots: about kBucketTarget
+// slots each, at most 2^max_bits.
+uint32_t hub_buckets(uint64_t occ, int max_bits);
 uint32_t hub_tiles(uint64_t L);
 uint32_t hub_stiles(uint64_t L);
 size_t hub_count_lds();

@@ -7,11 +7,12 @@
 // chunk:
 //   gather   rows of P_q -> their distinct vertices != q, T slots per row
 //            (-1 where a row has fewer), in a staging array;
-//   bucket   each staged vertex's bucket is counted (bucket = top bits of a
-//            bijective hash of the id, 2^bb buckets for query q, bb chosen
-//            so that a bucket holds about kBucketTarget occurrences), the
-//            counts are scanned, and the vertices are moved into bucket
-//            order;
+//   bucket   each staged vertex's bucket is counted (nb buckets for query
+//            q, nb = ceil(staged slots / kBucketTarget); bucket of v =
+//            floor(h(v) * nb / 2^32) for a bijective 32-bit hash h, so the
+//            buckets split the hash range into nb near-equal intervals),
+//            the counts are scanned, and the vertices are moved into
+//            bucket order;
 //   count    one work-group per bucket counts its vertices in an LDS hash
 //            table and selects the bucket's k best (count desc, id asc);
 //   merge    one work-group per query selects the k best of the per-bucket
@@ -19,10 +20,10 @@
 // Buckets partition the candidates of q, so the k best overall are among
 // the per-bucket k best, and the result is exactly that of one dense count
 // of q.  A bucket whose distinct vertices overflow the LDS table is redone
-// in sub-ranges of the hash (the next bits below the bucket bits), doubling
-// the split until it fits; a sub-range of at most half the table's size in
-// hash space holds at most that many distinct vertices, so the doubling
-// ends.
+// in sub-ranges of its hash interval (the top bits of h(v) * nb mod 2^32,
+// which runs through the interval in steps of nb), doubling the split until
+// it fits; a sub-range holding at most half the table's size of hash
+// values holds at most that many distinct vertices, so the doubling ends.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -41,7 +42,6 @@ constexpr int kGatherBlock = 256;
 constexpr int kGatherRows = 4;                        // rows per thread
 constexpr int kTileRows = kGatherBlock * kGatherRows;  // rows per gather tile
 constexpr int kSTileRows = 4096;                      // rows per bucketing tile
-constexpr int kMaxBucketBits = 12;
 constexpr int kCountBlock = 1024;
 constexpr int kTable = 2 * kBucketTarget;  // LDS hash entries of the count step
 constexpr int kTableBits = 13;
@@ -52,8 +52,20 @@ static_assert(kTable == 1 << kTableBits, "table size");
 
 __device__ __forceinline__ uint32_t vhash(int32_t v) { return (uint32_t)v * 0x9E3779B1u; }
 
-__device__ __forceinline__ uint32_t bucket_of(int32_t v, int bb) {
-  return bb == 0 ? 0u : vhash(v) >> (32 - bb);
+__device__ __forceinline__ uint32_t bucket_of(int32_t v, uint32_t nb) {
+  return (uint32_t)(((uint64_t)vhash(v) * nb) >> 32);
+}
+
+// Sub-range `sub` of 2^sbits of v's bucket: the top sbits of the position
+// of h(v) inside the bucket's hash interval.
+__device__ __forceinline__ uint32_t sub_of(int32_t v, uint32_t nb, int sbits) {
+  return (uint32_t)((uint64_t)vhash(v) * nb) >> (32 - sbits);
+}
+
+// True when a sub-range of 2^sbits holds at most kTable / 2 hash values
+// (ceil(2^(32 - sbits) / nb)), hence at most that many distinct vertices.
+__device__ __forceinline__ bool finest_split(uint32_t nb, int sbits) {
+  return ((((uint64_t)1 << (32 - sbits)) + nb - 1) / nb) <= (uint64_t)kTable / 2;
 }
 
 // kUnroll staged slots per thread, loaded before any is used (-1 past m):
@@ -76,7 +88,7 @@ __global__ void __launch_bounds__(256) k_hub_prep(HubArgs A) {
   const bool last = j + 1 == A.nq;
   const uint32_t t1 = last ? A.n_tiles : A.hq[j + 1].tile0;
   const uint32_t s1 = last ? A.n_stiles : A.hq[j + 1].stile0;
-  const uint32_t nb = 1u << Q.bb;
+  const uint32_t nb = Q.nb;
   if (threadIdx.x == 0) {
     const int32_t q = A.queries[Q.qi];
     const uint64_t a = A.inv_ptr[q];
@@ -151,7 +163,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_hist(HubArgs A) {
   const int j = A.stile_owner[tile];
   const HubQuery Q = A.hq[j];
   const uint64_t L = A.hx[j].L;
-  const int nb = 1 << Q.bb;
+  const int nb = (int)Q.nb;
   const uint64_t r0 = (uint64_t)(tile - Q.stile0) * kSTileRows;
   const uint64_t rows = L - r0 < (uint64_t)kSTileRows ? L - r0 : (uint64_t)kSTileRows;
   const uint64_t m = rows * (uint64_t)A.T;
@@ -163,7 +175,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_hist(HubArgs A) {
     load_batch(src, m, i0, x);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.bb)], 1u);
+      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.nb)], 1u);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
@@ -179,7 +191,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
   const int j = A.stile_owner[tile];
   const HubQuery Q = A.hq[j];
   const uint64_t L = A.hx[j].L;
-  const int nb = 1 << Q.bb;
+  const int nb = (int)Q.nb;
   const uint64_t r0 = (uint64_t)(tile - Q.stile0) * kSTileRows;
   const uint64_t rows = L - r0 < (uint64_t)kSTileRows ? L - r0 : (uint64_t)kSTileRows;
   const uint64_t m = rows * (uint64_t)A.T;
@@ -191,7 +203,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
     load_batch(src, m, i0, x);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.bb)], 1u);
+      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.nb)], 1u);
   }
   __syncthreads();
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
@@ -206,7 +218,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
       if (x[u] >= 0) {
-        const uint32_t b = bucket_of(x[u], Q.bb);
+        const uint32_t b = bucket_of(x[u], Q.nb);
         A.stB[base[b] + atomicAdd(&hist[b], 1u)] = x[u];
       }
   }
@@ -254,14 +266,14 @@ struct alignas(16) CountSmem {
   uint32_t ctl[8];
 };
 
-// Counts the vertices of stB[s, e) whose hash bits below the bucket bits
-// equal `sub` (all of them when sbits == 0) in the LDS table.  Returns false
-// when the table overflowed.  At the finest split (bb + sbits == 32 -
-// kFitBits) at most kTable / 2 distinct ids qualify and the probe sequence
-// is unbounded, so it never fails there.
+// Counts the vertices of stB[s, e) (one bucket of a query with nb buckets)
+// whose sub-range of 2^sbits is `sub` (all of them when sbits == 0) in the
+// LDS table.  Returns false when the table overflowed.  At the finest split
+// at most kTable / 2 distinct ids qualify and the probe sequence is
+// unbounded, so it never fails there.
 __device__ bool count_part(const HubArgs& A, int32_t* keys, uint32_t* vals, uint32_t* ctl,
-                           uint64_t s, uint64_t e, int bb, int sbits, uint32_t sub) {
-  const int probes = bb + sbits >= 32 - kFitBits ? kTable : kProbes;
+                           uint64_t s, uint64_t e, uint32_t nb, int sbits, uint32_t sub) {
+  const int probes = sbits > 0 && finest_split(nb, sbits) ? kTable : kProbes;
   for (int j = threadIdx.x; j < kTable / 4; j += kCountBlock) {
     reinterpret_cast<int4*>(keys)[j] = make_int4(-1, -1, -1, -1);
     reinterpret_cast<uint4*>(vals)[j] = make_uint4(0u, 0u, 0u, 0u);
@@ -282,7 +294,7 @@ __device__ bool count_part(const HubArgs& A, int32_t* keys, uint32_t* vals, uint
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       if (x[u] < 0) continue;
-      if (sbits > 0 && ((vhash(x[u]) << bb) >> (32 - sbits)) != sub) continue;
+      if (sbits > 0 && sub_of(x[u], nb, sbits) != sub) continue;
       if (!table_add(keys, vals, x[u], probes)) fail = true;
     }
   }
@@ -428,7 +440,7 @@ __global__ void __launch_bounds__(kCountBlock) k_hub_count(HubArgs A) {
   const uint64_t cand0 = A.bkt_cand0[g];
   const uint64_t s = A.bkt_start[g];
   const uint64_t e = A.bkt_start[g + 1];
-  if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, 0, 0, 0u) && emit_by_count(A, sm, j, cand0))
+  if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, 1u, 0, 0u) && emit_by_count(A, sm, j, cand0))
     return;
   if (threadIdx.x == 0) A.redo[atomicAdd(A.redo_n, 1u)] = g;
 }
@@ -447,16 +459,16 @@ __global__ void __launch_bounds__(kCountBlock) k_hub_count_rare(HubArgs A) {
     const uint64_t e = A.bkt_start[g + 1];
     int m;
     const uint64_t* best = sm.sel.out;
-    if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.bb, 0, 0u)) {
+    if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.nb, 0, 0u)) {
       m = select_exact(A, sm);
     } else {
       // split by the next hash bits until every part fits
       m = 0;
-      for (int sbits = 1; sbits <= 32 - kFitBits - Q.bb; ++sbits) {
+      for (int sbits = 1; sbits <= 32 - kFitBits; ++sbits) {
         int rr = 0;  // keys in sm.run
         bool ok = true;
         for (uint32_t sub = 0; sub < (1u << sbits); ++sub) {
-          if (!count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.bb, sbits, sub)) {
+          if (!count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.nb, sbits, sub)) {
             ok = false;
             break;
           }
@@ -517,10 +529,10 @@ __global__ void __launch_bounds__(kCountBlock) k_hub_merge(HubArgs A) {
 
 namespace panther {
 
-int hub_bucket_bits(uint64_t occ) {
-  int bb = 0;
-  while (bb < kMaxBucketBits && ((uint64_t)kBucketTarget << bb) < occ) ++bb;
-  return bb;
+uint32_t hub_buckets(uint64_t occ, int max_bits) {
+  const uint64_t lim = (uint64_t)1 << std::min(std::max(max_bits, 0), kMaxBucketBits);
+  const uint64_t nb = (occ + kBucketTarget - 1) / kBucketTarget;
+  return (uint32_t)std::max<uint64_t>(1, std::min(nb, lim));
 }
 
 uint32_t hub_tiles(uint64_t L) { return (uint32_t)((L + kTileRows - 1) / kTileRows); }
