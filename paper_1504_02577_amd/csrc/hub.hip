@@ -43,12 +43,13 @@ constexpr int kGatherRows = 4;                        // rows per thread
 constexpr int kTileRows = kGatherBlock * kGatherRows;  // rows per gather tile
 constexpr int kSTileRows = 4096;                      // rows per bucketing tile
 constexpr int kCountBlock = 1024;
-constexpr int kTable = 2 * kBucketTarget;  // LDS hash entries of the count step
+constexpr int kTable = 8192;  // LDS hash entries of the count step
 constexpr int kTableBits = 13;
 constexpr int kProbes = 32;                // bounded probe sequence
 constexpr int kFitBits = kTableBits - 1;   // log2(kTable / 2)
 constexpr uint32_t kRareGrid = 256;        // work-groups of the rare count path
 static_assert(kTable == 1 << kTableBits, "table size");
+static_assert(kBucketTarget * 8 <= kTable * 5, "table load");
 
 __device__ __forceinline__ uint32_t vhash(int32_t v) { return (uint32_t)v * 0x9E3779B1u; }
 
