@@ -253,7 +253,6 @@ struct alignas(16) TableSmem {
   int32_t keys[kTable];
   uint32_t vals[kTable];
   uint32_t ch[256];
-  uint64_t red[32];
   uint32_t ctl[8];
 };
 
@@ -388,24 +387,39 @@ __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t c
     atomicAdd(&sm.ch[3], low >> 20);
   }
   __syncthreads();
-  // descending bins, one per thread: the count above a bin by a block scan
-  const int bin = kBins - 1 - (int)threadIdx.x;
-  const uint64_t h = bin >= 0 ? (uint64_t)sm.ch[bin] : 0ull;
-  uint64_t tot;
-  const uint64_t above = block_exclusive_sum<kCountBlock>(h, sm.red, &tot);
-  const uint64_t k = (uint64_t)A.k;
-  if (bin >= 1 && above < k && above + h >= k) {
-    sm.ctl[2] = (uint32_t)bin;
-    sm.ctl[3] = (uint32_t)(above + h);
+  // the threshold, by one wave: lane L holds bins 255 - 4L .. 252 - 4L
+  // (descending), a wave scan gives the entries above each of them
+  const uint32_t k = (uint32_t)A.k;
+  const int lane = threadIdx.x & (kWave - 1);
+  static_assert(kBins == 4 * kWave, "four bins per lane");
+  if (threadIdx.x < kWave) {
+    uint32_t hb[4], sum = 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      hb[i] = sm.ch[kBins - 1 - 4 * lane - i];
+      sum += hb[i];
+    }
+    const uint32_t inc = wave_inclusive_sum(sum);
+    uint32_t above = inc - sum;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int bin = kBins - 1 - 4 * lane - i;
+      if (bin >= 1 && above < k && above + hb[i] >= k) {
+        sm.ctl[2] = (uint32_t)bin;
+        sm.ctl[3] = above + hb[i];
+      }
+      above += hb[i];
+    }
+    if (lane == kWave - 1) sm.ctl[6] = inc;  // entries in the table
   }
   __syncthreads();
   const uint32_t thr = sm.ctl[2];
-  const uint32_t n_emit = tot < k ? (uint32_t)tot : sm.ctl[3];
+  const uint32_t tot = sm.ctl[6];
+  const uint32_t n_emit = tot < k ? tot : sm.ctl[3];
   const uint32_t cap = (uint32_t)(A.k > kEmitCap ? A.k : kEmitCap);
   if (n_emit > cap) return false;  // uniform: every thread read the same words
   if (threadIdx.x == 0) sm.ctl[5] = n_emit ? atomicAdd(&A.cand_n[j], n_emit) : 0u;
   // a wave's emitted entries: ballots first, then one cursor add per wave
-  const int lane = threadIdx.x & (kWave - 1);
   uint64_t mask[kPer];
   uint32_t wtot = 0u;
 #pragma unroll
