@@ -379,8 +379,7 @@ __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t c
         atomicAdd(&sm.ch[c < kBins - 1 ? c : kBins - 1], 1u);
     }
   }
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) low += __shfl_xor(low, off, kWave);
+  low = __ockl_wfred_add_u32(low);  // wave sum (DPP lane moves)
   if ((threadIdx.x & (kWave - 1)) == 0 && low) {
     atomicAdd(&sm.ch[1], low & 1023u);
     atomicAdd(&sm.ch[2], (low >> 10) & 1023u);
@@ -429,7 +428,7 @@ __device__ bool emit_by_count(const HubArgs& A, TableSmem& sm, int j, uint64_t c
   }
   uint32_t base = 0u;
   if (lane == 0 && wtot) base = atomicAdd(&sm.ctl[4], wtot);
-  base = __shfl(base, 0, kWave);
+  base = __builtin_amdgcn_readfirstlane(base);  // lane 0's value (all lanes active)
   __syncthreads();
   uint64_t* dst = A.cand + cand0 + sm.ctl[5];
   const uint64_t below = (1ull << lane) - 1ull;
