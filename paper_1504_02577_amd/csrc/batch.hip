@@ -322,6 +322,8 @@ struct BatchState {
   size_t hx_cap = 0;
   int32_t* d_tile_owner = nullptr;
   size_t tile_owner_cap = 0;
+  uint32_t* d_th = nullptr;
+  size_t th_cap = 0;
   int32_t* d_stile_owner = nullptr;
   size_t stile_owner_cap = 0;
   int32_t* d_bkt_owner = nullptr;
@@ -417,7 +419,7 @@ void free_batch_state(Lane* lane) {
                   (void*)b->d_bkt_fill, (void*)b->d_bkt_start, (void*)b->d_cand,
                   (void*)b->d_cand_n, (void*)b->d_scan, (void*)b->d_hx,
                   (void*)b->d_tile_owner, (void*)b->d_stile_owner, (void*)b->d_bkt_owner,
-                  (void*)b->d_bkt_cand0, (void*)b->d_redo})
+                  (void*)b->d_bkt_cand0, (void*)b->d_redo, (void*)b->d_th})
     ctx_free(p);
   delete b;
   lane->batch = nullptr;
@@ -692,12 +694,12 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
   struct Chunk {
     size_t first, nq;
     uint32_t tiles, stiles, bkts;
-    uint64_t occ, cand;
+    uint64_t occ, cand, ths;
   };
   std::vector<Chunk> chunks;
-  Chunk cur{0, 0, 0, 0, 0, 0, 0};
+  Chunk cur{0, 0, 0, 0, 0, 0, 0, 0};
   size_t max_bkt = 0, max_nq = 0, max_tiles = 0, max_stiles = 0;
-  uint64_t max_occ = 0, max_cand = 0;
+  uint64_t max_occ = 0, max_cand = 0, max_ths = 0;
   auto close = [&]() {
     if (!cur.nq) return;
     chunks.push_back(cur);
@@ -707,7 +709,8 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     max_stiles = std::max<size_t>(max_stiles, cur.stiles);
     max_occ = std::max(max_occ, cur.occ);
     max_cand = std::max(max_cand, cur.cand);
-    cur = Chunk{b->h_hq.size(), 0, 0, 0, 0, 0, 0};
+    max_ths = std::max(max_ths, cur.ths);
+    cur = Chunk{b->h_hq.size(), 0, 0, 0, 0, 0, 0, 0};
   };
   for (const auto& x : C) {
     const uint64_t L = x.first;
@@ -718,7 +721,8 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     const uint64_t cand = std::min<uint64_t>((uint64_t)std::max(k, kEmitCap) * nb, occ);
     if (cur.nq && (cur.occ + occ > occ_limit || (uint64_t)cur.tiles + tiles > 0x7FFFFFFFu ||
                    (uint64_t)cur.nq + 1 > 0x7FFFFFFFu ||
-                   (uint64_t)cur.bkts + nb > 0x7FFFFFFFu))
+                   (uint64_t)cur.bkts + nb > 0x7FFFFFFFu ||
+                   cur.ths + (uint64_t)stiles * nb > 0xFFFFFFFFu))
       close();
     HubQuery h{};
     h.qi = x.second;
@@ -728,6 +732,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     h.bkt0 = cur.bkts;
     h.occ0 = cur.occ;
     h.cand0 = cur.cand;
+    h.th0 = (uint32_t)cur.ths;
     b->h_hq.push_back(h);
     cur.nq += 1;
     cur.tiles += tiles;
@@ -735,6 +740,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     cur.bkts += nb;
     cur.occ += occ;
     cur.cand += cand;
+    cur.ths += (uint64_t)stiles * nb;
   }
   close();
   int st;
@@ -763,6 +769,8 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
   if ((st = grow(c, b->d_bkt_cand0, b->bkt_cand0_cap, max_bkt, sizeof(uint64_t), "hub maps")))
     return st;
   if ((st = grow(c, b->d_redo, b->redo_cap, max_bkt + 16, sizeof(uint32_t), "hub maps")))
+    return st;
+  if ((st = grow(c, b->d_th, b->th_cap, max_ths, sizeof(uint32_t), "hub tile counts")))
     return st;
   if ((st = pinned_ensure(c, b->pin_hq, sizeof(HubQuery) * b->h_hq.size(), "hub plan")))
     return st;
@@ -796,6 +804,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     h.bkt_cnt = b->d_bkt_cnt;
     h.bkt_start = b->d_bkt_start;
     h.bkt_fill = b->d_bkt_fill;
+    h.th = b->d_th;
     h.cand = b->d_cand;
     h.cand_n = b->d_cand_n;
     h.out_ids = d_ids;
@@ -1024,6 +1033,7 @@ size_t batched_query_bytes(const BatchSizing& z, uint64_t L, int32_t kmax) {
   bytes += scan_temp_bytes((int64_t)nb) + sizeof(uint64_t) * cand + sizeof(uint32_t);
   bytes += sizeof(HubQuery) + sizeof(HubList) +
            sizeof(int32_t) * ((size_t)hub_tiles(L) + hub_stiles(L));
+  bytes += sizeof(uint32_t) * ((size_t)hub_stiles(L) * nb);  // per-tile bucket counts
   return bytes;
 }
 
@@ -1045,6 +1055,7 @@ size_t lane_device_bytes(const Lane* lane) {
   t += sizeof(uint64_t) * (b->bkt_start_cap + b->cand_cap + b->bkt_cand0_cap);
   t += sizeof(HubList) * b->hx_cap + b->scan_cap;
   t += sizeof(int32_t) * (b->tile_owner_cap + b->stile_owner_cap + b->bkt_owner_cap);
+  t += sizeof(uint32_t) * b->th_cap;
   return t;
 }
 

@@ -26,7 +26,7 @@ struct HubQuery {
   uint32_t tile0;   // first gather tile
   uint32_t stile0;  // first bucketing tile
   uint32_t bkt0;    // first bucket
-  uint32_t pad;
+  uint32_t th0;     // first per-tile bucket count (bucketing tile-major)
   uint64_t occ0;    // first staging slot (T slots per row of P_q)
   uint64_t cand0;   // first slot of its per-bucket winners
 };
@@ -63,6 +63,7 @@ struct HubArgs {
   uint32_t* bkt_cnt;     // [n_bkt]
   uint64_t* bkt_start;   // [n_bkt + 1]
   uint32_t* bkt_fill;    // [n_bkt]
+  uint32_t* th;          // per bucketing tile bucket counts (gather -> scatter)
   uint64_t* cand;        // per-bucket winners, grouped by query
   uint32_t* cand_n;      // [nq]
   int32_t* out_ids;

@@ -6,13 +6,15 @@
 // through four steps, each a grid-wide launch over all hub queries of a
 // chunk:
 //   gather   rows of P_q -> their distinct vertices != q, T slots per row
-//            (-1 where a row has fewer), in a staging array;
-//   bucket   each staged vertex's bucket is counted (nb buckets for query
-//            q, nb = ceil(staged slots / kBucketTarget); bucket of v =
+//            (-1 where a row has fewer), in a staging array; each tile
+//            also counts its vertices per bucket (nb buckets for query q,
+//            nb = ceil(staged slots / kBucketTarget); bucket of v =
 //            floor(h(v) * nb / 2^32) for a bijective 32-bit hash h, so the
 //            buckets split the hash range into nb near-equal intervals),
-//            the counts are scanned, and the vertices are moved into
-//            bucket order;
+//            keeps the tile's counts and adds them to the bucket totals;
+//   bucket   the totals are scanned, and each tile moves its vertices into
+//            bucket order (its run of a bucket placed by one atomic
+//            reservation);
 //   count    one work-group per bucket counts its vertices in an LDS hash
 //            table and selects the bucket's k best (count desc, id asc);
 //   merge    one work-group per query selects the k best of the per-bucket
@@ -41,10 +43,10 @@ namespace {
 constexpr int kGatherBlock = 256;
 constexpr int kGatherRows = 4;                        // rows per thread
 constexpr int kTileRows = kGatherBlock * kGatherRows;  // rows per gather tile
-// rows per bucketing tile: one gather tile (its staged slots are still in
-// L2 for the second read of the scatter); 4,096 measured 1.5 ms slower per
-// R-MAT 24 call, 512 and 2,048 in between
-constexpr int kSTileRows = 1024;
+// Rows per bucketing tile: one gather tile, whose per-bucket counts the
+// gather keeps for the scatter.  (Before the gather counted, 4,096-row
+// bucketing tiles measured 1.5 ms slower per R-MAT 24 call than 1,024.)
+constexpr int kSTileRows = kTileRows;
 constexpr int kCountBlock = 1024;
 constexpr int kTable = 8192;  // LDS hash entries of the count step
 constexpr int kTableBits = 13;
@@ -112,6 +114,7 @@ __global__ void __launch_bounds__(256) k_hub_prep(HubArgs A) {
 
 template <int S>
 __global__ void __launch_bounds__(kGatherBlock) k_hub_gather(HubArgs A) {
+  __shared__ uint32_t hist[1 << kMaxBucketBits];
   const uint32_t tile = blockIdx.x;
   const int j = A.tile_owner[tile];
   const HubQuery Q = A.hq[j];
@@ -120,7 +123,10 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_gather(HubArgs A) {
   const uint64_t a = X.a;
   const uint64_t L = X.L;
   const int T = A.T;
+  const int nb = (int)Q.nb;
   const uint64_t r0 = (uint64_t)(tile - Q.tile0) * kTileRows;
+  for (int b = threadIdx.x; b < nb; b += kGatherBlock) hist[b] = 0u;
+  __syncthreads();
   // rows are held in registers RG at a time (fewer for long rows)
   constexpr int RG = S <= 16 ? kGatherRows : 1;
 #pragma unroll 1
@@ -153,37 +159,20 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_gather(HubArgs A) {
 #pragma unroll
       for (int jj = 0; jj < S; ++jj) {
         const int32_t x = v[i][jj];
-        if (x >= 0 && x != q && c < T) dst[c++] = x;
+        if (x >= 0 && x != q && c < T) {
+          dst[c++] = x;
+          atomicAdd(&hist[bucket_of(x, Q.nb)], 1u);
+        }
       }
       for (int jj = c; jj < T; ++jj) dst[jj] = -1;
     }
   }
-}
-
-// Bucket counts of one bucketing tile (kSTileRows rows of one query).
-__global__ void __launch_bounds__(kGatherBlock) k_hub_hist(HubArgs A) {
-  __shared__ uint32_t hist[1 << kMaxBucketBits];
-  const uint32_t tile = blockIdx.x;
-  const int j = A.stile_owner[tile];
-  const HubQuery Q = A.hq[j];
-  const uint64_t L = A.hx[j].L;
-  const int nb = (int)Q.nb;
-  const uint64_t r0 = (uint64_t)(tile - Q.stile0) * kSTileRows;
-  const uint64_t rows = L - r0 < (uint64_t)kSTileRows ? L - r0 : (uint64_t)kSTileRows;
-  const uint64_t m = rows * (uint64_t)A.T;
-  const int32_t* src = A.stA + Q.occ0 + r0 * (uint64_t)A.T;
-  for (int b = threadIdx.x; b < nb; b += kGatherBlock) hist[b] = 0u;
+  // the tile's bucket counts: kept for the scatter, added to the totals
   __syncthreads();
-  for (uint64_t i0 = 0; i0 < m; i0 += kUnroll * kGatherBlock) {
-    int32_t x[kUnroll];
-    load_batch(src, m, i0, x);
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.nb)], 1u);
-  }
-  __syncthreads();
+  uint32_t* th = A.th + Q.th0 + (uint64_t)(tile - Q.tile0) * (uint32_t)nb;
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
     const uint32_t h = hist[b];
+    th[b] = h;
     if (h) atomicAdd(&A.bkt_cnt[Q.bkt0 + b], h);
   }
 }
@@ -200,18 +189,10 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
   const uint64_t rows = L - r0 < (uint64_t)kSTileRows ? L - r0 : (uint64_t)kSTileRows;
   const uint64_t m = rows * (uint64_t)A.T;
   const int32_t* src = A.stA + Q.occ0 + r0 * (uint64_t)A.T;
-  for (int b = threadIdx.x; b < nb; b += kGatherBlock) hist[b] = 0u;
-  __syncthreads();
-  for (uint64_t i0 = 0; i0 < m; i0 += kUnroll * kGatherBlock) {
-    int32_t x[kUnroll];
-    load_batch(src, m, i0, x);
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      if (x[u] >= 0) atomicAdd(&hist[bucket_of(x[u], Q.nb)], 1u);
-  }
-  __syncthreads();
+  // this tile's bucket counts, from the gather
+  const uint32_t* th = A.th + Q.th0 + (uint64_t)(tile - Q.stile0) * (uint32_t)nb;
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
-    const uint32_t h = hist[b];
+    const uint32_t h = th[b];
     base[b] = h ? (uint32_t)A.bkt_start[Q.bkt0 + b] + atomicAdd(&A.bkt_fill[Q.bkt0 + b], h) : 0u;
     hist[b] = 0u;
   }
@@ -569,7 +550,6 @@ hipError_t enqueue_hub_chunk(const HubArgs& A, int stride, void* scan_temp, hipS
     case 32: k_hub_gather<32><<<A.n_tiles, kGatherBlock, 0, s>>>(A); break;
     default: k_hub_gather<64><<<A.n_tiles, kGatherBlock, 0, s>>>(A); break;
   }
-  k_hub_hist<<<A.n_stiles, kGatherBlock, 0, s>>>(A);
   launch_scan_u32_to_u64(A.bkt_cnt, A.bkt_start, A.n_bkt, scan_temp, s);
   k_hub_scatter<<<A.n_stiles, kGatherBlock, 0, s>>>(A);
   k_hub_count<<<A.n_bkt, kCountBlock, 0, s>>>(A);
