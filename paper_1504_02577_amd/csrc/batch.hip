@@ -1,20 +1,21 @@
-// Panther query, batched form: every query of a call in one persistent
-// kernel launch (captured in a HIP graph and replayed), with the tile sizes
+// Panther query, batched form: every query of a call in one launch
+// sequence (captured in a HIP graph and replayed), with the tile sizes
 // picked by an autotuner.
 //
 // Queries are split by the length L of their path list P_q (known on the
-// host from the index offsets) into three tiers, placed on a device work
-// queue longest-first:
-//   A  (T*L fits half of a per-wave LDS table): one wavefront per query.
-//      Open-addressing hash (vertex -> count) in LDS, then the occupied
-//      slots are compacted to 64-bit ranking keys and bitonic-sorted by the
-//      wave alone (no work-group barrier).
-//   B  (fits half of a work-group LDS table): one work-group per query, LDS
-//      hash, then block selection of the k largest keys.
+// host from the index offsets) into three tiers, each ordered longest
+// length class first:
+//   A  (T*L fits half of a per-wave LDS table): one wavefront per query in
+//      k_topk_waves.  Open-addressing hash (vertex -> count) in LDS, then
+//      the occupied slots are compacted to 64-bit ranking keys and
+//      bitonic-sorted by the wave alone (no work-group barrier).
+//   B  (fits half of a work-group LDS table): one work-group per query in
+//      the persistent k_topk_batched (work queue), LDS hash, then block
+//      selection of the k largest keys.
 //   C  (hubs, the rest): split across many work-groups by the pipeline in
 //      hub.hip (candidates bucketed by a hash of their id, each bucket
 //      counted in LDS by its own work-group, per-bucket winners merged),
-//      enqueued on the same stream ahead of the persistent kernel.
+//      on a second stream beside the other two.
 // Counting is exact integer arithmetic and the ranking key (count desc, id
 // asc) is a total order, so the result equals the plain form bit for bit.
 #include <fcntl.h>
@@ -215,34 +216,43 @@ __device__ void block_query_lds(const BatchArgs& A, int32_t qi, char* region, Se
   __syncthreads();
 }
 
+// ---- tier B: a persistent grid of work-groups takes the B items from a
+// work queue, one query per work-group at a time ----
 template <int BLOCK, int S>
 __global__ void __launch_bounds__(BLOCK) k_topk_batched(BatchArgs A) {
   extern __shared__ __align__(16) char lds[];
   SelectSmem& sm = *reinterpret_cast<SelectSmem*>(lds);
   uint32_t* s_ctl = reinterpret_cast<uint32_t*>(lds + sizeof(SelectSmem));
   char* region = lds + sizeof(SelectSmem) + 64;
-  constexpr int kWaves = BLOCK / kWave;
-  const int nAgroups = (A.nA + kWaves - 1) / kWaves;
   while (true) {
     if (threadIdx.x == 0) {
-      const uint32_t x = atomicAdd(&A.queue[0], 1u);  // [0, nB) B, then A groups
-      s_ctl[1] = (int)x < A.nB + nAgroups ? x : 0xFFFFFFFFu;
+      const uint32_t x = atomicAdd(&A.queue[0], 1u);
+      s_ctl[1] = (int)x < A.nB ? x : 0xFFFFFFFFu;
     }
     __syncthreads();
     const int item = (int)s_ctl[1];
     __syncthreads();
     if (item < 0) break;
-    if (item < A.nB) {
-      block_query_lds<BLOCK, S>(A, A.itemsB[item], region, sm, s_ctl + 4);
-    } else {
-      const int g = item - A.nB;
-      const int w = threadIdx.x / kWave;
-      const int ai = g * kWaves + w;
-      if (ai < A.nA)
-        wave_query<S>(A, A.itemsA[ai], region + (size_t)w * (size_t)A.TA * 12);
-      __syncthreads();
-    }
+    block_query_lds<BLOCK, S>(A, A.itemsB[item], region, sm, s_ctl + 4);
   }
+}
+
+// ---- tier A as a kernel of its own: no block selection scratch, so more
+// waves share a CU (six work-groups of four waves); wave w of W takes the
+// A items w, w + W, ... (they are ordered longest class first, so every
+// wave gets a similar mix), with no shared queue to contend on ----
+constexpr int kWaveBlock = 256;
+constexpr int kWaveTA = 512;      // table entries per wave
+constexpr int kWaveWgsPerCu = 6;  // 6 x 24 KB of LDS per CU
+
+template <int S>
+__global__ void __launch_bounds__(kWaveBlock) k_topk_waves(BatchArgs A) {
+  __shared__ __align__(16) char lds[kWaveBlock / kWave * 12 * kWaveTA];
+  const int w = threadIdx.x / kWave;
+  char* region = lds + (size_t)w * 12 * kWaveTA;
+  const int W = (int)(gridDim.x * (kWaveBlock / kWave));
+  for (int ai = (int)(blockIdx.x * (kWaveBlock / kWave)) + w; ai < A.nA; ai += W)
+    wave_query<S>(A, A.itemsA[ai], region);
 }
 
 __global__ void k_reset_queue(uint32_t* q) {
@@ -250,6 +260,16 @@ __global__ void k_reset_queue(uint32_t* q) {
 }
 
 using KernelFn = void (*)(BatchArgs);
+
+KernelFn pick_wave_kernel(int stride) {
+  switch (stride) {
+    case 4: return k_topk_waves<4>;
+    case 8: return k_topk_waves<8>;
+    case 16: return k_topk_waves<16>;
+    case 32: return k_topk_waves<32>;
+    default: return k_topk_waves<64>;
+  }
+}
 
 template <int BLOCK>
 KernelFn pick_kernel(int stride) {
@@ -471,12 +491,10 @@ Layout layout_for(const panther_ctx* c, const BatchConfig& cfg) {
   if (cfg.wgs_per_cu > 1) limit = std::min(limit, (size_t)163840 / cfg.wgs_per_cu);
   const size_t fixed = sizeof(SelectSmem) + 64;
   const size_t avail = limit > fixed ? limit - fixed : 0;
-  const int waves = cfg.block / kWave;
-  int TB = 64, TA = 64;
+  int TB = 64;
   while ((size_t)12 * (TB * 2) <= avail && TB < 16384) TB *= 2;
-  while ((size_t)12 * (TA * 2) * waves <= avail && TA < 2048) TA *= 2;
-  const size_t region = std::max((size_t)12 * TB, (size_t)12 * TA * waves);
-  return Layout{fixed + region, TA, TB};
+  // tier A runs in k_topk_waves with tables of its own size
+  return Layout{fixed + (size_t)12 * TB, kWaveTA, TB};
 }
 
 // The configurations a lane may run: every tuner choice, with the forced
@@ -595,8 +613,15 @@ static hipError_t enqueue(panther_ctx* c, BatchState* b, const Plan& P, KernelFn
     if (e != hipSuccess) return e;
   }
   if (P.run_kernel) {
-    k_reset_queue<<<1, 64, 0, s>>>(P.args.queue);
-    hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, P.args);
+    if (P.args.nB > 0) {
+      k_reset_queue<<<1, 64, 0, s>>>(P.args.queue);
+      hipLaunchKernelGGL(fn, dim3(grid), dim3(block), lds, s, P.args);
+    }
+    if (P.args.nA > 0) {
+      const int wgrid = c->num_cus * kWaveWgsPerCu;
+      hipLaunchKernelGGL(pick_wave_kernel(c->stride), dim3(wgrid), dim3(kWaveBlock), 0, s,
+                         P.args);
+    }
   }
   if (fork) {
     hipError_t e = hipEventRecord(b->ev_join, b->side);
