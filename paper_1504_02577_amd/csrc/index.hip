@@ -59,7 +59,10 @@ k_radix_up_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shi
   __shared__ uint32_t s_hist[kRadix];
   for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
   __syncthreads();
-  const uint64_t p0 = (uint64_t)blockIdx.x * ppt;
+  // tiles in the down-sweeps' XCD order, so that the counts of neighbouring
+  // tiles (adjacent in the digit-major table) leave one L2 as whole lines
+  const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint64_t p0 = tile * (uint64_t)ppt;
   // RG rows in flight per thread before their digits are counted
   constexpr int RG = S <= 8 ? 4 : (S <= 16 ? 2 : 1);
   for (int r0 = 0; r0 < ppt; r0 += RG * kBlock) {
@@ -84,7 +87,7 @@ k_radix_up_paths(const int32_t* __restrict__ paths, uint64_t R, int ppt, int shi
     }
   }
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + tile] = s_hist[d];
 }
 
 // LDS of a down-sweep: the tile's pairs (pass 1 stages them here), then the
@@ -250,7 +253,8 @@ k_radix_up_pairs(const uint32_t* __restrict__ keys, const uint64_t* __restrict__
   for (int d = threadIdx.x; d < kRadix; d += kBlock) s_hist[d] = 0u;
   __syncthreads();
   const uint64_t nnz = *nnz_dev;  // tiles past it count nothing
-  const uint64_t a = (uint64_t)blockIdx.x * kTileItems;
+  const uint64_t tile = xcd_tile(blockIdx.x, gridDim.x);  // as in k_radix_up_paths
+  const uint64_t a = tile * kTileItems;
   // all 16 keys of the thread are loaded before any is counted
   uint32_t k[16];
 #pragma unroll
@@ -262,7 +266,7 @@ k_radix_up_pairs(const uint32_t* __restrict__ keys, const uint64_t* __restrict__
   for (int j = 0; j < 16; ++j)
     if (k[j] != 0xFFFFFFFFu) atomicAdd(&s_hist[digit_of(k[j], shift, bits)], 1u);
   __syncthreads();
-  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + blockIdx.x] = s_hist[d];
+  for (int d = threadIdx.x; d < kRadix; d += kBlock) hist[(uint64_t)d * ntiles + tile] = s_hist[d];
 }
 
 // Passes >= 2: the tile of 4096 consecutive pairs goes straight to registers.
