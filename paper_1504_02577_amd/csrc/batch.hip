@@ -51,6 +51,9 @@ struct BatchArgs {
   const int32_t* itemsB;   // query indices, longest class first
   const int32_t* itemsA;
   int32_t nB, nA;
+  // tier A runs in four phases of 64, 32, 16 and 8 lanes per query:
+  // itemsA [0, nA64), [nA64, nA32), [nA32, nA16), [nA16, nA)
+  int32_t nA64, nA32, nA16;
   const uint64_t* inv_ptr;
   const uint32_t* inv_pid;
   const int32_t* paths;
@@ -130,57 +133,85 @@ __device__ __forceinline__ void write_row(const BatchArgs& A, int32_t qi, const 
   if (t == 0) A.out_len[qi] = m;
 }
 
-// ---- tier A: one wavefront per query ----
-template <int S>
-__device__ void wave_query(const BatchArgs& A, int32_t qi, char* region) {
+// ---- tier A: a group of G lanes of one wavefront per query (G = 64, 32,
+// 16 or 8), with a table of kWaveTA * G / 64 entries ----
+constexpr int kWaveTA = 512;  // table entries of a whole wave
+
+// Item ai (< hi) of itemsA by the G lanes of this thread's group, whose LDS
+// region holds 12 * TG bytes: the table (TG keys, TG counts), then up to
+// TG / 2 ranking keys.  Open-addressing hash (vertex -> count), then the
+// occupied slots are compacted and bitonic-sorted by the group alone (no
+// work-group barrier; groups of one wave diverge only in trip counts and
+// touch disjoint regions).  An inactive group (ai >= hi) writes nothing.
+template <int S, int G>
+__device__ void group_query(const BatchArgs& A, int ai, int hi, char* region) {
+  constexpr int TG = kWaveTA * G / kWave;
   const int lane = threadIdx.x & (kWave - 1);
-  const int TA = A.TA;
+  const int gl = lane & (G - 1);
+  const int gbase = lane & ~(G - 1);
+  const uint64_t gmask = G == kWave ? ~0ull : ((1ull << (G & 63)) - 1ull) << gbase;
   int32_t* keys = reinterpret_cast<int32_t*>(region);
-  uint32_t* vals = reinterpret_cast<uint32_t*>(keys + TA);
-  uint64_t* sorted = reinterpret_cast<uint64_t*>(vals + TA);  // TA/2 entries
-  const int32_t q = A.queries[qi];
-  const uint64_t a = A.inv_ptr[q];
-  const uint64_t L = A.inv_ptr[q + 1] - a;
-  for (int j = lane; j < TA; j += kWave) {
+  uint32_t* vals = reinterpret_cast<uint32_t*>(keys + TG);
+  uint64_t* sorted = reinterpret_cast<uint64_t*>(vals + TG);  // TG/2 entries
+  const bool active = ai < hi;
+  int32_t qi = 0, q = -1;
+  uint64_t a = 0, L = 0;
+  if (active) {
+    qi = A.itemsA[ai];
+    q = A.queries[qi];
+    a = A.inv_ptr[q];
+    L = A.inv_ptr[q + 1] - a;
+  }
+  for (int j = gl; j < TG; j += G) {
     keys[j] = -1;
     vals[j] = 0u;
   }
   wave_sync();
-  const uint32_t mask = (uint32_t)TA - 1u;
-  for_each_candidate<S>(A, q, a, L, lane, kWave,
-                        [&](int32_t v) { lds_insert(keys, vals, mask, v); });
+  for_each_candidate<S>(A, q, a, L, gl, G,
+                        [&](int32_t v) { lds_insert(keys, vals, (uint32_t)TG - 1u, v); });
   wave_sync();
   // compact occupied slots into ranking keys
   int nc = 0;
-  for (int base = 0; base < TA; base += kWave) {
-    const int j = base + lane;
+  for (int base = 0; base < TG; base += G) {
+    const int j = base + gl;
     const int32_t key = keys[j];
     const bool occ = key >= 0;
-    const uint64_t bm = __ballot(occ);
-    if (occ) sorted[nc + __popcll(bm & ((1ull << lane) - 1ull))] = rank_key(vals[j], key);
+    const uint64_t bm = (__ballot(occ) & gmask) >> gbase;
+    if (occ) sorted[nc + __popcll(bm & ((1ull << gl) - 1ull))] = rank_key(vals[j], key);
     nc += __popcll(bm);
   }
   int P = 2;
   while (P < nc) P <<= 1;
-  for (int j = nc + lane; j < P; j += kWave) sorted[j] = 0ull;
+  for (int j = nc + gl; j < P; j += G) sorted[j] = 0ull;
   wave_sync();
   for (int size = 2; size <= P; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = lane; i < (P >> 1); i += kWave) {
+      for (int i = gl; i < (P >> 1); i += G) {
         const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));  // stride: power of two
-        const int hi = lo + stride;
+        const int hi2 = lo + stride;
         const bool desc = (lo & size) == 0;
-        const uint64_t x = sorted[lo], y = sorted[hi];
+        const uint64_t x = sorted[lo], y = sorted[hi2];
         if ((x < y) == desc) {
           sorted[lo] = y;
-          sorted[hi] = x;
+          sorted[hi2] = x;
         }
       }
       wave_sync();
     }
   }
-  write_row(A, qi, sorted, nc < A.k ? nc : A.k, lane, kWave);
+  if (active) write_row(A, qi, sorted, nc < A.k ? nc : A.k, gl, G);
   wave_sync();
+}
+
+// Items [lo, hi) in groups of G lanes: wave wg of W takes the 64 / G items
+// from lo + (wg + i * W) * (64 / G) on, one per group.
+template <int S, int G>
+__device__ void group_items(const BatchArgs& A, int lo, int hi, int wg, int W, char* region) {
+  constexpr int per = kWave / G;
+  const int gi = (int)(threadIdx.x & (kWave - 1)) / G;
+  char* mine = region + (size_t)gi * 12 * (kWaveTA / per);
+  for (int base = lo + wg * per; base < hi; base += W * per)
+    group_query<S, G>(A, base + gi, hi, mine);
 }
 
 // ---- tier B: one work-group per query, LDS table ----
@@ -238,11 +269,11 @@ __global__ void __launch_bounds__(BLOCK) k_topk_batched(BatchArgs A) {
 }
 
 // ---- tier A as a kernel of its own: no block selection scratch, so more
-// waves share a CU (six work-groups of four waves); wave w of W takes the
-// A items w, w + W, ... (they are ordered longest class first, so every
-// wave gets a similar mix), with no shared queue to contend on ----
+// waves share a CU (six work-groups of four waves).  The A items are
+// ordered longest class first; each phase (64, 32, 16, then 8 lanes per
+// query) deals its items over all waves in turn, so every wave gets a
+// similar mix, with no shared queue to contend on ----
 constexpr int kWaveBlock = 256;
-constexpr int kWaveTA = 512;      // table entries per wave
 constexpr int kWaveWgsPerCu = 6;  // 6 x 24 KB of LDS per CU
 
 template <int S>
@@ -251,8 +282,11 @@ __global__ void __launch_bounds__(kWaveBlock) k_topk_waves(BatchArgs A) {
   const int w = threadIdx.x / kWave;
   char* region = lds + (size_t)w * 12 * kWaveTA;
   const int W = (int)(gridDim.x * (kWaveBlock / kWave));
-  for (int ai = (int)(blockIdx.x * (kWaveBlock / kWave)) + w; ai < A.nA; ai += W)
-    wave_query<S>(A, A.itemsA[ai], region);
+  const int wg = (int)(blockIdx.x * (kWaveBlock / kWave)) + w;
+  group_items<S, 64>(A, 0, A.nA64, wg, W, region);
+  group_items<S, 32>(A, A.nA64, A.nA32, wg, W, region);
+  group_items<S, 16>(A, A.nA32, A.nA16, wg, W, region);
+  group_items<S, 8>(A, A.nA16, A.nA, wg, W, region);
 }
 
 __global__ void k_reset_queue(uint32_t* q) {
@@ -940,6 +974,20 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
     if (tier == 0) nB = need;
   }
   for (int t = 0; t < nth; ++t) nC += cnt[t][130];
+  // tier A phases: class c (lengths below 2^c) runs in groups of G lanes
+  // when T * (2^c - 1) fits half of the group's table (kWaveTA * G / 64);
+  // the classes are in descending order, so each phase is a range
+  auto fits = [&](int c2, int G) {
+    return c2 < 32 && T * (((uint64_t)1 << c2) - 1) <= (uint64_t)(kWaveTA * G / kWave / 2);
+  };
+  size_t nA64 = 0, nA32 = 0, nA16 = 0;
+  for (int c2 = 64; c2 >= 0; --c2) {
+    size_t m = 0;
+    for (int t = 0; t < nth; ++t) m += cnt[t][65 + c2];
+    if (!fits(c2, 32)) nA64 += m;
+    if (!fits(c2, 16)) nA32 += m;
+    if (!fits(c2, 8)) nA16 += m;
+  }
   // the pinned staging of the previous plan must have been consumed
   if (b->upload_pending) {
     int st0 = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan");
@@ -1004,6 +1052,9 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   a.itemsA = b->d_items + nB;
   a.nB = (int32_t)nB;
   a.nA = (int32_t)(need - nB);
+  a.nA64 = (int32_t)nA64;
+  a.nA32 = (int32_t)nA32;
+  a.nA16 = (int32_t)nA16;
   a.inv_ptr = c->d_inv_ptr;
   a.inv_pid = c->d_inv_pid;
   a.paths = c->d_paths;
