@@ -215,6 +215,159 @@ __device__ void group_items(const BatchArgs& A, int lo, int hi, int wg, int W, c
 }
 
 // ---- tier B: one work-group per query, LDS table ----
+
+// Exact top k of a tier-B query's nc ranking keys comp[0, nc) without
+// sorting all of them.  A histogram of the counts gives the k-th best count
+// c (keys with a larger count are certainly selected); when c is shared by
+// many keys, a histogram of the top eight bits of their ids gives the digit
+// holding the one whose id ranks last among the selected (ties of a smaller
+// digit have smaller ids, so they are certainly selected too).  Only the
+// keys at or above both thresholds survive; up to kWaveSort of them are
+// sorted by one wave, with no work-group barrier.  Returns the number
+// selected, sorted descending in sm.out, or -1 when more than kFastCand
+// keys survive or k is large (the caller then runs the full selection);
+// the answer is the same either way, since the ranking key is a total
+// order.
+constexpr int kFastCand = 512;
+constexpr int kWaveSort = 128;
+template <int BLOCK>
+__device__ int select_fast(const BatchArgs& A, const uint64_t* comp, int nc, SelectSmem& sm,
+                           uint32_t* s_ctl) {
+  const int k = A.k;
+  if (2 * k > kFastCand) return -1;  // uniform
+  uint32_t* ch = sm.hist;        // 256 count bins, counts >= 255 in the last
+  uint32_t* ih = sm.hist + 256;  // 256 bins of id >> s2
+  const int lane = threadIdx.x & (kWave - 1);
+  const uint32_t n = (uint32_t)A.n;
+  const int s2 = n > 256u ? 32 - __clz((int)(n - 1u)) - 8 : 0;
+  uint32_t thr = 0u, dstar = 255u;  // every key survives
+  if (nc > kWaveSort) {
+    for (int b = threadIdx.x; b < 512; b += BLOCK) sm.hist[b] = 0u;
+    if (threadIdx.x == 0) {
+      s_ctl[1] = 0u;    // threshold count
+      s_ctl[2] = 0u;    // keys with a larger count
+      s_ctl[4] = 255u;  // id digit threshold
+      s_ctl[6] = 0u;    // ties of a smaller digit
+    }
+    __syncthreads();
+    // counts 1 and 2 (most keys) by ballots, one add per wave
+    for (int i0 = 0; i0 < nc; i0 += BLOCK) {
+      const int i = i0 + (int)threadIdx.x;
+      const uint32_t c = i < nc ? key_count(comp[i]) : 0u;
+      const uint32_t n1 = (uint32_t)__popcll(__ballot(c == 1u));
+      const uint32_t n2 = (uint32_t)__popcll(__ballot(c == 2u));
+      if (lane == 0) {
+        if (n1) atomicAdd(&ch[1], n1);
+        if (n2) atomicAdd(&ch[2], n2);
+      }
+      if (c >= 3u) atomicAdd(&ch[c < 255u ? c : 255u], 1u);
+    }
+    __syncthreads();
+    // the k-th best count (nc > k), by one wave: lane L holds bins
+    // 255 - 4L .. 252 - 4L
+    if (threadIdx.x < kWave) {
+      uint32_t hb[4], sum = 0u;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        hb[i] = ch[255 - 4 * lane - i];
+        sum += hb[i];
+      }
+      uint32_t above = wave_inclusive_sum(sum) - sum;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int bin = 255 - 4 * lane - i;
+        if (bin >= 1 && above < (uint32_t)k && above + hb[i] >= (uint32_t)k) {
+          s_ctl[1] = (uint32_t)bin;
+          s_ctl[2] = above;
+        }
+        above += hb[i];
+      }
+    }
+    __syncthreads();
+    thr = s_ctl[1];
+    const uint32_t above = s_ctl[2];
+    if (thr >= 255u) return -1;  // the k-th count is clamped: uniform
+    if (above + ch[thr] > (uint32_t)kWaveSort) {
+      for (int i = threadIdx.x; i < nc; i += BLOCK) {
+        const uint64_t x = comp[i];
+        if (key_count(x) == thr) atomicAdd(&ih[(uint32_t)key_vertex(x) >> s2], 1u);
+      }
+      __syncthreads();
+      // the digit of the (k - above)-th smallest tie id, ascending digits
+      if (threadIdx.x < kWave) {
+        const uint32_t r = (uint32_t)k - above;
+        uint32_t hb[4], sum = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          hb[i] = ih[4 * lane + i];
+          sum += hb[i];
+        }
+        uint32_t below = wave_inclusive_sum(sum) - sum;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (below < r && below + hb[i] >= r) {
+            s_ctl[4] = (uint32_t)(4 * lane + i);
+            s_ctl[6] = below;
+          }
+          below += hb[i];
+        }
+      }
+      __syncthreads();
+      dstar = s_ctl[4];
+      if (above + s_ctl[6] + ih[dstar] > (uint32_t)kFastCand) return -1;  // uniform
+    }
+  }
+  // the survivors, by ballots with one cursor add per wave
+  if (threadIdx.x == 0) s_ctl[5] = 0u;
+  __syncthreads();
+  uint64_t* cand = sm.cand;
+  for (int i0 = 0; i0 < nc; i0 += BLOCK) {
+    const int i = i0 + (int)threadIdx.x;
+    const uint64_t x = i < nc ? comp[i] : 0ull;
+    const uint32_t c = key_count(x);
+    const bool ok =
+        i < nc && (c > thr || (c == thr && ((uint32_t)key_vertex(x) >> s2) <= dstar));
+    const uint64_t bm = __ballot(ok);
+    uint32_t base = 0u;
+    if (lane == 0 && bm) base = atomicAdd(&s_ctl[5], (uint32_t)__popcll(bm));
+    base = __shfl(base, 0);
+    if (ok) cand[base + __popcll(bm & ((1ull << lane) - 1ull))] = x;
+  }
+  __syncthreads();
+  const int m = (int)s_ctl[5];
+  const int P = next_pow2(m < 2 ? 2 : m);
+  const int mk = m < k ? m : k;
+  if (P <= kWaveSort) {
+    if (threadIdx.x < kWave) {
+      for (int i = m + lane; i < P; i += kWave) cand[i] = 0ull;
+      wave_sync();
+      for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+          for (int i = lane; i < (P >> 1); i += kWave) {
+            const int lo = ((i & ~(stride - 1)) << 1) | (i & (stride - 1));
+            const int hi = lo + stride;
+            const bool desc = (lo & size) == 0;
+            const uint64_t x = cand[lo], y = cand[hi];
+            if ((x < y) == desc) {
+              cand[lo] = y;
+              cand[hi] = x;
+            }
+          }
+          wave_sync();
+        }
+      }
+      for (int i = lane; i < mk; i += kWave) sm.out[i] = cand[i];
+    }
+  } else {
+    for (int i = m + threadIdx.x; i < P; i += BLOCK) cand[i] = 0ull;
+    __syncthreads();
+    block_bitonic_desc<BLOCK>(cand, P);
+    for (int i = threadIdx.x; i < mk; i += BLOCK) sm.out[i] = cand[i];
+  }
+  __syncthreads();
+  return mk;
+}
+
 template <int BLOCK, int S>
 __device__ void block_query_lds(const BatchArgs& A, int32_t qi, char* region, SelectSmem& sm,
                                 uint32_t* s_ctl) {
@@ -235,14 +388,23 @@ __device__ void block_query_lds(const BatchArgs& A, int32_t qi, char* region, Se
   for_each_candidate<S>(A, q, a, L, threadIdx.x, BLOCK,
                         [&](int32_t v) { lds_insert(keys, vals, mask, v); });
   __syncthreads();
+  // compact: one cursor add per wave and pass (ballot ranks inside it)
+  const int lane = threadIdx.x & (kWave - 1);
   for (int j = threadIdx.x; j < TB; j += BLOCK) {
     const int32_t key = keys[j];
-    if (key >= 0) comp[atomicAdd(&s_ctl[0], 1u)] = rank_key(vals[j], key);
+    const uint64_t bm = __ballot(key >= 0);
+    uint32_t base = 0u;
+    if (lane == 0 && bm) base = atomicAdd(&s_ctl[0], (uint32_t)__popcll(bm));
+    base = __shfl(base, 0);
+    if (key >= 0) comp[base + __popcll(bm & ((1ull << lane) - 1ull))] = rank_key(vals[j], key);
   }
   __syncthreads();
   const int nc = (int)s_ctl[0];
-  auto keyfn = [&](int i) { return comp[i]; };
-  const int m = block_select_topk<BLOCK>(keyfn, nc, A.k, sm);
+  int m = select_fast<BLOCK>(A, comp, nc, sm, s_ctl);
+  if (m < 0) {
+    auto keyfn = [&](int i) { return comp[i]; };
+    m = block_select_topk<BLOCK>(keyfn, nc, A.k, sm);
+  }
   write_row(A, qi, sm.out, m, threadIdx.x, BLOCK);
   __syncthreads();
 }

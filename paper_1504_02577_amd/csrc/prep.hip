@@ -331,16 +331,29 @@ k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, uint64_t* __restrict__
   }
 }
 
-// single block: exclusive scan of the tile sums in place; total at [ntiles]
-__global__ void __launch_bounds__(1024) k_scan_tiles(uint64_t* tile_sums, int64_t ntiles) {
-  __shared__ uint64_t s[1024 / kWave + 1];
+// single block: exclusive scan of the tile sums in place; total at [ntiles].
+// 256 threads of four sums each: a 1,024-thread block found no room beside
+// a persistent kernel on another stream and waited for it to end.
+constexpr int kScanPer = 4;
+__global__ void __launch_bounds__(kBlock) k_scan_tiles(uint64_t* tile_sums, int64_t ntiles) {
+  __shared__ uint64_t s[kBlock / kWave + 1];
   uint64_t carry = 0;
-  for (int64_t base = 0; base < ntiles; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    const uint64_t x = i < ntiles ? tile_sums[i] : 0ull;
+  for (int64_t base = 0; base < ntiles; base += kBlock * kScanPer) {
+    const int64_t i0 = base + (int64_t)threadIdx.x * kScanPer;
+    uint64_t x[kScanPer];
+    uint64_t loc = 0;
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      x[j] = i0 + j < ntiles ? tile_sums[i0 + j] : 0ull;
+      loc += x[j];
+    }
     uint64_t tot;
-    const uint64_t ex = block_exclusive_sum<1024>(x, s, &tot);
-    if (i < ntiles) tile_sums[i] = carry + ex;
+    uint64_t run = carry + block_exclusive_sum<kBlock>(loc, s, &tot);
+#pragma unroll
+    for (int j = 0; j < kScanPer; ++j) {
+      if (i0 + j < ntiles) tile_sums[i0 + j] = run;
+      run += x[j];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) tile_sums[ntiles] = carry;
@@ -469,7 +482,7 @@ void launch_scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, void* 
   if (tiles < 1) tiles = 1;
   uint64_t* ts = static_cast<uint64_t*>(temp);
   k_scan_reduce<<<(unsigned)tiles, kBlock, 0, s>>>(in, n, ts);
-  k_scan_tiles<<<1, 1024, 0, s>>>(ts, tiles);
+  k_scan_tiles<<<1, kBlock, 0, s>>>(ts, tiles);
   k_scan_apply<<<(unsigned)tiles, kBlock, 0, s>>>(in, n, ts, out);
 }
 
