@@ -167,7 +167,7 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * keeps it in the text file $PANTHER_TUNE_CACHE (default
  * $HOME/.cache/panther_tune.txt); forcing any of them turns it off.
  * "test.hub_budget" (bytes of hub staging per
- * chunk of the batched form, 0 = automatic: min(8 GiB, free / 4), at least
+ * chunk of the batched form, 0 = automatic: min(16 GiB, free / 4), at least
  * 256 MiB; a small value splits the hub queries into many chunks, for
  * tests), "test.pp_recompute_all" (0..2, default 0;
  * 1: the BF16 form recomputes every query whose pool is full by the exact

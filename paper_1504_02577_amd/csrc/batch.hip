@@ -552,7 +552,6 @@ struct BatchState {
   size_t cand_n_cap = 0;
   char* d_scan = nullptr;
   size_t scan_cap = 0;
-  std::vector<HubQuery> h_hq;
   // page-locked staging of the plan; `uploaded` guards its reuse
   PinnedBuf pin_items, pin_hq;
   hipEvent_t uploaded = nullptr;
@@ -898,13 +897,18 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
                      const int32_t* dq, int32_t k, int bias, int32_t* d_ids, uint32_t* d_counts,
                      int32_t* d_len, float* theta, hipStream_t s, std::vector<HubArgs>* out) {
   out->clear();
-  b->h_hq.clear();
   if (C.empty()) return PANTHER_OK;
   const uint64_t T = (uint64_t)c->T;
+  // the plan is written straight into the pinned upload buffer (the
+  // previous plan's upload has completed: plan waits for it)
+  int st;
+  if ((st = pinned_ensure(c, b->pin_hq, sizeof(HubQuery) * C.size(), "hub plan"))) return st;
+  HubQuery* hq = static_cast<HubQuery*>(b->pin_hq.p);
+  size_t nhq = 0;
   if (!b->hub_budget) {
     size_t free_b = 0, total_b = 0;
     (void)hipMemGetInfo(&free_b, &total_b);
-    b->hub_budget = std::max<size_t>(std::min((size_t)8 << 30, free_b / 4), (size_t)1 << 28);
+    b->hub_budget = std::max<size_t>(std::min((size_t)16 << 30, free_b / 4), (size_t)1 << 28);
   }
   // staging bytes per occurrence slot: row order, bucket order
   const size_t budget = b->hub_budget_forced ? b->hub_budget_forced : b->hub_budget;
@@ -931,7 +935,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     max_occ = std::max(max_occ, cur.occ);
     max_cand = std::max(max_cand, cur.cand);
     max_ths = std::max(max_ths, cur.ths);
-    cur = Chunk{b->h_hq.size(), 0, 0, 0, 0, 0, 0, 0};
+    cur = Chunk{nhq, 0, 0, 0, 0, 0, 0, 0};
   };
   for (const auto& x : C) {
     const uint64_t L = x.first;
@@ -954,7 +958,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     h.occ0 = cur.occ;
     h.cand0 = cur.cand;
     h.th0 = (uint32_t)cur.ths;
-    b->h_hq.push_back(h);
+    hq[nhq++] = h;
     cur.nq += 1;
     cur.tiles += tiles;
     cur.stiles += stiles;
@@ -964,8 +968,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     cur.ths += (uint64_t)stiles * nb;
   }
   close();
-  int st;
-  if ((st = grow(c, b->d_hq, b->hq_cap, b->h_hq.size(), sizeof(HubQuery), "hub plan"))) return st;
+  if ((st = grow(c, b->d_hq, b->hq_cap, nhq, sizeof(HubQuery), "hub plan"))) return st;
   if ((st = grow(c, b->d_stA, b->occ_cap, max_occ, sizeof(int32_t), "hub staging"))) return st;
   if ((st = grow(c, b->d_stB, b->occB_cap, max_occ, sizeof(int32_t), "hub staging"))) return st;
   if ((st = grow(c, b->d_bkt_cnt, b->bkt_cap, max_bkt, sizeof(uint32_t), "hub buckets"))) return st;
@@ -993,10 +996,7 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
     return st;
   if ((st = grow(c, b->d_th, b->th_cap, max_ths, sizeof(uint32_t), "hub tile counts")))
     return st;
-  if ((st = pinned_ensure(c, b->pin_hq, sizeof(HubQuery) * b->h_hq.size(), "hub plan")))
-    return st;
-  std::memcpy(b->pin_hq.p, b->h_hq.data(), sizeof(HubQuery) * b->h_hq.size());
-  st = ctx_hip(c, hipMemcpyAsync(b->d_hq, b->pin_hq.p, sizeof(HubQuery) * b->h_hq.size(),
+  st = ctx_hip(c, hipMemcpyAsync(b->d_hq, b->pin_hq.p, sizeof(HubQuery) * nhq,
                                  hipMemcpyHostToDevice, s),
                "hub plan upload");
   if (st) return st;
@@ -1043,6 +1043,10 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
 // length's 11-bit digits, complemented so that longer lists come first:
 // linear in the number of hubs (a comparison sort of the tens of thousands
 // of hubs of an R-MAT 24 batch took milliseconds of host time).
+// Large sets split each pass over host threads: thread t takes a
+// contiguous range, and its run of digit d starts after every earlier
+// thread's run of d (positions are prefix sums in (digit, thread) order), so
+// the result is the one-thread order.
 static void sort_hubs_longest_first(std::vector<std::pair<uint64_t, int32_t>>& C,
                                     std::vector<std::pair<uint64_t, int32_t>>& tmp) {
   if (C.size() < 2) return;
@@ -1052,17 +1056,35 @@ static void sort_hubs_longest_first(std::vector<std::pair<uint64_t, int32_t>>& C
   constexpr int kDigit = 11;
   constexpr uint64_t kMask = (1u << kDigit) - 1u;
   tmp.resize(C.size());
-  std::vector<uint32_t> pos(kMask + 1);
+  const size_t n = C.size();
+  const int nth = n >= ((size_t)1 << 16) ? 8 : 1;
+  std::vector<std::vector<size_t>> pos(nth, std::vector<size_t>(kMask + 1));
+  auto lo_of = [&](int t) { return n * (size_t)t / (size_t)nth; };
+  auto in_threads = [&](auto&& fn) {
+    std::vector<std::thread> th;
+    for (int t = 1; t < nth; ++t) th.emplace_back(fn, t);
+    fn(0);
+    for (auto& x : th) x.join();
+  };
   for (int sh = 0; sh < bits; sh += kDigit) {
-    std::fill(pos.begin(), pos.end(), 0u);
-    for (const auto& x : C) ++pos[kMask - ((x.first >> sh) & kMask)];
-    uint32_t run = 0;
-    for (uint32_t& p : pos) {
-      const uint32_t c = p;
-      p = run;
-      run += c;
-    }
-    for (const auto& x : C) tmp[pos[kMask - ((x.first >> sh) & kMask)]++] = x;
+    in_threads([&](int t) {
+      auto& pt = pos[t];
+      std::fill(pt.begin(), pt.end(), (size_t)0);
+      for (size_t i = lo_of(t), e = lo_of(t + 1); i < e; ++i)
+        ++pt[kMask - ((C[i].first >> sh) & kMask)];
+    });
+    size_t run = 0;
+    for (uint64_t d = 0; d <= kMask; ++d)
+      for (int t = 0; t < nth; ++t) {
+        const size_t c = pos[t][d];
+        pos[t][d] = run;
+        run += c;
+      }
+    in_threads([&](int t) {
+      auto& pt = pos[t];
+      for (size_t i = lo_of(t), e = lo_of(t + 1); i < e; ++i)
+        tmp[pt[kMask - ((C[i].first >> sh) & kMask)]++] = C[i];
+    });
     C.swap(tmp);
   }
 }
@@ -1091,7 +1113,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   // contiguous range of queries; positions are prefix sums over (tier,
   // class, thread), so the order is the same as one thread's).
   auto cls = [](uint64_t L) { return L ? 64 - __builtin_clzll(L) : 0; };
-  const int nth = nq >= (int64_t)1 << 20 ? 8 : 1;
+  const int nth = nq >= (int64_t)1 << 22 ? 16 : (nq >= (int64_t)1 << 20 ? 8 : 1);
   std::vector<std::array<size_t, 131>> cnt(nth);  // [tier 0: 0..64, tier 1: 65..129, hubs: 130]
   auto range = [&](int t, int64_t& lo, int64_t& hi) {
     lo = nq * t / nth;
