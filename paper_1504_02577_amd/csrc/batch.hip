@@ -451,6 +451,38 @@ __global__ void __launch_bounds__(kWaveBlock) k_topk_waves(BatchArgs A) {
   group_items<S, 8>(A, A.nA16, A.nA, wg, W, region);
 }
 
+// ---- device planning of large batches ----
+// Digit of query i in the plan's order: tier B classes 64..0 (digits
+// 0..64), tier A classes 64..0 (65..129), then the hubs (130); a stable
+// sort by digit gives the host planner's order.  Also writes the pair count
+// the sort reads and the query index as the sort's value.
+constexpr uint32_t kHubDigit = 130;
+__global__ void k_plan_digits(const uint64_t* __restrict__ qlen, int64_t nq, uint64_t LA,
+                              uint64_t LB, uint32_t* __restrict__ keys,
+                              uint32_t* __restrict__ vals, uint64_t* __restrict__ nnz) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *nnz = (uint64_t)nq;
+  if (i >= nq) return;
+  const uint64_t L = qlen[i];
+  const uint32_t cl = L ? 64u - (uint32_t)__clzll((long long)L) : 0u;
+  keys[i] = L > LB ? kHubDigit : (L > LA ? 0u : 65u) + (64u - cl);
+  vals[i] = (uint32_t)i;
+}
+
+// starts[d] = first position of digit d in the sorted order, d = 0..131
+// (offsets are the digit-major exclusive scan of the tile counts).
+__global__ void k_plan_starts(const uint64_t* __restrict__ offs, uint64_t ntiles,
+                              uint64_t* __restrict__ starts) {
+  const uint32_t d = threadIdx.x;
+  if (d <= kHubDigit + 1) starts[d] = offs[(uint64_t)d * ntiles];
+}
+
+__global__ void k_plan_hub_lengths(const int32_t* __restrict__ idx, int64_t n,
+                                   const uint64_t* __restrict__ qlen, uint64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = qlen[idx[i]];
+}
+
 __global__ void k_reset_queue(uint32_t* q) {
   if (threadIdx.x < kQueueCtl) q[threadIdx.x] = 0u;
 }
@@ -554,6 +586,23 @@ struct BatchState {
   size_t scan_cap = 0;
   // page-locked staging of the plan; `uploaded` guards its reuse
   PinnedBuf pin_items, pin_hq;
+  // device planning of large batches: digit keys, the sort's scratch, the
+  // digit starts and the hubs' lengths (and their pinned copies)
+  uint32_t* dp_keys = nullptr;
+  uint32_t* dp_keys2 = nullptr;
+  uint32_t* dp_vals = nullptr;
+  size_t dp_cap = 0, dp_keys2_cap = 0, dp_vals_cap = 0;
+  uint32_t* dp_hist = nullptr;
+  size_t dp_hist_cap = 0;
+  uint64_t* dp_offs = nullptr;
+  size_t dp_offs_cap = 0;
+  char* dp_scan = nullptr;
+  size_t dp_scan_cap = 0;
+  uint64_t* dp_small = nullptr;  // [0]: the pair count, [1, 133): digit starts
+  size_t dp_small_cap = 0;
+  uint64_t* dp_hubL = nullptr;
+  size_t dp_hubL_cap = 0;
+  PinnedBuf pin_starts, pin_hubL, pin_hubI;
   hipEvent_t uploaded = nullptr;
   bool upload_pending = false;
   // second stream: the hub pipeline runs beside the persistent kernel
@@ -628,6 +677,12 @@ void free_batch_state(Lane* lane) {
   if (b->side) (void)hipStreamDestroy(b->side);
   pinned_release(b->pin_items);
   pinned_release(b->pin_hq);
+  pinned_release(b->pin_starts);
+  pinned_release(b->pin_hubL);
+  pinned_release(b->pin_hubI);
+  for (void* p : {(void*)b->dp_keys, (void*)b->dp_keys2, (void*)b->dp_vals, (void*)b->dp_hist,
+                  (void*)b->dp_offs, (void*)b->dp_scan, (void*)b->dp_small, (void*)b->dp_hubL})
+    ctx_free(p);
   ctx_free(b->d_items);
   ctx_free(b->d_queue);
   for (void* p : {(void*)b->d_hq, (void*)b->d_stA, (void*)b->d_stB, (void*)b->d_bkt_cnt,
@@ -1089,10 +1144,84 @@ static void sort_hubs_longest_first(std::vector<std::pair<uint64_t, int32_t>>& C
   }
 }
 
+// Device planning of a large batch: the digits of k_plan_digits sorted by
+// one stable pass of the index's radix sort (8-bit digit, query index as
+// the value) straight into d_items, so the tier items need no host pass and
+// no upload.  Only the digit starts and the hubs' lengths come back.
+// Fills nB, need (tier items), cntA (tier A items per length class) and C
+// (the hubs, in batch order).
+bool batched_plan_on_device(int64_t nq) { return nq >= ((int64_t)1 << 20); }
+
+static int plan_on_device(panther_ctx* c, BatchState* b, const uint64_t* dqlen, int64_t nq,
+                          uint64_t LA, uint64_t LB, hipStream_t s, bool with_hubs, size_t* nB,
+                          size_t* need, std::array<size_t, 65>& cntA,
+                          std::vector<std::pair<uint64_t, int32_t>>* C) {
+  const uint64_t n = (uint64_t)nq;
+  const uint64_t ntiles = radix_tiles_pairs(n);
+  const size_t nh = (size_t)256 * ntiles;
+  constexpr size_t kStarts = kHubDigit + 2;
+  int st;
+  if ((st = grow(c, b->dp_keys, b->dp_cap, n, sizeof(uint32_t), "batch plan")) ||
+      (st = grow(c, b->dp_keys2, b->dp_keys2_cap, n, sizeof(uint32_t), "batch plan")) ||
+      (st = grow(c, b->dp_vals, b->dp_vals_cap, n, sizeof(uint32_t), "batch plan")) ||
+      (st = grow(c, b->d_items, b->items_cap, std::max<size_t>(n, 1024), sizeof(int32_t),
+                 "batch plan")) ||
+      (st = grow(c, b->dp_hist, b->dp_hist_cap, nh, sizeof(uint32_t), "batch plan")) ||
+      (st = grow(c, b->dp_offs, b->dp_offs_cap, nh + 1, sizeof(uint64_t), "batch plan")) ||
+      (st = grow(c, b->dp_scan, b->dp_scan_cap, scan_temp_bytes((int64_t)nh), 1, "batch plan")) ||
+      (st = grow(c, b->dp_small, b->dp_small_cap, 1 + kStarts, sizeof(uint64_t), "batch plan")) ||
+      (st = pinned_ensure(c, b->pin_starts, sizeof(uint64_t) * kStarts, "batch plan")))
+    return st;
+  uint64_t* d_nnz = b->dp_small;
+  uint64_t* d_starts = b->dp_small + 1;
+  k_plan_digits<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dqlen, nq, LA, LB, b->dp_keys,
+                                                            b->dp_vals, d_nnz);
+  launch_radix_up_pairs(b->dp_keys, d_nnz, n, 0, 8, b->dp_hist, s);
+  launch_scan_u32_to_u64(b->dp_hist, b->dp_offs, (int64_t)nh, b->dp_scan, s);
+  launch_radix_down_pairs(b->dp_keys, b->dp_vals, d_nnz, n, 0, 8, b->dp_offs, b->dp_keys2,
+                          reinterpret_cast<uint32_t*>(b->d_items), s);
+  k_plan_starts<<<1, 256, 0, s>>>(b->dp_offs, ntiles, d_starts);
+  if ((st = ctx_hip(c, hipGetLastError(), "batch plan")) ||
+      (st = ctx_hip(c, hipMemcpyAsync(b->pin_starts.p, d_starts, sizeof(uint64_t) * kStarts,
+                                      hipMemcpyDeviceToHost, s),
+                    "batch plan")) ||
+      (st = ctx_hip(c, hipStreamSynchronize(s), "batch plan")))
+    return st;
+  const uint64_t* sp = static_cast<const uint64_t*>(b->pin_starts.p);
+  *nB = (size_t)sp[65];
+  *need = (size_t)sp[kHubDigit];
+  for (int c2 = 0; c2 <= 64; ++c2) cntA[c2] = (size_t)(sp[65 + (64 - c2) + 1] - sp[65 + (64 - c2)]);
+  const size_t nC = (size_t)(sp[kHubDigit + 1] - sp[kHubDigit]);
+  C->clear();
+  if (!with_hubs || !nC) return PANTHER_OK;
+  const int32_t* hub_idx = b->d_items + sp[kHubDigit];
+  if ((st = grow(c, b->dp_hubL, b->dp_hubL_cap, nC, sizeof(uint64_t), "batch plan")) ||
+      (st = pinned_ensure(c, b->pin_hubL, sizeof(uint64_t) * nC, "batch plan")) ||
+      (st = pinned_ensure(c, b->pin_hubI, sizeof(int32_t) * nC, "batch plan")))
+    return st;
+  k_plan_hub_lengths<<<(unsigned)((nC + 255) / 256), 256, 0, s>>>(hub_idx, (int64_t)nC, dqlen,
+                                                                  b->dp_hubL);
+  if ((st = ctx_hip(c, hipGetLastError(), "batch plan")) ||
+      (st = ctx_hip(c, hipMemcpyAsync(b->pin_hubL.p, b->dp_hubL, sizeof(uint64_t) * nC,
+                                      hipMemcpyDeviceToHost, s),
+                    "batch plan")) ||
+      (st = ctx_hip(c, hipMemcpyAsync(b->pin_hubI.p, hub_idx, sizeof(int32_t) * nC,
+                                      hipMemcpyDeviceToHost, s),
+                    "batch plan")) ||
+      (st = ctx_hip(c, hipStreamSynchronize(s), "batch plan")))
+    return st;
+  const uint64_t* hl = static_cast<const uint64_t*>(b->pin_hubL.p);
+  const int32_t* hi = static_cast<const int32_t*>(b->pin_hubI.p);
+  C->resize(nC);
+  for (size_t i = 0; i < nC; ++i) (*C)[i] = {hl[i], hi[i]};
+  return PANTHER_OK;
+}
+
 // Builds the plan for one configuration.  With `with_hubs` false the hub
 // queries are left out (the autotuner times the persistent kernel alone).
+// qlen == nullptr: the batch is planned on the device from dqlen.
 static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int32_t* dq,
-                const uint64_t* qlen, int64_t nq, int32_t k, int32_t* d_ids,
+                const uint64_t* qlen, const uint64_t* dqlen, int64_t nq, int32_t k, int32_t* d_ids,
                 uint32_t* d_counts, int32_t* d_len, float* theta, hipStream_t s, bool with_hubs,
                 Plan* out, std::vector<int32_t>* host_items) {
   const Layout lay = layout_for(c, cfg);
@@ -1113,51 +1242,92 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   // contiguous range of queries; positions are prefix sums over (tier,
   // class, thread), so the order is the same as one thread's).
   auto cls = [](uint64_t L) { return L ? 64 - __builtin_clzll(L) : 0; };
-  const int nth = nq >= (int64_t)1 << 22 ? 16 : (nq >= (int64_t)1 << 20 ? 8 : 1);
-  std::vector<std::array<size_t, 131>> cnt(nth);  // [tier 0: 0..64, tier 1: 65..129, hubs: 130]
-  auto range = [&](int t, int64_t& lo, int64_t& hi) {
-    lo = nq * t / nth;
-    hi = nq * (t + 1) / nth;
-  };
-  auto count_part = [&](int t) {
-    auto& ct = cnt[t];
-    ct.fill(0);
-    int64_t lo, hi;
-    range(t, lo, hi);
-    for (int64_t i = lo; i < hi; ++i) {
-      const uint64_t L = qlen[i];
-      if (L > LB)
-        ++ct[130];
-      else
-        ++ct[(L > LA ? 0 : 65) + cls(L)];  // tier 0: work-group (B), 1: wave (A)
-    }
-  };
-  auto run_parts = [&](auto&& fn) {
-    if (nth == 1) {
-      fn(0);
-      return;
-    }
-    std::vector<std::thread> th;
-    for (int t = 1; t < nth; ++t) th.emplace_back(fn, t);
-    fn(0);
-    for (auto& x : th) x.join();
-  };
-  run_parts(count_part);
-  // start of each (bucket, thread): buckets in order tier 0 classes 64..0,
-  // tier 1 classes 64..0
-  std::vector<std::array<size_t, 130>> pos(nth);
-  size_t nB = 0, need = 0, nC = 0;
-  for (int tier = 0; tier < 2; ++tier) {
-    for (int c2 = 64; c2 >= 0; --c2) {
-      const int bk = tier * 65 + c2;
-      for (int t = 0; t < nth; ++t) {
-        pos[t][bk] = need;
-        need += cnt[t][bk];
+  std::array<size_t, 65> cntA{};  // tier A items per length class
+  size_t nB = 0, need = 0;
+  std::vector<std::pair<uint64_t, int32_t>> C;
+  int st;
+  const bool on_device = qlen == nullptr;
+  if (on_device) {
+    if ((st = plan_on_device(c, b, dqlen, nq, LA, LB, s, with_hubs, &nB, &need, cntA, &C)))
+      return st;
+  } else {
+    const int nth = nq >= (int64_t)1 << 22 ? 16 : (nq >= (int64_t)1 << 20 ? 8 : 1);
+    std::vector<std::array<size_t, 131>> cnt(nth);  // [tier 0: 0..64, tier 1: 65..129, hubs: 130]
+    auto range = [&](int t, int64_t& lo, int64_t& hi) {
+      lo = nq * t / nth;
+      hi = nq * (t + 1) / nth;
+    };
+    auto count_part = [&](int t) {
+      auto& ct = cnt[t];
+      ct.fill(0);
+      int64_t lo, hi;
+      range(t, lo, hi);
+      for (int64_t i = lo; i < hi; ++i) {
+        const uint64_t L = qlen[i];
+        if (L > LB)
+          ++ct[130];
+        else
+          ++ct[(L > LA ? 0 : 65) + cls(L)];  // tier 0: work-group (B), 1: wave (A)
       }
+    };
+    auto run_parts = [&](auto&& fn) {
+      if (nth == 1) {
+        fn(0);
+        return;
+      }
+      std::vector<std::thread> th;
+      for (int t = 1; t < nth; ++t) th.emplace_back(fn, t);
+      fn(0);
+      for (auto& x : th) x.join();
+    };
+    run_parts(count_part);
+    // start of each (bucket, thread): buckets in order tier 0 classes 64..0,
+    // tier 1 classes 64..0
+    std::vector<std::array<size_t, 130>> pos(nth);
+    size_t nC = 0;
+    for (int tier = 0; tier < 2; ++tier) {
+      for (int c2 = 64; c2 >= 0; --c2) {
+        const int bk = tier * 65 + c2;
+        for (int t = 0; t < nth; ++t) {
+          pos[t][bk] = need;
+          need += cnt[t][bk];
+        }
+      }
+      if (tier == 0) nB = need;
     }
-    if (tier == 0) nB = need;
+    for (int t = 0; t < nth; ++t) nC += cnt[t][130];
+    for (int c2 = 0; c2 <= 64; ++c2)
+      for (int t = 0; t < nth; ++t) cntA[c2] += cnt[t][65 + c2];
+    // the pinned staging of the previous plan must have been consumed
+    if (b->upload_pending) {
+      if ((st = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan"))) return st;
+      b->upload_pending = false;
+    }
+    if (need && (st = pinned_ensure(c, b->pin_items, sizeof(int32_t) * need, "batch plan")))
+      return st;
+    int32_t* items = static_cast<int32_t*>(b->pin_items.p);
+    if (with_hubs) C.resize(nC);
+    std::vector<size_t> cpos(nth);
+    for (int t = 0, run = 0; t < nth; ++t) {
+      cpos[t] = run;
+      run += (int)cnt[t][130];
+    }
+    auto scatter_part = [&](int t) {
+      auto& pt = pos[t];
+      size_t cp = cpos[t];
+      int64_t lo, hi;
+      range(t, lo, hi);
+      for (int64_t i = lo; i < hi; ++i) {
+        const uint64_t L = qlen[i];
+        if (L > LB) {
+          if (with_hubs) C[cp++] = {L, (int32_t)i};
+        } else {
+          items[pt[(L > LA ? 0 : 65) + cls(L)]++] = (int32_t)i;
+        }
+      }
+    };
+    run_parts(scatter_part);
   }
-  for (int t = 0; t < nth; ++t) nC += cnt[t][130];
   // tier A phases: class c (lengths below 2^c) runs in groups of G lanes
   // when T * (2^c - 1) fits half of the group's table (kWaveTA * G / 64);
   // the classes are in descending order, so each phase is a range
@@ -1166,49 +1336,22 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   };
   size_t nA64 = 0, nA32 = 0, nA16 = 0;
   for (int c2 = 64; c2 >= 0; --c2) {
-    size_t m = 0;
-    for (int t = 0; t < nth; ++t) m += cnt[t][65 + c2];
+    const size_t m = cntA[c2];
     if (!fits(c2, 32)) nA64 += m;
     if (!fits(c2, 16)) nA32 += m;
     if (!fits(c2, 8)) nA16 += m;
   }
-  // the pinned staging of the previous plan must have been consumed
+  // the pinned hub plan of the previous call must have been consumed too
   if (b->upload_pending) {
-    int st0 = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan");
-    if (st0) return st0;
+    if ((st = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan"))) return st;
     b->upload_pending = false;
   }
-  int st;
-  if (need && (st = pinned_ensure(c, b->pin_items, sizeof(int32_t) * need, "batch plan")))
-    return st;
-  int32_t* items = static_cast<int32_t*>(b->pin_items.p);
-  std::vector<std::pair<uint64_t, int32_t>> C;
-  if (with_hubs) C.resize(nC);
-  std::vector<size_t> cpos(nth);
-  for (int t = 0, run = 0; t < nth; ++t) {
-    cpos[t] = run;
-    run += (int)cnt[t][130];
-  }
-  auto scatter_part = [&](int t) {
-    auto& pt = pos[t];
-    size_t cp = cpos[t];
-    int64_t lo, hi;
-    range(t, lo, hi);
-    for (int64_t i = lo; i < hi; ++i) {
-      const uint64_t L = qlen[i];
-      if (L > LB) {
-        if (with_hubs) C[cp++] = {L, (int32_t)i};
-      } else {
-        items[pt[(L > LA ? 0 : 65) + cls(L)]++] = (int32_t)i;
-      }
-    }
-  };
-  run_parts(scatter_part);
   sort_hubs_longest_first(C, b->hub_sort_tmp);
   st = plan_hubs(c, b, C, dq, k, cfg.bucket_bias, d_ids, d_counts, d_len, theta, s, &out->hub);
   if (st) return st;
   host_items->clear();
-  if ((st = grow(c, b->d_items, b->items_cap, std::max<size_t>(need, 1024), sizeof(int32_t),
+  if (!on_device &&
+      (st = grow(c, b->d_items, b->items_cap, std::max<size_t>(need, 1024), sizeof(int32_t),
                  "batch plan")))
     return st;
   if (!b->d_queue) {
@@ -1217,7 +1360,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
     if (st) return st;
     b->d_queue = static_cast<uint32_t*>(p);
   }
-  if (need) {
+  if (!on_device && need) {
     st = ctx_hip(c, hipMemcpyAsync(b->d_items, b->pin_items.p, sizeof(int32_t) * need,
                                    hipMemcpyHostToDevice, s),
                  "batch plan upload");
@@ -1316,6 +1459,8 @@ size_t lane_device_bytes(const Lane* lane) {
   t += sizeof(HubList) * b->hx_cap + b->scan_cap;
   t += sizeof(int32_t) * (b->tile_owner_cap + b->stile_owner_cap + b->bkt_owner_cap);
   t += sizeof(uint32_t) * b->th_cap;
+  t += sizeof(uint32_t) * (b->dp_cap + b->dp_keys2_cap + b->dp_vals_cap + b->dp_hist_cap);
+  t += sizeof(uint64_t) * (b->dp_offs_cap + b->dp_small_cap + b->dp_hubL_cap) + b->dp_scan_cap;
   return t;
 }
 
@@ -1325,6 +1470,7 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
   BatchState* b = state(lane);
   std::vector<int32_t> items;
   Plan args;
+  const uint64_t* dqlen = static_cast<const uint64_t*>(lane->b_qlen.p);
   // configuration: forced, cached, autotuned, or the default
   if (b->forced_block || b->forced_wgs || b->forced_div || b->forced_bias >= 0) {
     BatchConfig f;
@@ -1360,6 +1506,20 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
       // kStage2MaxQueries queries, times the whole call for each (tier B
       // divisor, bucket bias).  Each candidate
       // runs once to warm up and is then timed twice (the faster counts).
+      // the tuner plans prefixes on the host: a batch planned on the device
+      // brings back the lengths of the prefix it times
+      const int64_t m = std::min<int64_t>(nq, 16384);
+      const uint64_t* tq = qlen;
+      if (!tq) {
+        int st0 = pinned_ensure(c, lane->h_qlen, sizeof(uint64_t) * (size_t)m, "autotune");
+        if (!st0)
+          st0 = ctx_hip(c, hipMemcpyAsync(lane->h_qlen.p, dqlen, sizeof(uint64_t) * (size_t)m,
+                                          hipMemcpyDeviceToHost, s),
+                        "autotune");
+        if (!st0) st0 = ctx_hip(c, hipStreamSynchronize(s), "autotune");
+        if (st0) return st0;
+        tq = static_cast<const uint64_t*>(lane->h_qlen.p);
+      }
       hipEvent_t e0, e1;
       int st = ctx_hip(c, hipEventCreate(&e0), "autotune");
       if (st) return st;
@@ -1369,8 +1529,8 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
         return st;
       }
       auto time_cfg = [&](const BatchConfig& cfg, int64_t m, bool hubs, float* ms_out) -> int {
-        int r = plan(c, b, cfg, dq, qlen, m, k, d_ids, d_counts, d_len, theta, s, hubs, &args,
-                     &items);
+        int r = plan(c, b, cfg, dq, hubs ? qlen : tq, dqlen, m, k, d_ids, d_counts, d_len, theta,
+                     s, hubs, &args, &items);
         if (r) return r;
         float best_ms = 1e30f;
         for (int rep = 0; rep < 3; ++rep) {
@@ -1387,7 +1547,6 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
       };
       BatchConfig best_cfg{};
       float best = 1e30f;
-      const int64_t m = std::min<int64_t>(nq, 16384);
       for (int blk : kBlocks)
         for (int wgs : kWgs) {
           const BatchConfig cfg{blk, wgs, 1, 0};
@@ -1407,8 +1566,9 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
         // large, such as a feature pass over every vertex, that one call
         // already takes long)
         bool near_hubs = false;
-        for (int64_t i = 0; i < nq && !near_hubs; ++i) near_hubs = qlen[i] > lo;
-        if (near_hubs && nq <= kStage2MaxQueries) {
+        if (nq <= kStage2MaxQueries)  // (qlen is on the host for such batches)
+          for (int64_t i = 0; i < nq && !near_hubs; ++i) near_hubs = qlen[i] > lo;
+        if (near_hubs) {
           best = 1e30f;
           const BatchConfig base = best_cfg;
           for (int div : kTierBDivs)
@@ -1434,8 +1594,8 @@ int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* q
       b->tuned = true;
     }
   }
-  int st = plan(c, b, b->cfg, dq, qlen, nq, k, d_ids, d_counts, d_len, theta, s, true, &args,
-                &items);
+  int st = plan(c, b, b->cfg, dq, qlen, dqlen, nq, k, d_ids, d_counts, d_len, theta, s, true,
+                &args, &items);
   if (st) return st;
   // the plan's pinned staging is guarded by b->uploaded; nothing here waits
   return launch_batched(c, b, b->cfg, args, s, true);

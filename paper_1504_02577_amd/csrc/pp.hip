@@ -63,7 +63,7 @@ int ensure_features(panther_ctx* c, int32_t D, hipStream_t s) {
   k_iota<<<(unsigned)((c->n + 255) / 256), 256, 0, s>>>(ids, c->n);
   HIPTRY(hipGetLastError(), "features");
   const uint64_t* qlen = nullptr;
-  TRY(query_lengths(c, &c->lane0, ids, c->n, s, &qlen));
+  TRY(query_lengths(c, &c->lane0, ids, c->n, s, &qlen, !batched_plan_on_device(c->n)));
   stage_begin(c, 3, s);
   TRY(run_batched(c, &c->lane0, ids, qlen, c->n, D, nullptr, nullptr, nullptr, c->d_theta, s));
   stage_end(c, 3, s);

@@ -127,10 +127,11 @@ int ctx_ensure(panther_ctx* c, DevBuf& b, size_t bytes, const char* what);
 void ctx_release(DevBuf& b);
 int pinned_ensure(panther_ctx* c, PinnedBuf& b, size_t bytes, const char* what);
 void pinned_release(PinnedBuf& b);
-// Path-list lengths of the queries, gathered on the device and copied back
-// to the lane's pinned buffer (*len points there until the lane's next call).
+// Path-list lengths of the queries, gathered on the device into the lane's
+// b_qlen and, with to_host, copied back to its pinned buffer (*len points
+// there until the lane's next call; nullptr without to_host).
 int query_lengths(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, hipStream_t s,
-                  const uint64_t** len);
+                  const uint64_t** len, bool to_host = true);
 void ctx_free(void* p);
 // Stage timing: stage i is bracketed by events 2i and 2i+1.
 void stage_begin(panther_ctx* c, int stage, hipStream_t s);
@@ -142,7 +143,10 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
 
 // batched form (batch.hip).  With theta != nullptr the pass writes Panther++
 // feature rows (k = D) instead of ids/counts.
-// Enqueues the work on s; returns without waiting for it.
+// Enqueues the work on s; returns without waiting for it.  qlen are the
+// lengths on the host, or nullptr for a batch that batched_plan_on_device
+// accepts: it is then planned from the lane's device lengths (b_qlen).
+bool batched_plan_on_device(int64_t nq);
 int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* qlen, int64_t nq,
                 int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
                 hipStream_t s);

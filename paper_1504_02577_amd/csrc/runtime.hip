@@ -721,12 +721,16 @@ void free_lane(Lane* lane) {
 }
 
 int query_lengths(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, hipStream_t s,
-                  const uint64_t** len) {
+                  const uint64_t** len, bool to_host) {
   const size_t bytes = sizeof(uint64_t) * (size_t)std::max<int64_t>(nq, 1);
   TRY(ctx_ensure(c, lane->b_qlen, bytes, "query lengths"));
-  TRY(pinned_ensure(c, lane->h_qlen, bytes, "query lengths"));
   launch_query_lengths(c->d_inv_ptr, dq, nq, static_cast<uint64_t*>(lane->b_qlen.p), s);
   HIPTRY(hipGetLastError(), "query lengths");
+  if (!to_host) {
+    *len = nullptr;
+    return PANTHER_OK;
+  }
+  TRY(pinned_ensure(c, lane->h_qlen, bytes, "query lengths"));
   HIPTRY(hipMemcpyAsync(lane->h_qlen.p, lane->b_qlen.p, sizeof(uint64_t) * (size_t)nq,
                         hipMemcpyDeviceToHost, s),
          "query lengths");
@@ -771,7 +775,7 @@ extern "C" int panther_topk_all(panther_ctx* c, int32_t k, int32_t* out_ids, uin
   launch_iota(ids, (int32_t)n, s);
   HIPTRY(hipGetLastError(), "vertex ids");
   const uint64_t* qlen = nullptr;
-  TRY(query_lengths(c, &c->lane0, ids, n, s, &qlen));
+  TRY(query_lengths(c, &c->lane0, ids, n, s, &qlen, !batched_plan_on_device(n)));
   TRY(run_batched(c, &c->lane0, ids, qlen, n, k, d_ids, d_cnt, d_len, nullptr, s));
   stage_end(c, 2, s);
   TRY(order_end(c, s));
@@ -830,7 +834,8 @@ extern "C" int panther_topk_similar(panther_ctx* c, const int32_t* queries, int6
   TRY(order_begin(c, s));
   stage_begin(c, 2, s);
   const uint64_t* qlen = nullptr;
-  TRY(query_lengths(c, &c->lane0, dq, nq, s, &qlen));
+  TRY(query_lengths(c, &c->lane0, dq, nq, s, &qlen,
+                    c->topk_form == PANTHER_FORM_PLAIN || !batched_plan_on_device(nq)));
   if (c->topk_form == PANTHER_FORM_PLAIN) {
     TopkScratch sc{c->d_cnt, c->d_touched, c->d_ctl};
     for (int64_t i = 0; i < nq; ++i) {

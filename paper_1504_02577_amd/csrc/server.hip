@@ -182,7 +182,7 @@ static void run_batch(panther_server* sv, LaneWorker* w, Batch& b) {
                    "server upload");
     if (!st && kind == 0) {
       const uint64_t* qlen = nullptr;
-      st = query_lengths(c, &w->lane, dq, nq, s, &qlen);
+      st = query_lengths(c, &w->lane, dq, nq, s, &qlen, !batched_plan_on_device(nq));
       if (!st)
         st = run_batched(c, &w->lane, dq, qlen, nq, kmax, d_ids, d_cnt, d_len, nullptr, s);
       if (!st)

@@ -42,3 +42,20 @@ def test_rmat20_full_parity(full):
     P.sample_paths(p["T"], p["R"], p["seed"])
     assert (P.paths()[::997] == paths[::997]).all()
     P.close()
+
+
+def test_rmat20_all_vertex(full, oracle):
+    """All 1,048,576 vertices as queries (planned on the device): every row
+    equals the oracle's top-5."""
+    from paper_1504_02577_amd.panther import Panther
+
+    g, q, p, paths, inv_ptr, inv_pid, want = full
+    print("case: rmat20 all-vertex top-5", file=sys.__stderr__, flush=True)
+    wall = oracle.topk(g.n, paths, inv_ptr, inv_pid, np.arange(g.n, dtype=np.int32), 5)
+    P = Panther(0)
+    P.load_graph(g)
+    P.sample_paths(p["T"], p["R"], p["seed"])
+    ids, cnt, ln = P.topk_all(g.n, 5)
+    bad = np.nonzero((ids != wall[0]).any(1) | (cnt != wall[1]).any(1) | (ln != wall[2]))[0]
+    assert bad.size == 0, f"{bad.size} rows differ, first {bad[:5]}"
+    P.close()

@@ -307,6 +307,46 @@ def test_autotune_cache_rmat14(P, oracle, inputs, rmat14, tmp_path, monkeypatch)
     assert len(cache.read_text().splitlines()) == 3
 
 
+def test_device_planned_batch_rmat14(P, oracle, inputs, rmat14, tmp_path, monkeypatch):
+    """A batch of 2^20 queries is planned on the device (digit keys sorted by
+    the index's radix pass, only the hubs' lengths downloaded); the
+    autotuner, run afresh, times host-planned prefixes of it.  Every row
+    equals the oracle's, in host and device outputs, with the tuned and the
+    forced configurations."""
+    import torch
+
+    g, T, R, seed, paths, inv_ptr, inv_pid = rmat14
+    _say("case: device-planned batch of 2^20 queries")
+    monkeypatch.setenv("PANTHER_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    P.load_graph(g)
+    P.sample_paths(T, R, seed)
+    P.set_option("topk.form", 1)
+    P.set_option("autotune", 1)
+    P.set_option("batch.block", 0)
+    rng = np.random.default_rng(23)
+    qs = np.concatenate([rng.integers(0, g.n, (1 << 20) - 4096),
+                         inputs.queries_by_degree(g, 4096, 29)]).astype(np.int32)
+    uq, inv = np.unique(qs, return_inverse=True)
+    k = 10
+    wu = oracle.topk(g.n, paths, inv_ptr, inv_pid, uq, k)
+    want = (wu[0][inv], wu[1][inv], wu[2][inv])
+    assert (np.diff(inv_ptr)[qs] > 400).any()  # hubs among them
+    _check_topk(P.topk(qs, k), want, "device plan, tuned")
+    assert (tmp_path / "tune.txt").exists()
+    dq = torch.from_numpy(qs).cuda()
+    out = (torch.full((len(qs), k), 7, dtype=torch.int32, device="cuda"),
+           torch.full((len(qs), k), 7, dtype=torch.uint32, device="cuda"),
+           torch.full((len(qs),), 7, dtype=torch.int32, device="cuda"))
+    for blk, wgs in ((256, 2), (512, 1)):
+        P.set_option("batch.block", blk)
+        P.set_option("batch.wgs_per_cu", wgs)
+        P.topk(dq, k, out=out, stream=torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        _check_topk(tuple(t.cpu().numpy() for t in out), want, f"device plan {blk}x{wgs}")
+    P.set_option("batch.block", 0)
+    P.set_option("batch.wgs_per_cu", 0)
+
+
 @pytest.mark.parametrize("k", [5, 50])
 def test_all_vertex_topk(P, oracle, rmat14, k):
     """panther_topk_all equals the oracle's top-k of every vertex (the
