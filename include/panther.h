@@ -151,7 +151,9 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
 /* Integer options: "topk.form" (PANTHER_FORM_*; default BATCHED),
  * "pp.form" (PANTHER_PP_*; default BF16), "pp.pool" (candidate pool per
  * query of the BF16 form, 32..1024, default 256; the pool used is the
- * smallest power of two >= max(pp.pool, 2k), at most 1024), "autotune" (0/1,
+ * smallest power of two >= max(pp.pool, 2k), at most 1024), "pp.qw" (queries
+ * per work-group tile of the BF16 pool pass: 0 = autotuned per shape class,
+ * 16 or 32; the answer is the same for each), "autotune" (0/1,
  * default 1), "timing" (0/1, default 0; see panther_stage_times),
  * "batch.block" (0 = autotuned, 256, 512), "batch.wgs_per_cu" (0 =
  * autotuned, 1, 2), "batch.tier_a" / "batch.tier_b" (caps on the path-list
@@ -163,9 +165,11 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * work-group tier keeps lists up to its LDS bound divided by this; longer
  * ones go to the hub pipeline), "batch.bucket_bias" (-1 = autotuned, 0, 1:
  * a hub query gets 2^bias times the buckets its length asks for).  The
- * autotuner picks every unforced batch.* choice above per shape class and
- * keeps it in the text file $PANTHER_TUNE_CACHE (default
- * $HOME/.cache/panther_tune.txt); forcing any of them turns it off.
+ * autotuner picks every unforced batch.* choice above, and "pp.qw" when it
+ * is 0 (timed on calls of 2,048 queries or more on the context's own lane),
+ * per shape class and keeps it in the text file $PANTHER_TUNE_CACHE
+ * (default $HOME/.cache/panther_tune.txt); forcing any of them turns it
+ * off for that choice.
  * "test.hub_budget" (bytes of hub staging per
  * chunk of the batched form, 0 = automatic: min(16 GiB, free / 4), at least
  * 256 MiB; a small value splits the hub queries into many chunks, for

@@ -771,16 +771,16 @@ std::string tune_cache_path() {
   return std::string(h ? h : "/tmp") + "/.cache/panther_tune.txt";
 }
 
-// The cache is a text file of "key block wgs_per_cu tier_b_div
-// bucket_bias" lines (last match wins; the last two fields may be missing,
-// and a line with a value outside the tuner's choices is ignored).
+}  // namespace
+
+// The cache is a text file of "key value..." lines, the values integers.
 // Readers take a shared and writers an exclusive flock(2) on it, so lanes
 // and processes that tune at once never interleave a line.  Every failure
 // (no home, read-only disk) leaves tuning to run again next time.
-bool tune_lookup(const std::string& key, BatchConfig* cfg) {
+std::vector<std::vector<int>> tune_cache_read(const std::string& key) {
+  std::vector<std::vector<int>> out;
   const int fd = open(tune_cache_path().c_str(), O_RDONLY | O_CLOEXEC);
-  if (fd < 0) return false;
-  bool found = false;
+  if (fd < 0) return out;
   if (flock(fd, LOCK_SH) == 0) {
     std::string text;
     char buf[4096];
@@ -791,27 +791,20 @@ bool tune_lookup(const std::string& key, BatchConfig* cfg) {
     while (std::getline(lines, line)) {
       std::istringstream is(line);
       std::string k;
-      int blk, wgs, div = 1, bias = 0;
-      if (!(is >> k >> blk >> wgs) || k != key) continue;
-      if (is >> div) {
-        if (!(is >> bias)) continue;
-      }
-      auto one_of = [](int v, const int* xs, size_t nx) {
-        return std::find(xs, xs + nx, v) != xs + nx;
-      };
-      if (!one_of(blk, kBlocks, 2) || !one_of(wgs, kWgs, 2) || !one_of(div, kTierBDivs, 2) ||
-          !one_of(bias, kBucketBiases, 2))
-        continue;
-      *cfg = BatchConfig{blk, wgs, div, bias};
-      found = true;
+      if (!(is >> k) || k != key) continue;
+      std::vector<int> v;
+      int x;
+      while (is >> x) v.push_back(x);
+      if (is.fail() && !is.eof()) continue;  // a field that is not an integer
+      out.push_back(v);
     }
     (void)flock(fd, LOCK_UN);
   }
   close(fd);
-  return found;
+  return out;
 }
 
-void tune_store(const std::string& key, const BatchConfig& cfg) {
+void tune_cache_append(const std::string& key, const std::vector<int>& fields) {
   const std::string path = tune_cache_path();
   // create the parent directories one component at a time (no shell)
   for (size_t pos = path.find('/', 1); pos != std::string::npos; pos = path.find('/', pos + 1))
@@ -819,13 +812,39 @@ void tune_store(const std::string& key, const BatchConfig& cfg) {
   const int fd = open(path.c_str(), O_WRONLY | O_CREAT | O_APPEND | O_CLOEXEC, 0644);
   if (fd < 0) return;
   if (flock(fd, LOCK_EX) == 0) {
-    char line[512];
-    const int len = snprintf(line, sizeof line, "%s %d %d %d %d\n", key.c_str(), cfg.block,
-                             cfg.wgs_per_cu, cfg.tier_b_div, cfg.bucket_bias);
-    if (len > 0 && len < (int)sizeof line) (void)!write(fd, line, (size_t)len);
+    std::string line = key;
+    for (int x : fields) line += " " + std::to_string(x);
+    line += "\n";
+    (void)!write(fd, line.data(), line.size());
     (void)flock(fd, LOCK_UN);
   }
   close(fd);
+}
+
+namespace {
+
+// Batched-form lines: "key block wgs_per_cu tier_b_div bucket_bias" (last
+// valid match wins; the last two fields may be missing, and a line with a
+// value outside the tuner's choices is ignored).
+bool tune_lookup(const std::string& key, BatchConfig* cfg) {
+  bool found = false;
+  auto one_of = [](int v, const int* xs, size_t nx) {
+    return std::find(xs, xs + nx, v) != xs + nx;
+  };
+  for (const std::vector<int>& f : tune_cache_read(key)) {
+    if (f.size() != 2 && f.size() != 4) continue;
+    const int blk = f[0], wgs = f[1], div = f.size() == 4 ? f[2] : 1, bias = f.size() == 4 ? f[3] : 0;
+    if (!one_of(blk, kBlocks, 2) || !one_of(wgs, kWgs, 2) || !one_of(div, kTierBDivs, 2) ||
+        !one_of(bias, kBucketBiases, 2))
+      continue;
+    *cfg = BatchConfig{blk, wgs, div, bias};
+    found = true;
+  }
+  return found;
+}
+
+void tune_store(const std::string& key, const BatchConfig& cfg) {
+  tune_cache_append(key, {cfg.block, cfg.wgs_per_cu, cfg.tier_b_div, cfg.bucket_bias});
 }
 
 }  // namespace

@@ -1061,7 +1061,7 @@ struct PoolGeom {
   int64_t S;      // database slices per tile
 };
 
-PoolGeom pool_geom(const panther_ctx* c, int64_t nq, int32_t k) {
+PoolGeom pool_geom(const panther_ctx* c, int64_t nq, int32_t k, int qw = 0) {
   PoolGeom g{};
   // pool: at least the option and at least 2k (margin for the bfloat16
   // rounding at the pool boundary), a power of two, at most 1024
@@ -1071,12 +1071,13 @@ PoolGeom pool_geom(const panther_ctx* c, int64_t nq, int32_t k) {
   // buffer: P kept keys, at least P more before a compaction is worth its
   // sort, and room for the kCheckEvery chunks between checks
   g.cap = 2 * g.P + kCheckEvery * kChunk;
-  // Query tiles: 32 queries per work-group for large batches, 16 for
-  // small ones (a tile scans the union of its queries' norm bands, so
-  // narrower tiles scan fewer rows; wider ones reuse each row more).  The
-  // database is split into slices when the batch has few tiles, so that
-  // about two work-groups per CU scan it.
-  g.qw = nq >= 8192 ? 32 : 16;
+  // Query tiles of qw queries per work-group: by default 32 for large
+  // batches, 16 for small ones (a tile scans the union of its queries' norm
+  // bands, so narrower tiles scan fewer rows; wider ones reuse each row
+  // more); the autotuner may choose either.  The database is split into
+  // slices when the batch has few tiles, so that about two work-groups per
+  // CU scan it.
+  g.qw = qw ? qw : (nq >= 8192 ? 32 : 16);
   g.tiles = (nq + g.qw - 1) / g.qw;
   const int64_t rows = c->pp && c->pp->bf16_rows ? c->pp->bf16_rows : (int64_t)c->n;
   int64_t S = (2 * (int64_t)c->num_cus + g.tiles - 1) / std::max<int64_t>(g.tiles, 1);
@@ -1089,15 +1090,12 @@ PoolGeom pool_geom(const panther_ctx* c, int64_t nq, int32_t k) {
 
 }  // namespace
 
-// Pool pass + rerank over the database context c.  qtheta (null: c's own
-// features) holds the queries' feature rows when they come from another
-// graph; their bf16 operands are then gathered per query first.
-int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
-                int32_t* d_ids, double* d_dist, hipStream_t s, const float* qtheta) {
+// One BF16 call with the pool geometry G: the pool pass, the rerank and the
+// exact recompute of the uncertified queries.
+static int run_pp_bf16_geom(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq,
+                            int32_t D, int32_t k, int32_t* d_ids, double* d_dist, hipStream_t s,
+                            const float* qtheta, const PoolGeom& G) {
   PPState* pp = c->pp;
-  if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
-  if (!pp || pp->bf16_D != D) return ctx_fail(c, PANTHER_ESTATE, "bf16 rows not prepared");
-  const PoolGeom G = pool_geom(c, nq, k);
   const int P = G.P, cap = G.cap, qw = G.qw;
   const int64_t tiles = G.tiles, S = G.S;
   const float scale = (float)c->R;
@@ -1264,6 +1262,84 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
   return PANTHER_OK;
 }
 
+// The pool tile width of a BF16 call: forced by "pp.qw", else the tuned
+// choice of its shape class (rows, D, batch size and k rounded to powers of
+// two, pool, cross-graph), else, when autotuning, timed now on the main lane
+// (each width warmed once and timed once; the answer is the same for
+// either, since the exact rerank decides it), else the default.
+static int pool_width(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D,
+                      int32_t k, int32_t* d_ids, double* d_dist, hipStream_t s,
+                      const float* qtheta, int* qw_out) {
+  *qw_out = c->pp_qw;
+  if (c->pp_qw) return PANTHER_OK;
+  int nq_bucket = 0;
+  while ((int64_t(2) << nq_bucket) <= nq) ++nq_bucket;
+  int k_bucket = 1;
+  while (k_bucket < k) k_bucket <<= 1;
+  char key[256];
+  snprintf(key, sizeof key, "gfx950:pp:rows%lld:D%d:nq2^%d:k%d:P%d:cu%d:x%d",
+           (long long)c->pp->bf16_rows, D, nq_bucket, k_bucket, pool_geom(c, nq, k).P,
+           c->num_cus, qtheta ? 1 : 0);
+  {
+    std::lock_guard<std::mutex> g(c->pp_tune_mu);
+    auto it = c->pp_qw_tuned.find(key);
+    if (it != c->pp_qw_tuned.end()) {
+      *qw_out = it->second;
+      return PANTHER_OK;
+    }
+  }
+  int qw = 0;
+  for (const std::vector<int>& f : tune_cache_read(key))
+    if (f.size() == 1 && (f[0] == 16 || f[0] == 32)) qw = f[0];
+  if (!qw && c->autotune && nq >= 2048 && lane == &c->lane0) {
+    hipEvent_t e0, e1;
+    HIPTRY(hipEventCreate(&e0), "pp autotune");
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return ctx_fail(c, PANTHER_EDEVICE, "pp autotune: event");
+    }
+    float best = 1e30f;
+    int st = PANTHER_OK;
+    for (int w : {16, 32}) {
+      const PoolGeom G = pool_geom(c, nq, k, w);
+      if (!st) st = run_pp_bf16_geom(c, lane, dq, nq, D, k, d_ids, d_dist, s, qtheta, G);
+      if (!st) st = ctx_hip(c, hipEventRecord(e0, s), "pp autotune");
+      if (!st) st = run_pp_bf16_geom(c, lane, dq, nq, D, k, d_ids, d_dist, s, qtheta, G);
+      if (!st) st = ctx_hip(c, hipEventRecord(e1, s), "pp autotune");
+      if (!st) st = ctx_hip(c, hipEventSynchronize(e1), "pp autotune");
+      float ms = 0.f;
+      if (!st) st = ctx_hip(c, hipEventElapsedTime(&ms, e0, e1), "pp autotune");
+      if (!st && ms < best) {
+        best = ms;
+        qw = w;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    tune_cache_append(key, {qw});
+  }
+  if (qw) {
+    std::lock_guard<std::mutex> g(c->pp_tune_mu);
+    c->pp_qw_tuned[key] = qw;
+  }
+  *qw_out = qw;
+  return PANTHER_OK;
+}
+
+// Pool pass + rerank over the database context c.  qtheta (null: c's own
+// features) holds the queries' feature rows when they come from another
+// graph; their bf16 operands are then gathered per query first.
+int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32_t D, int32_t k,
+                int32_t* d_ids, double* d_dist, hipStream_t s, const float* qtheta) {
+  PPState* pp = c->pp;
+  if (D > kDP) return ctx_fail(c, PANTHER_EINVAL, "the BF16 form supports D <= %d", kDP);
+  if (!pp || pp->bf16_D != D) return ctx_fail(c, PANTHER_ESTATE, "bf16 rows not prepared");
+  int qw = 0;
+  TRY(pool_width(c, lane, dq, nq, D, k, d_ids, d_dist, s, qtheta, &qw));
+  return run_pp_bf16_geom(c, lane, dq, nq, D, k, d_ids, d_dist, s, qtheta, pool_geom(c, nq, k, qw));
+}
+
 }  // namespace panther
 
 // Device bytes of the lane scratch a BF16 call of nq queries takes (the
@@ -1272,11 +1348,15 @@ int run_pp_bf16(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq, int32
 size_t pp_lane_bytes(const panther_ctx* c, int64_t nq, int32_t k) {
   if (nq <= 0) return 0;
   if (c->pp_form == PANTHER_PP_FP64) return 0;
-  const panther::PoolGeom G = panther::pool_geom(c, nq, k);
   const size_t n = (size_t)nq;
-  size_t b = sizeof(uint64_t) * n * G.S * G.cap + sizeof(uint64_t) * n +
-             (G.S > 1 ? sizeof(uint64_t) * n * G.S * G.P : 0) +
-             (sizeof(int32_t) + sizeof(float)) * n * G.P + 256;
+  // either tile width may be chosen: the larger need
+  size_t b = 0;
+  for (int w : {16, 32}) {
+    const panther::PoolGeom G = panther::pool_geom(c, nq, k, w);
+    b = std::max(b, sizeof(uint64_t) * n * G.S * G.cap + sizeof(uint64_t) * n +
+                        (G.S > 1 ? sizeof(uint64_t) * n * G.S * G.P : 0) +
+                        (sizeof(int32_t) + sizeof(float)) * n * G.P + 256);
+  }
   b += 64;
   b += (2 * sizeof(uint32_t) + 2 * sizeof(int32_t)) * ((n + 63) / 64 * 64);
   b += sort_pairs_bytes(nq);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -61,7 +62,10 @@ struct panther_ctx {
   int pp_form = 1;    // PANTHER_PP_BF16
   int pp_pool = 256;
   int pp_recompute_all = 0;  // test: recompute every full-pool query (2: via brute force)
+  int pp_qw = 0;             // BF16 pool tile width (0: tuned)
   int autotune = 1;
+  std::map<std::string, int> pp_qw_tuned;  // tuned pool tile width per shape class
+  std::mutex pp_tune_mu;
   int64_t fail_alloc_after = -1;
   std::mutex alloc_mu;
   // graph
@@ -147,6 +151,10 @@ int stage_queries(panther_ctx* c, const int32_t* queries, int64_t nq, int mem, h
 // lengths on the host, or nullptr for a batch that batched_plan_on_device
 // accepts: it is then planned from the lane's device lengths (b_qlen).
 bool batched_plan_on_device(int64_t nq);
+// Autotuner cache (a text file, flock-guarded): the integer fields of every
+// line of `key`, in file order; appending adds one line.
+std::vector<std::vector<int>> tune_cache_read(const std::string& key);
+void tune_cache_append(const std::string& key, const std::vector<int>& fields);
 int run_batched(panther_ctx* c, Lane* lane, const int32_t* dq, const uint64_t* qlen, int64_t nq,
                 int32_t k, int32_t* d_ids, uint32_t* d_counts, int32_t* d_len, float* theta,
                 hipStream_t s);

@@ -140,21 +140,33 @@ def test_knn_rmat14(P, oracle, inputs, rmat, form, pool):
     P.set_option("pp.pool", 256)
 
 
-def test_knn_rmat14_large_batch(P, oracle, inputs, rmat):
-    """8,192 queries: the pool pass takes its wide-tile form (32 queries per
-    work-group, one slice); ids equal the oracle's."""
+@pytest.mark.parametrize("qw", [0, 16, 32])
+def test_knn_rmat14_large_batch(P, oracle, inputs, rmat, qw, tmp_path, monkeypatch):
+    """8,192 queries with each pool tile width (16 or 32 queries per
+    work-group, one slice) and with the autotuned one (both timed on a
+    fresh cache, the choice stored): ids equal the oracle's every time."""
     g, paths, inv_ptr, inv_pid = rmat
-    _say("case: knn rmat14 large batch")
+    _say(f"case: knn rmat14 large batch, pool tile width {qw or 'tuned'}")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PANTHER_TUNE_CACHE", str(cache))
     P.load_graph(g)
     P.sample_paths(5, 400_000, 7)
     P.set_option("pp.form", 1)
+    P.set_option("pp.qw", qw)
     theta = oracle.features(g.n, paths, inv_ptr, inv_pid, 50)
     q = np.random.default_rng(6).choice(g.n, 8192, replace=False).astype(np.int32)
     wi, wd = oracle.knn(theta, q, 20)
     gi, gd = P.pp_topk(q, 50, 20)
-    check_knn(gi, gd, wi, wd, "rmat14 large batch", exact_ids=True)
+    check_knn(gi, gd, wi, wd, f"rmat14 large batch qw={qw}", exact_ids=True)
     nq, redo = P.pp_certified()
     _say(f"  recomputed {redo}/{nq}, scanned {P.pp_scanned():.3f}")
+    if qw == 0:
+        lines = [l.split() for l in cache.read_text().splitlines() if ":pp:" in l]
+        assert len(lines) == 1 and lines[0][1] in ("16", "32"), lines
+        gi2, gd2 = P.pp_topk(q, 50, 20)  # the stored choice, no timing
+        assert (gi2 == gi).all() and (gd2 == gd).all()
+        assert len([l for l in cache.read_text().splitlines() if ":pp:" in l]) == 1
+    P.set_option("pp.qw", 0)
 
 
 @pytest.mark.parametrize("mode,k", [(1, 20), (1, 200), (2, 20)])
