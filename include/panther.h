@@ -153,7 +153,7 @@ int64_t panther_sample_size(double eps, double c, double delta, int32_t T);
  * query of the BF16 form, 32..1024, default 256; the pool used is the
  * smallest power of two >= max(pp.pool, 2k), at most 1024), "pp.qw" (queries
  * per work-group tile of the BF16 pool pass: 0 = autotuned per shape class,
- * 16 or 32; the answer is the same for each), "autotune" (0/1,
+ * 16, 32 or 64; the answer is the same for each), "autotune" (0/1,
  * default 1), "timing" (0/1, default 0; see panther_stage_times),
  * "batch.block" (0 = autotuned, 256, 512), "batch.wgs_per_cu" (0 =
  * autotuned, 1, 2), "batch.tier_a" / "batch.tier_b" (caps on the path-list

@@ -1071,13 +1071,13 @@ PoolGeom pool_geom(const panther_ctx* c, int64_t nq, int32_t k, int qw = 0) {
   // buffer: P kept keys, at least P more before a compaction is worth its
   // sort, and room for the kCheckEvery chunks between checks
   g.cap = 2 * g.P + kCheckEvery * kChunk;
-  // Query tiles of qw queries per work-group: by default 32 for large
-  // batches, 16 for small ones (a tile scans the union of its queries' norm
-  // bands, so narrower tiles scan fewer rows; wider ones reuse each row
-  // more); the autotuner may choose either.  The database is split into
+  // Query tiles of qw queries per work-group: by default 64 for large
+  // batches, 32 for medium and 16 for small ones (a tile scans the union of
+  // its queries' norm bands, so narrower tiles scan fewer rows; wider ones
+  // reuse each row more); the autotuner may choose any of them.  The database is split into
   // slices when the batch has few tiles, so that about two work-groups per
   // CU scan it.
-  g.qw = qw ? qw : (nq >= 8192 ? 32 : 16);
+  g.qw = qw ? qw : (nq >= 32768 ? 64 : (nq >= 8192 ? 32 : 16));
   g.tiles = (nq + g.qw - 1) / g.qw;
   const int64_t rows = c->pp && c->pp->bf16_rows ? c->pp->bf16_rows : (int64_t)c->n;
   int64_t S = (2 * (int64_t)c->num_cus + g.tiles - 1) / std::max<int64_t>(g.tiles, 1);
@@ -1172,11 +1172,15 @@ static int run_pp_bf16_geom(panther_ctx* c, Lane* lane, const int32_t* dq, int64
     pa.q_order = vout;
   }
   const size_t sort_lds = sizeof(uint64_t) * (size_t)sort_cap * (kBlock / kWave);
-  const void* pool_fn = qw == 32 ? (const void*)k_pp_pool<32> : (const void*)k_pp_pool<16>;
+  const void* pool_fn = qw == 64   ? (const void*)k_pp_pool<64>
+                        : qw == 32 ? (const void*)k_pp_pool<32>
+                                   : (const void*)k_pp_pool<16>;
   HIPTRY(hipFuncSetAttribute(pool_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_lds),
          "pp pool attribute");
   auto launch_pool = [&](const PoolArgs& args, unsigned gy) {
-    if (qw == 32)
+    if (qw == 64)
+      k_pp_pool<64><<<dim3((unsigned)tiles, gy), kBlock, sort_lds, s>>>(args);
+    else if (qw == 32)
       k_pp_pool<32><<<dim3((unsigned)tiles, gy), kBlock, sort_lds, s>>>(args);
     else
       k_pp_pool<16><<<dim3((unsigned)tiles, gy), kBlock, sort_lds, s>>>(args);
@@ -1290,7 +1294,7 @@ static int pool_width(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq,
   }
   int qw = 0;
   for (const std::vector<int>& f : tune_cache_read(key))
-    if (f.size() == 1 && (f[0] == 16 || f[0] == 32)) qw = f[0];
+    if (f.size() == 1 && (f[0] == 16 || f[0] == 32 || f[0] == 64)) qw = f[0];
   if (!qw && c->autotune && nq >= 2048 && lane == &c->lane0) {
     hipEvent_t e0, e1;
     HIPTRY(hipEventCreate(&e0), "pp autotune");
@@ -1300,7 +1304,7 @@ static int pool_width(panther_ctx* c, Lane* lane, const int32_t* dq, int64_t nq,
     }
     float best = 1e30f;
     int st = PANTHER_OK;
-    for (int w : {16, 32}) {
+    for (int w : {16, 32, 64}) {
       const PoolGeom G = pool_geom(c, nq, k, w);
       if (!st) st = run_pp_bf16_geom(c, lane, dq, nq, D, k, d_ids, d_dist, s, qtheta, G);
       if (!st) st = ctx_hip(c, hipEventRecord(e0, s), "pp autotune");
@@ -1351,7 +1355,7 @@ size_t pp_lane_bytes(const panther_ctx* c, int64_t nq, int32_t k) {
   const size_t n = (size_t)nq;
   // either tile width may be chosen: the larger need
   size_t b = 0;
-  for (int w : {16, 32}) {
+  for (int w : {16, 32, 64}) {
     const panther::PoolGeom G = panther::pool_geom(c, nq, k, w);
     b = std::max(b, sizeof(uint64_t) * n * G.S * G.cap + sizeof(uint64_t) * n +
                         (G.S > 1 ? sizeof(uint64_t) * n * G.S * G.P : 0) +

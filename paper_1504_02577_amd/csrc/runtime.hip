@@ -282,8 +282,8 @@ extern "C" int panther_set_option(panther_ctx* c, const char* key, int64_t value
       return ctx_fail(c, PANTHER_EINVAL, "pp.pool must lie in [32, 1024]");
     c->pp_pool = (int)value;
   } else if (k == "pp.qw") {
-    if (value != 0 && value != 16 && value != 32)
-      return ctx_fail(c, PANTHER_EINVAL, "pp.qw must be 0 (tuned), 16 or 32");
+    if (value != 0 && value != 16 && value != 32 && value != 64)
+      return ctx_fail(c, PANTHER_EINVAL, "pp.qw must be 0 (tuned), 16, 32 or 64");
     c->pp_qw = (int)value;
   } else if (k == "autotune") {
     if (value != 0 && value != 1) return ctx_fail(c, PANTHER_EINVAL, "autotune must be 0 or 1");
