@@ -46,10 +46,22 @@ namespace {
 
 constexpr int kQueueCtl = 4;  // [0] work-queue head
 
+// A tier item as the kernels read it: the list P_q = inv_pid[a, a + L) of
+// query q (batch index qi), expanded once per call after planning, so that
+// a query costs one dependent load before its list instead of three (item,
+// query, offsets).
+struct ItemRec {
+  uint64_t a;
+  uint32_t L;
+  int32_t qi;
+  int32_t q;
+  int32_t pad;
+};
+
 struct BatchArgs {
   const int32_t* queries;  // [nq]
-  const int32_t* itemsB;   // query indices, longest class first
-  const int32_t* itemsA;
+  const ItemRec* itemsB;   // the B queries, longest class first
+  const ItemRec* itemsA;
   int32_t nB, nA;
   // tier A runs in four phases of 64, 32, 16 and 8 lanes per query:
   // itemsA [0, nA64), [nA64, nA32), [nA32, nA16), [nA16, nA)
@@ -157,10 +169,11 @@ __device__ void group_query(const BatchArgs& A, int ai, int hi, char* region) {
   int32_t qi = 0, q = -1;
   uint64_t a = 0, L = 0;
   if (active) {
-    qi = A.itemsA[ai];
-    q = A.queries[qi];
-    a = A.inv_ptr[q];
-    L = A.inv_ptr[q + 1] - a;
+    const ItemRec r = A.itemsA[ai];
+    qi = r.qi;
+    q = r.q;
+    a = r.a;
+    L = r.L;
   }
   for (int j = gl; j < TG; j += G) {
     keys[j] = -1;
@@ -369,15 +382,16 @@ __device__ int select_fast(const BatchArgs& A, const uint64_t* comp, int nc, Sel
 }
 
 template <int BLOCK, int S>
-__device__ void block_query_lds(const BatchArgs& A, int32_t qi, char* region, SelectSmem& sm,
-                                uint32_t* s_ctl) {
+__device__ void block_query_lds(const BatchArgs& A, const ItemRec& r, char* region,
+                                SelectSmem& sm, uint32_t* s_ctl) {
   const int TB = A.TB;
   int32_t* keys = reinterpret_cast<int32_t*>(region);
   uint32_t* vals = reinterpret_cast<uint32_t*>(keys + TB);
   uint64_t* comp = reinterpret_cast<uint64_t*>(vals + TB);  // TB/2 entries
-  const int32_t q = A.queries[qi];
-  const uint64_t a = A.inv_ptr[q];
-  const uint64_t L = A.inv_ptr[q + 1] - a;
+  const int32_t qi = r.qi;
+  const int32_t q = r.q;
+  const uint64_t a = r.a;
+  const uint64_t L = r.L;
   for (int j = threadIdx.x; j < TB; j += BLOCK) {
     keys[j] = -1;
     vals[j] = 0u;
@@ -483,6 +497,17 @@ __global__ void k_plan_hub_lengths(const int32_t* __restrict__ idx, int64_t n,
   if (i < n) out[i] = qlen[idx[i]];
 }
 
+__global__ void k_expand_items(const int32_t* __restrict__ items, int64_t n,
+                               const int32_t* __restrict__ queries,
+                               const uint64_t* __restrict__ inv_ptr, ItemRec* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t qi = items[i];
+  const int32_t q = queries[qi];
+  const uint64_t a = inv_ptr[q];
+  out[i] = ItemRec{a, (uint32_t)(inv_ptr[q + 1] - a), qi, q, 0};
+}
+
 __global__ void k_reset_queue(uint32_t* q) {
   if (threadIdx.x < kQueueCtl) q[threadIdx.x] = 0u;
 }
@@ -550,6 +575,8 @@ struct BatchState {
   // device plan buffers (grown as needed)
   int32_t* d_items = nullptr;
   size_t items_cap = 0;
+  ItemRec* d_irec = nullptr;  // the tier items expanded (k_expand_items)
+  size_t irec_cap = 0;
   uint32_t* d_queue = nullptr;
   // hub pipeline buffers (grown as needed)
   HubQuery* d_hq = nullptr;
@@ -684,6 +711,7 @@ void free_batch_state(Lane* lane) {
                   (void*)b->dp_offs, (void*)b->dp_scan, (void*)b->dp_small, (void*)b->dp_hubL})
     ctx_free(p);
   ctx_free(b->d_items);
+  ctx_free(b->d_irec);
   ctx_free(b->d_queue);
   for (void* p : {(void*)b->d_hq, (void*)b->d_stA, (void*)b->d_stB, (void*)b->d_bkt_cnt,
                   (void*)b->d_bkt_fill, (void*)b->d_bkt_start, (void*)b->d_cand,
@@ -1385,6 +1413,12 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
                  "batch plan upload");
     if (st) return st;
   }
+  if (need) {
+    if ((st = grow(c, b->d_irec, b->irec_cap, need, sizeof(ItemRec), "batch plan"))) return st;
+    k_expand_items<<<(unsigned)((need + 255) / 256), 256, 0, s>>>(b->d_items, (int64_t)need, dq,
+                                                                   c->d_inv_ptr, b->d_irec);
+    if ((st = ctx_hip(c, hipGetLastError(), "batch plan"))) return st;
+  }
   if (!b->uploaded) {
     st = ctx_hip(c, hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming), "batch plan");
     if (st) return st;
@@ -1394,8 +1428,8 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   b->upload_pending = true;
   BatchArgs a{};
   a.queries = dq;
-  a.itemsB = b->d_items;
-  a.itemsA = b->d_items + nB;
+  a.itemsB = b->d_irec;
+  a.itemsA = b->d_irec + nB;
   a.nB = (int32_t)nB;
   a.nA = (int32_t)(need - nB);
   a.nA64 = (int32_t)nA64;
@@ -1445,7 +1479,7 @@ BatchSizing batched_sizing(panther_ctx* c, Lane* lane) {
 
 size_t batched_query_bytes(const BatchSizing& z, uint64_t L, int32_t kmax) {
   const uint64_t T = z.T;
-  size_t bytes = sizeof(int32_t) + sizeof(uint64_t);
+  size_t bytes = sizeof(int32_t) + sizeof(uint64_t) + sizeof(ItemRec);
   if (L <= z.LB) return bytes;
   const uint64_t occ = T * L;
   const uint64_t nb = hub_buckets(occ << z.bucket_bias, z.hub_bits_max);
@@ -1471,7 +1505,7 @@ size_t lane_device_bytes(const Lane* lane) {
     t += d->p ? d->cap : 0;
   const BatchState* b = lane->batch;
   if (!b) return t;
-  t += sizeof(int32_t) * b->items_cap + (b->d_queue ? 64 : 0);
+  t += sizeof(int32_t) * b->items_cap + sizeof(ItemRec) * b->irec_cap + (b->d_queue ? 64 : 0);
   t += sizeof(HubQuery) * b->hq_cap + sizeof(int32_t) * (b->occ_cap + b->occB_cap);
   t += sizeof(uint32_t) * (b->bkt_cap + b->bkt_fill_cap + b->redo_cap + b->cand_n_cap);
   t += sizeof(uint64_t) * (b->bkt_start_cap + b->cand_cap + b->bkt_cand0_cap);
