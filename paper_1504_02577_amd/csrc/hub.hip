@@ -14,7 +14,8 @@
 //            keeps the tile's counts and adds them to the bucket totals;
 //   bucket   the totals are scanned, and each tile moves its vertices into
 //            bucket order (its run of a bucket placed by one atomic
-//            reservation);
+//            reservation); a query with a single bucket skips this step,
+//            its count reads the row-order staging;
 //   count    one work-group per bucket counts its vertices in an LDS hash
 //            table and selects the bucket's k best (count desc, id asc);
 //   merge    one work-group per query selects the k best of the per-bucket
@@ -173,7 +174,9 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_gather(HubArgs A) {
   for (int b = threadIdx.x; b < nb; b += kGatherBlock) {
     const uint32_t h = hist[b];
     th[b] = h;
-    if (h) atomicAdd(&A.bkt_cnt[Q.bkt0 + b], h);
+    // a single-bucket query is counted from its row-order staging: its
+    // bucket keeps an empty range of the bucket order
+    if (h && nb > 1) atomicAdd(&A.bkt_cnt[Q.bkt0 + b], h);
   }
 }
 
@@ -183,6 +186,7 @@ __global__ void __launch_bounds__(kGatherBlock) k_hub_scatter(HubArgs A) {
   const uint32_t tile = blockIdx.x;
   const int j = A.stile_owner[tile];
   const HubQuery Q = A.hq[j];
+  if (Q.nb == 1u) return;  // its bucket is its row-order staging
   const uint64_t L = A.hx[j].L;
   const int nb = (int)Q.nb;
   const uint64_t r0 = (uint64_t)(tile - Q.stile0) * kSTileRows;
@@ -250,13 +254,30 @@ struct alignas(16) CountSmem {
   uint32_t ctl[8];
 };
 
-// Counts the vertices of stB[s, e) (one bucket of a query with nb buckets)
+// The slots of bucket g of query j: its run [s, e) of the bucket order, or,
+// for a query with a single bucket, the query's whole row-order staging
+// (the scatter leaves such queries alone; -1 marks the empty slots of rows
+// with fewer vertices, which the count skips).
+__device__ __forceinline__ const int32_t* bucket_slots(const HubArgs& A, uint32_t g, int j,
+                                                      uint64_t* s, uint64_t* e) {
+  *s = A.bkt_start[g];
+  *e = A.bkt_start[g + 1];
+  if (*s != *e) return A.stB;
+  const HubQuery Q = A.hq[j];
+  if (Q.nb != 1u) return A.stB;  // an empty bucket
+  *s = Q.occ0;
+  *e = Q.occ0 + A.hx[j].L * (uint64_t)A.T;
+  return A.stA;
+}
+
+// Counts the vertices of src[s, e) (one bucket of a query with nb buckets)
 // whose sub-range of 2^sbits is `sub` (all of them when sbits == 0) in the
 // LDS table.  Returns false when the table overflowed.  At the finest split
 // at most kTable / 2 distinct ids qualify and the probe sequence is
 // unbounded, so it never fails there.
-__device__ bool count_part(const HubArgs& A, int32_t* keys, uint32_t* vals, uint32_t* ctl,
-                           uint64_t s, uint64_t e, uint32_t nb, int sbits, uint32_t sub) {
+__device__ bool count_part(const HubArgs& A, const int32_t* src, int32_t* keys, uint32_t* vals,
+                           uint32_t* ctl, uint64_t s, uint64_t e, uint32_t nb, int sbits,
+                           uint32_t sub) {
   const int probes = sbits > 0 && finest_split(nb, sbits) ? kTable : kProbes;
   for (int j = threadIdx.x; j < kTable / 4; j += kCountBlock) {
     reinterpret_cast<int4*>(keys)[j] = make_int4(-1, -1, -1, -1);
@@ -273,7 +294,7 @@ __device__ bool count_part(const HubArgs& A, int32_t* keys, uint32_t* vals, uint
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const uint64_t i = i0 + (uint64_t)u * kCountBlock + threadIdx.x;
-      x[u] = i < e ? A.stB[i] : -1;
+      x[u] = i < e ? src[i] : -1;
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -436,9 +457,10 @@ __global__ void __launch_bounds__(kCountBlock) k_hub_count(HubArgs A) {
   const uint32_t g = blockIdx.x;
   const int j = A.bkt_owner[g];
   const uint64_t cand0 = A.bkt_cand0[g];
-  const uint64_t s = A.bkt_start[g];
-  const uint64_t e = A.bkt_start[g + 1];
-  if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, 1u, 0, 0u) && emit_by_count(A, sm, j, cand0))
+  uint64_t s, e;
+  const int32_t* src = bucket_slots(A, g, j, &s, &e);
+  if (count_part(A, src, sm.keys, sm.vals, sm.ctl, s, e, 1u, 0, 0u) &&
+      emit_by_count(A, sm, j, cand0))
     return;
   if (threadIdx.x == 0) A.redo[atomicAdd(A.redo_n, 1u)] = g;
 }
@@ -453,11 +475,11 @@ __global__ void __launch_bounds__(kCountBlock) k_hub_count_rare(HubArgs A) {
     const uint32_t g = A.redo[r];
     const int j = A.bkt_owner[g];
     const HubQuery Q = A.hq[j];
-    const uint64_t s = A.bkt_start[g];
-    const uint64_t e = A.bkt_start[g + 1];
+    uint64_t s, e;
+    const int32_t* src = bucket_slots(A, g, j, &s, &e);
     int m;
     const uint64_t* best = sm.sel.out;
-    if (count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.nb, 0, 0u)) {
+    if (count_part(A, src, sm.keys, sm.vals, sm.ctl, s, e, Q.nb, 0, 0u)) {
       m = select_exact(A, sm);
     } else {
       // split by the next hash bits until every part fits
@@ -466,7 +488,7 @@ __global__ void __launch_bounds__(kCountBlock) k_hub_count_rare(HubArgs A) {
         int rr = 0;  // keys in sm.run
         bool ok = true;
         for (uint32_t sub = 0; sub < (1u << sbits); ++sub) {
-          if (!count_part(A, sm.keys, sm.vals, sm.ctl, s, e, Q.nb, sbits, sub)) {
+          if (!count_part(A, src, sm.keys, sm.vals, sm.ctl, s, e, Q.nb, sbits, sub)) {
             ok = false;
             break;
           }
