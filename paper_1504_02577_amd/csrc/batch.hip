@@ -72,7 +72,7 @@ struct BatchArgs {
   uint32_t* queue;         // kQueueCtl words
   int32_t n;
   int32_t k;
-  int32_t TA, TB;          // table sizes (powers of two)
+  int32_t TB;              // tier B table size (a power of two)
   int32_t* out_ids;
   uint32_t* out_counts;
   int32_t* out_len;
@@ -1441,7 +1441,6 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
   a.queue = b->d_queue;
   a.n = c->n;
   a.k = k;
-  a.TA = lay.TA;
   a.TB = lay.TB;
   a.out_ids = d_ids;
   a.out_counts = d_counts;
