@@ -467,10 +467,15 @@ __global__ void __launch_bounds__(kWaveBlock) k_topk_waves(BatchArgs A) {
 
 // ---- device planning of large batches ----
 // Digit of query i in the plan's order: tier B classes 64..0 (digits
-// 0..64), tier A classes 64..0 (65..129), then the hubs (130); a stable
-// sort by digit gives the host planner's order.  Also writes the pair count
-// the sort reads and the query index as the sort's value.
+// 0..64), tier A classes 64..0 (65..129), then the hubs by class, 64..0
+// (130..194); a stable sort by digit gives the host planner's tier order,
+// and the hubs longest class first (the host planner orders them exactly
+// by length, so that repeated queries of one vertex run side by side; the
+// batches planned here, such as a pass over every vertex, rarely repeat
+// one).  Also writes the pair count the sort reads and the query index as
+// the sort's value.
 constexpr uint32_t kHubDigit = 130;
+constexpr uint32_t kDigits = kHubDigit + 65;
 __global__ void k_plan_digits(const uint64_t* __restrict__ qlen, int64_t nq, uint64_t LA,
                               uint64_t LB, uint32_t* __restrict__ keys,
                               uint32_t* __restrict__ vals, uint64_t* __restrict__ nnz) {
@@ -479,16 +484,16 @@ __global__ void k_plan_digits(const uint64_t* __restrict__ qlen, int64_t nq, uin
   if (i >= nq) return;
   const uint64_t L = qlen[i];
   const uint32_t cl = L ? 64u - (uint32_t)__clzll((long long)L) : 0u;
-  keys[i] = L > LB ? kHubDigit : (L > LA ? 0u : 65u) + (64u - cl);
+  keys[i] = (L > LB ? kHubDigit : (L > LA ? 0u : 65u)) + (64u - cl);
   vals[i] = (uint32_t)i;
 }
 
-// starts[d] = first position of digit d in the sorted order, d = 0..131
+// starts[d] = first position of digit d in the sorted order, d = 0..kDigits
 // (offsets are the digit-major exclusive scan of the tile counts).
 __global__ void k_plan_starts(const uint64_t* __restrict__ offs, uint64_t ntiles,
                               uint64_t* __restrict__ starts) {
   const uint32_t d = threadIdx.x;
-  if (d <= kHubDigit + 1) starts[d] = offs[(uint64_t)d * ntiles];
+  if (d <= kDigits) starts[d] = offs[(uint64_t)d * ntiles];
 }
 
 __global__ void k_plan_hub_lengths(const int32_t* __restrict__ idx, int64_t n,
@@ -1014,9 +1019,18 @@ static int plan_hubs(panther_ctx* c, BatchState* b,
   }
   // staging bytes per occurrence slot: row order, bucket order
   const size_t budget = b->hub_budget_forced ? b->hub_budget_forced : b->hub_budget;
-  uint64_t occ_limit = std::max<uint64_t>(budget / 8, T * C.front().first);
+  // the longest hub leads its class (exact order) or its class leads
+  // (device-planned batches): it is among the first class's entries
+  uint64_t max_L = 0;
+  {
+    const auto cls = [](uint64_t L) { return 64 - __builtin_clzll(L); };
+    const int c0 = cls(C.front().first);
+    for (size_t i = 0; i < C.size() && cls(C[i].first) == c0; ++i)
+      max_L = std::max(max_L, C[i].first);
+  }
+  uint64_t occ_limit = std::max<uint64_t>(budget / 8, T * max_L);
   occ_limit = std::min<uint64_t>(occ_limit, (uint64_t)1 << 31);
-  if (T * C.front().first > occ_limit)
+  if (T * max_L > occ_limit)
     return ctx_fail(c, PANTHER_ERANGE, "a hub query's path list exceeds the staging limit");
   struct Chunk {
     size_t first, nq;
@@ -1206,7 +1220,8 @@ static int plan_on_device(panther_ctx* c, BatchState* b, const uint64_t* dqlen, 
   const uint64_t n = (uint64_t)nq;
   const uint64_t ntiles = radix_tiles_pairs(n);
   const size_t nh = (size_t)256 * ntiles;
-  constexpr size_t kStarts = kHubDigit + 2;
+  constexpr size_t kStarts = kDigits + 1;
+  static_assert(kDigits < 256, "one 8-bit radix pass");
   int st;
   if ((st = grow(c, b->dp_keys, b->dp_cap, n, sizeof(uint32_t), "batch plan")) ||
       (st = grow(c, b->dp_keys2, b->dp_keys2_cap, n, sizeof(uint32_t), "batch plan")) ||
@@ -1238,7 +1253,7 @@ static int plan_on_device(panther_ctx* c, BatchState* b, const uint64_t* dqlen, 
   *nB = (size_t)sp[65];
   *need = (size_t)sp[kHubDigit];
   for (int c2 = 0; c2 <= 64; ++c2) cntA[c2] = (size_t)(sp[65 + (64 - c2) + 1] - sp[65 + (64 - c2)]);
-  const size_t nC = (size_t)(sp[kHubDigit + 1] - sp[kHubDigit]);
+  const size_t nC = (size_t)(sp[kDigits] - sp[kHubDigit]);
   C->clear();
   if (!with_hubs || !nC) return PANTHER_OK;
   const int32_t* hub_idx = b->d_items + sp[kHubDigit];
@@ -1393,7 +1408,7 @@ static int plan(panther_ctx* c, BatchState* b, const BatchConfig& cfg, const int
     if ((st = ctx_hip(c, hipEventSynchronize(b->uploaded), "batch plan"))) return st;
     b->upload_pending = false;
   }
-  sort_hubs_longest_first(C, b->hub_sort_tmp);
+  if (!on_device) sort_hubs_longest_first(C, b->hub_sort_tmp);
   st = plan_hubs(c, b, C, dq, k, cfg.bucket_bias, d_ids, d_counts, d_len, theta, s, &out->hub);
   if (st) return st;
   host_items->clear();
